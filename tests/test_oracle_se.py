@@ -1,0 +1,199 @@
+"""Pins of the oracle's spectral Ewald steps (Sections 4-8) against closed forms,
+the direct sum, the paper's printed parameter sets and its error estimates."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import erf
+
+import workloads as W
+from oracle import direct, se
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+SQPI = math.sqrt(math.pi)
+
+
+def _src(kernel, n, seed, uniform=False):
+    gen = W.uniform_strengths if uniform else W.normal_strengths
+    a = gen(n, seed)
+    b = gen(n, seed + 1) if kernel == "stresslet" else None
+    return a, b
+
+
+def test_geometry_relations():
+    """h = L/M, d = hP, m = C sqrt(pi P), eta = (xi d/m)^2 (Section 6.3); Mt = M + P
+    for deltaL = d; M_g even and above (1 + sqrt 3) Mt; R = sqrt(3) Lt."""
+    g = se.geometry(xi=7.0, rc=0.63, M=48, P=16, L=2.0)
+    assert g.h == 2.0 / 48 and g.Mt == 64 and g.Lt == pytest.approx(64 * 2.0 / 48)
+    assert g.m == pytest.approx(0.976 * math.sqrt(16 * math.pi))
+    assert g.eta == pytest.approx((7.0 * 16 * g.h / g.m) ** 2)
+    assert g.Mg % 2 == 0 and g.Mg > (1 + math.sqrt(3)) * 64 and g.Mg - 2 <= (1 + math.sqrt(3)) * 64
+    assert g.R == pytest.approx(math.sqrt(3) * g.Lt)
+    np.testing.assert_allclose(g.x0, -(g.Lt - 2.0) / 2)
+    # Gaussian exponent in grid units depends on P only: alpha h^2 = 2 C^2 pi / P
+    assert g.alpha * g.h ** 2 == pytest.approx(2 * 0.976 ** 2 * math.pi / 16)
+
+
+def test_window_inside_grid_at_box_corners():
+    for P in (7, 8, 15, 16):
+        g = se.geometry(xi=5.0, rc=0.5, M=20, P=P, box_lo=(-1, 0, 2), L=3.0)
+        lo = np.array([[-1, 0, 2]], float)
+        hi = lo + 3.0 * (1 - 1e-15)
+        for x in (lo, hi):
+            t, b = se.window(x, g)
+            assert b.min() >= 0 and (b + P - 1).max() <= g.Mt - 1
+            c = t - b - (P - 1) / 2.0
+            assert np.all(c >= -0.5) and np.all(c < 0.5)
+
+
+def test_spread_gaussian_mass():
+    """h^3 sum_p of one spread Gaussian is 1 up to the truncation at the P^3 cube
+    (eq. Hx normalisation; Section 6.3 truncation level e^{-m^2/2})."""
+    for P in (8, 16, 24):
+        g = se.geometry(xi=10.0, rc=0.3, M=32, P=P, L=1.0)
+        x = W.uniform_cube(5, 40)
+        for i in range(5):
+            G = se.spread(x[i:i + 1], np.ones((1, 1)), g)
+            mass = G.sum() * g.h ** 3
+            assert abs(mass - 1.0) < 10 * math.exp(-g.m ** 2 / 2) + 1e-13
+
+
+def test_spread_gather_adjoint():
+    """<gather(F), s> = h^3 <F, spread(s)>: the two steps use the same windows."""
+    g = se.geometry(xi=6.0, rc=0.5, M=16, P=8, L=1.0)
+    x = W.uniform_cube(30, 41)
+    s = W.normal_strengths(30, 42)
+    F = W.rng(43).standard_normal((3, g.Mt, g.Mt, g.Mt))
+    lhs = np.sum(se.gather(F, x, g) * s)
+    rhs = g.h ** 3 * np.sum(F * se.spread(x, s, g))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("family", ["B", "H"])
+def test_mollified_kernel_solves_free_space_problem(family):
+    """Section 4: convolving the gridded Ewald screening Gaussian gamma_E with the
+    mollified kernel gives Table 1's closed forms: B * gamma_E = Phi_E(r) =
+    r erf + r erf/(2 xi^2 r^2) + e^{-xi^2 r^2}/(sqrt(pi) xi), and
+    H * gamma_E = erf(xi r)/r (eq. laplace_decomp)."""
+    xi = 10.0  # e^{-xi^2 (0.6)^2}: the Gaussian is below roundoff at the grid edge
+    g = se.geometry(xi=xi, rc=0.3, M=40, P=8, L=1.0)
+    Kt = se.mollified_kernel(family, g)
+    Mt, n = g.Mt, g.n
+    nodes = g.x0[0] + g.h * np.arange(Mt)
+    c = np.array([0.5, 0.5, 0.5]) + 0.37 * g.h
+    X, Y, Z = np.meshgrid(nodes - c[0], nodes - c[1], nodes - c[2], indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    gam = xi ** 3 / SQPI ** 3 * np.exp(-xi * xi * r * r)
+    phi = np.fft.ifftn(Kt * np.fft.fftn(gam, s=(n, n, n), axes=(0, 1, 2)))[:Mt, :Mt, :Mt].real
+    if family == "B":
+        ref = r * erf(xi * r) + erf(xi * r) / (2 * xi * xi * r) + np.exp(-xi * xi * r * r) / (SQPI * xi)
+    else:
+        ref = erf(xi * r) / r
+    np.testing.assert_allclose(phi, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_mollified_kernel_is_real_and_even():
+    g = se.geometry(xi=5.0, rc=0.5, M=12, P=8, L=1.0)
+    Kt, imax = se.mollified_kernel("B", g, return_imag=True)
+    assert imax < 1e-12 * np.abs(Kt).max()
+    n = g.n
+    neg = (-np.arange(n)) % n
+    np.testing.assert_allclose(Kt, Kt[neg][:, neg][:, :, neg], rtol=0, atol=1e-12 * np.abs(Kt).max())
+    np.testing.assert_allclose(Kt, Kt.transpose(1, 0, 2), rtol=0, atol=1e-12 * np.abs(Kt).max())
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
+def test_identity_with_direct_sum(kernel):
+    """u^R + u^F + u^self = direct sum to roundoff once every truncation is far
+    below it (deltaL from eq. deltaL_cond, Fourier and real-space estimates
+    negligible).  A wrong sign, factor or dropped term gives an O(1) mismatch."""
+    x = W.uniform_cube(120, 50)
+    a, b = _src(kernel, 120, 51)
+    g = se.geometry(xi=4.0, rc=1.75, M=20, P=20, L=1.0, deltaL_rule=1)
+    r = se.evaluate(kernel, x, a, b, g=g)
+    ref = direct.direct(kernel, x, a, b)
+    mx, rms = direct.rel_errors(r["u"], ref)
+    assert mx < 1e-11 and rms < 1e-11
+
+
+def test_xi_independence():
+    x = W.uniform_cube(150, 52)
+    f = W.normal_strengths(150, 53)
+    us = [se.evaluate("stokeslet", x, f, g=se.geometry(xi=xi, rc=7.0 / xi, M=M, P=22, L=1.0,
+                                                         deltaL_rule=1))["u"]
+          for xi, M in ((5.0, 24), (7.0, 34))]
+    assert direct.rel_errors(us[0], us[1])[1] < 1e-10
+
+
+def test_translation_of_box():
+    """Moving points and box together changes nothing but rounding."""
+    x = W.uniform_cube(100, 54)
+    f = W.normal_strengths(100, 55)
+    g1 = se.geometry(xi=6.0, rc=1.0, M=30, P=16, L=1.0)
+    g2 = se.geometry(xi=6.0, rc=1.0, M=30, P=16, L=1.0, box_lo=(3.0, -2.0, 0.5))
+    u1 = se.fourier_part("stokeslet", x, f, None, g1)
+    u2 = se.fourier_part("stokeslet", x + np.array([3.0, -2.0, 0.5]), f, None, g2)
+    np.testing.assert_allclose(u2, u1, rtol=0, atol=1e-11 * np.abs(u1).max())
+
+
+@pytest.mark.slow
+def test_paper_parameter_sets():
+    """Results section: xi=7, r_c=0.63/0.63/0.58, P=16, M=48/50/38 at L=2 and
+    N/L^3=2500 keep the relative rms error below 0.5e-8."""
+    spec = json.load(open(os.path.join(GOLD, "paper_parameter_sets.json")))
+    N, L = spec["N"], spec["L"]
+    x = W.uniform_cube(N, 60, L=L)
+    for c in spec["cases"]:
+        a, b = _src(c["kernel"], N, 61, uniform=True)
+        g = se.geometry(xi=spec["xi"], rc=c["rc"], M=c["M"], P=spec["P"], L=L)
+        u = se.evaluate(c["kernel"], x, a, b, g=g)["u"]
+        ref = direct.direct(c["kernel"], x, a, b)
+        assert direct.rel_errors(u, ref)[1] < spec["max_rel_rms"], c
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
+def test_fourier_error_tracks_estimate(kernel):
+    """Measured RMS Fourier truncation error against Table est_fourier (Section 7.1),
+    with P=24 so that approximation errors stay below it (Fig. fourier_err setup)."""
+    N, L, xi = 2000, 1.5, 3.49 * 3 / 1.5
+    x = W.uniform_cube(N, 62, L=L)
+    a, b = _src(kernel, N, 63, uniform=True)
+    ref = direct.fourier_dir(kernel, xi, x, a, b)
+    Q = np.sum(a * a) if b is None else np.sum(np.sum(a * a, 1) * np.sum(b * b, 1))
+    ratios = []
+    for M in (10, 14, 18):
+        g = se.geometry(xi=xi, rc=0.5, M=M, P=24, L=L, deltaL_rule=1)
+        uF = se.fourier_part(kernel, x, a, b, g)
+        meas = np.sqrt(np.sum((uF - ref) ** 2) / N)
+        est = se.est_fourier(kernel, Q, xi, L, math.pi / g.h, g.R)
+        ratios.append(meas / est)
+    assert all(0.1 < q < 10 for q in ratios), ratios
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
+def test_real_error_tracks_estimate(kernel):
+    """Measured RMS real-space truncation error against Table est_real (Fig. real_err setup)."""
+    N, L, xi = 2000, 3.0, 4.67
+    x = W.uniform_cube(N, 64, L=L)
+    a, b = _src(kernel, N, 65, uniform=True)
+    full = direct.real_trunc(kernel, xi, 10.0, x, a, b)
+    Q = np.sum(a * a) if b is None else np.sum(np.sum(a * a, 1) * np.sum(b * b, 1))
+    for rc in (0.4, 0.55, 0.7):
+        meas = np.sqrt(np.sum((direct.real_trunc(kernel, xi, rc, x, a, b) - full) ** 2) / N)
+        est = se.est_real(kernel, Q, xi, L, rc)
+        assert 0.2 < meas / est < 5, (rc, meas, est)
+
+
+def test_deltaL_rule_decouples_errors():
+    """With Mt larger than needed, deltaL = d leaves an error floor that eq. deltaL_cond
+    removes (Section 6.3, Fig. P_errors)."""
+    x = W.uniform_cube(200, 66)
+    f = W.normal_strengths(200, 67)
+    ref = direct.fourier_dir("stokeslet", 6.0, x, f)
+    e = []
+    for rule in (0, 1):
+        g = se.geometry(xi=6.0, rc=0.5, M=30, P=20, L=1.0, deltaL_rule=rule)
+        e.append(direct.rel_errors(se.fourier_part("stokeslet", x, f, None, g), ref)[1])
+    assert e[1] < 1e-11 and e[0] > 1e-9
