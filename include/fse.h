@@ -1,0 +1,172 @@
+/*
+ * fse.h -- C ABI of libfse: free-space spectral Ewald (FSE) evaluation of
+ * stokeslet, stresslet and rotlet sums on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: af Klinteberg, Shamshirgar & Tornberg, "Fast Ewald summation for
+ * free-space Stokes potentials", arXiv:1607.04808.
+ *
+ * Problem (Section 1, eq. usumfree; Section 2, eq. usum):
+ *     u(x_m) = sum_{n != m} G(x_m - x_n) . f_n ,   m = 1..N,
+ * with G the stokeslet S_jl = d_jl/r + r_j r_l/r^3 (eq. def_stokeslet), the
+ * stresslet T_jlm = -6 r_j r_l r_m / r^5 acting on f_lm = n_l q_m
+ * (eq. def_stresslet, Section 2) or the rotlet Omega_jl = eps_jlm r_m / r^3
+ * (eq. def_rotlet).  All points lie in the cube [box_lo, box_lo + L)^3
+ * (Section 6.2, Section 7).
+ *
+ * Conventions shared by every entry point:
+ *   - Array pointers are DEVICE pointers (HIP global memory) owned by the
+ *     caller, C-contiguous, in the plan's dtype (float or double).  Positions
+ *     x: (n, 3).  Sources and results: (batch, n, 3) with the batch index
+ *     slowest (batch = 1 means a plain (n, 3) array).
+ *   - Work is enqueued on the plan's HIP stream and is asynchronous; entry
+ *     points only synchronise where stated.
+ *   - The plan owns all workspace.  A plan is not thread-safe; calls on one
+ *     plan must not overlap.
+ *   - No C++ exception crosses the ABI.  Every call returns an fse_status_t;
+ *     on failure fse_last_error() gives a thread-local message.
+ */
+#ifndef FSE_H
+#define FSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FSE_STOKESLET = 0, FSE_STRESSLET = 1, FSE_ROTLET = 2 } fse_kernel_t;
+typedef enum { FSE_F32 = 0, FSE_F64 = 1 } fse_dtype_t;
+
+typedef enum {
+    FSE_OK = 0,
+    FSE_EINVAL = 1,        /* bad argument or parameter                       */
+    FSE_ERANGE = 2,        /* a point outside [box_lo, box_lo+L)^3 or not finite */
+    FSE_ENOMEM = 3,        /* device allocation failed                        */
+    FSE_EHIP = 4,          /* a HIP runtime call failed                       */
+    FSE_EUNSUPPORTED = 5,  /* combination not implemented (e.g. stresslet adjoint) */
+    FSE_ESTATE = 6         /* call order violated (e.g. eval before set_points) */
+} fse_status_t;
+
+/*
+ * Method parameters (Section 8 "Parameter selection"): the Ewald parameter
+ * xi, the real-space cutoff rc (Section 5), the number of grid intervals M on
+ * the box side (h = L/M) and the Gaussian support P (P^3 window, Section 6.2).
+ */
+typedef struct {
+    double xi;           /* Ewald split parameter, > 0                          */
+    double rc;           /* real-space cutoff radius, > 0                        */
+    int32_t M;           /* grid intervals on the box side L, >= 1              */
+    int32_t P;           /* Gaussian support in grid points, 2 <= P <= 32       */
+    double box_lo[3];    /* lower corner of the cube holding all points         */
+    double L;            /* side of the cube, > 0                               */
+    int32_t deltaL_rule; /* 0: deltaL = d = hP (Results section);
+                            1: deltaL from eq. deltaL_cond (Section 6.3)        */
+    int32_t Mt;          /* 0: the smallest grid size >= M + deltaL/h whose
+                            doubled size 2*Mt factors into 2,3,5,7;
+                            > 0: use this size (must be >= that minimum and
+                            2*Mt must factor into 2,3,5,7)                      */
+    double C;            /* Gaussian shape constant of m = C sqrt(pi P);
+                            0 selects 0.976 (Section 6.3)                       */
+} fse_params_t;
+
+/*
+ * Derived geometry (Sections 4.1, 6.2, 6.3 and the Results section):
+ * h = L/M, d = hP, m = C sqrt(pi P), eta = (xi d/m)^2, alpha = 2 xi^2/eta
+ * (exponent of the gridding Gaussians, eq. Hx), Lt = Mt h, grid nodes
+ * x0 + j h (j = 0..Mt-1) with x0 = box_lo - (Lt - L)/2, FFT size n = 2 Mt,
+ * R = sqrt(3) Lt, precompute grid Mg = smallest even integer > (1+sqrt 3) Mt,
+ * kinf = pi/h.  The real-space pass uses a cell list of ncell^3 cells of
+ * side cell >= rc.
+ */
+typedef struct {
+    int32_t Mt, n_fft, Mg;
+    int32_t ncell;
+    double h, d, m, eta, alpha, Lt, R, deltaL, kinf, cell;
+    double x0[3];
+    int32_t radices[8];  /* FFT factorisation of n_fft, 0-terminated */
+} fse_geometry_t;
+
+typedef struct fse_plan fse_plan_t;
+
+/* Host only, no device work.  Validates the parameters and fills *out.
+ * Returns FSE_EINVAL for out-of-range parameters or an impossible Mt. */
+fse_status_t fse_geometry(fse_kernel_t kernel, const fse_params_t *params, fse_geometry_t *out);
+
+/*
+ * Create a plan for `batch` (>= 1) source vectors over shared positions and
+ * at most `nmax` points.  Allocates every workspace buffer on the current HIP
+ * device and runs the FP64 precompute of the mollified Green's function
+ * transform (Section 4.3: the truncated biharmonic transform, eq. BhatR, for
+ * the stokeslet and stresslet, or the harmonic one, eq. HhatR, for the
+ * rotlet, oversampled on Mg^3, inverse-transformed, cropped to (2Mt)^3 and
+ * transformed back), folded with the scaling factors of eq. gridfcnsc and
+ * eqs. AS/AT/AR.  `stream` is a hipStream_t (NULL = the null stream).
+ * Synchronises the stream once, at the end.  *out is NULL on failure.
+ */
+fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t *params,
+                             int32_t batch, int64_t nmax, void *stream, fse_plan_t **out);
+
+/* Geometry the plan was built with (host copy). */
+fse_status_t fse_plan_geometry(const fse_plan_t *plan, fse_geometry_t *out);
+
+/* Change the stream later calls are enqueued on. */
+fse_status_t fse_plan_set_stream(fse_plan_t *plan, void *stream);
+
+/*
+ * Set the n (2 <= n <= nmax) points x (device, (n,3), plan dtype): bins them
+ * by grid tile (for spreading and quadrature, Section 6.2) and by real-space
+ * cell (Section 5's cell list), computes each point's Gaussian window start
+ * and offset in FP64, and keeps sorted copies.  Points outside the box are
+ * clamped into it on the device, so no kernel ever leaves its buffers.
+ * validate != 0: also synchronises the stream and returns FSE_ERANGE if any
+ * point was outside [box_lo, box_lo+L)^3 or not finite.  Coincident
+ * distinct points give an undefined sum (as the direct sum does).
+ */
+fse_status_t fse_set_points(fse_plan_t *plan, int64_t n, const void *x, int32_t validate);
+
+/*
+ * u = u^R + u^F + u^self at the n points (Section 7): src_a is f (stokeslet,
+ * rotlet) or q (stresslet), src_b is NULL or the normals n (stresslet), both
+ * (batch, n, 3); u is (batch, n, 3) and is overwritten.  The scaled,
+ * inverse-transformed grid of this call is kept for fse_eval_adjoint.
+ */
+fse_status_t fse_eval(fse_plan_t *plan, const void *src_a, const void *src_b, void *u);
+
+/*
+ * The two parts separately (for tests): u_real = u^R + u^self (the truncated
+ * real-space sum of Section 5 plus the stokeslet self term, eq. Slimit) and
+ * u_fourier = u^F (the five steps of Section 6.2).  Either may be NULL.
+ */
+fse_status_t fse_eval_parts(fse_plan_t *plan, const void *src_a, const void *src_b, void *u_real,
+                            void *u_fourier);
+
+/*
+ * Adjoint of fse_eval for L = sum_m w_m . u(x_m) (stokeslet and rotlet, whose
+ * discrete operator is symmetric): dsrc = dL/df = K w (batch, n, 3) and
+ * dx = dL/dx (n, 3), summed over the batch, from the derivatives of the
+ * Gaussian windows (spreading and quadrature) and of the real-space kernel.
+ * src_a must be the f of the last fse_eval on this plan and set_points must
+ * not have been called since; with recompute != 0 the forward grid is
+ * rebuilt from src_a first.  Either output may be NULL.
+ * FSE_EUNSUPPORTED for the stresslet.
+ */
+fse_status_t fse_eval_adjoint(fse_plan_t *plan, const void *src_a, const void *w, void *dsrc,
+                              void *dx, int32_t recompute);
+
+/* Copy the (Mt+1)^3 FP64 octant of the scalar Fourier multiplier (the
+ * precomputed mollified kernel transform times the kernel's scalar factors
+ * and normalisations) to host memory `out`.  Synchronises. */
+fse_status_t fse_plan_multiplier(fse_plan_t *plan, double *out);
+
+/* Device bytes held by the plan.  Synchronises nothing. */
+fse_status_t fse_plan_workspace(const fse_plan_t *plan, size_t *bytes);
+
+void fse_plan_destroy(fse_plan_t *plan);
+const char *fse_status_string(fse_status_t status);
+const char *fse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSE_H */

@@ -1,0 +1,8 @@
+"""MI355X-native free-space spectral Ewald evaluation of stokeslet, stresslet and
+rotlet sums (af Klinteberg, Shamshirgar & Tornberg, arXiv:1607.04808).
+
+The computation lives in the HIP library ``lib/libfse.so`` (C ABI in
+``include/fse.h``); :mod:`.fse` is its Python binding.
+"""
+from .fse import (FseError, Geometry, Plan, Params, fse_sum, geometry, lib,  # noqa: F401
+                  make_params)

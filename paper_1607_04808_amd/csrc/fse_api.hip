@@ -1,0 +1,607 @@
+// C ABI of libfse (declared in include/fse.h): parameters and geometry, plan
+// workspace, the FP64 precompute, and the orchestration of the hot path
+// (bin -> spread -> FFT/scale/IFFT -> gather -> real space).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "fse_common.h"
+
+using namespace fse;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void set_err(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+#define HIPCHK(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            set_err("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return FSE_EHIP;                                                      \
+        }                                                                         \
+    } while (0)
+
+#define LAUNCHCHK()                                                               \
+    do {                                                                          \
+        hipError_t e_ = hipGetLastError();                                        \
+        if (e_ != hipSuccess) {                                                   \
+            set_err("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, __LINE__); \
+            return FSE_EHIP;                                                      \
+        }                                                                         \
+    } while (0)
+
+constexpr double PI = 3.14159265358979323846;
+constexpr int MAX_MT = 540;  // n = 2 Mt <= 1080 keeps every FFT pass within 160 KB of LDS
+constexpr int MAX_CELLS_PER_SIDE = 128;
+
+bool smooth7(int n) {
+    if (n <= 0) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// radix stages (DIF order) for n: 8s first, then 7, 5, a final 4 or 2, then 3s
+int factorize(int n, int* rad) {
+    int ns = 0;
+    int m = n;
+    int c7 = 0, c5 = 0, c3 = 0, c2 = 0;
+    while (m % 7 == 0) { m /= 7; ++c7; }
+    while (m % 5 == 0) { m /= 5; ++c5; }
+    while (m % 3 == 0) { m /= 3; ++c3; }
+    while (m % 2 == 0) { m /= 2; ++c2; }
+    if (m != 1) return -1;
+    while (c2 >= 3) { rad[ns++] = 8; c2 -= 3; }
+    for (int i = 0; i < c7; ++i) rad[ns++] = 7;
+    for (int i = 0; i < c5; ++i) rad[ns++] = 5;
+    if (c2 == 2) rad[ns++] = 4;
+    else if (c2 == 1) rad[ns++] = 2;
+    for (int i = 0; i < c3; ++i) rad[ns++] = 3;
+    return ns;
+}
+
+// position p of the in-place DIF output holds frequency rev[p]
+void digit_reverse(const int* rad, int ns, int n, std::vector<int>& rev) {
+    rev.assign(n, 0);
+    for (int p = 0; p < n; ++p) {
+        // walk the stages: p = k2 * m + q; frequency = r * rev_sub(q) + k2
+        int q = p, L = n;
+        int mult = 1, acc = 0;
+        for (int s = 0; s < ns; ++s) {
+            const int r = rad[s], m = L / r;
+            const int k2 = q / m;
+            q -= k2 * m;
+            acc += mult * k2;
+            mult *= r;
+            L = m;
+        }
+        rev[p] = acc;
+    }
+}
+
+fse_status_t compute_geometry(fse_kernel_t kernel, const fse_params_t* p, fse_geometry_t* g) {
+    if (!p || !g) { set_err("null argument"); return FSE_EINVAL; }
+    if (kernel < FSE_STOKESLET || kernel > FSE_ROTLET) { set_err("unknown kernel %d", (int)kernel); return FSE_EINVAL; }
+    if (!(p->xi > 0 && isfinite(p->xi))) { set_err("xi must be > 0"); return FSE_EINVAL; }
+    if (!(p->rc > 0 && isfinite(p->rc))) { set_err("rc must be > 0"); return FSE_EINVAL; }
+    if (p->M < 1) { set_err("M must be >= 1"); return FSE_EINVAL; }
+    if (p->P < 2 || p->P > 32) { set_err("P must be in [2, 32]"); return FSE_EINVAL; }
+    if (!(p->L > 0 && isfinite(p->L))) { set_err("L must be > 0"); return FSE_EINVAL; }
+    for (int d = 0; d < 3; ++d)
+        if (!isfinite(p->box_lo[d])) { set_err("box_lo must be finite"); return FSE_EINVAL; }
+    if (p->deltaL_rule != 0 && p->deltaL_rule != 1) { set_err("deltaL_rule must be 0 or 1"); return FSE_EINVAL; }
+    if (!(p->C >= 0 && p->C < 10)) { set_err("C out of range"); return FSE_EINVAL; }
+    memset(g, 0, sizeof *g);
+    const double C = p->C > 0 ? p->C : 0.976;
+    const double h = p->L / p->M;
+    const double d = h * p->P;
+    const double m = C * sqrt(PI * p->P);
+    const double eta = (p->xi * d / m) * (p->xi * d / m);
+    double dL = d;
+    if (p->deltaL_rule == 1 && eta < 1.0) {
+        const double need = sqrt(2.0 * (1.0 - eta) * m * m / (p->xi * p->xi));
+        if (need > dL) dL = need;
+    }
+    const int Mt_min = p->M + (int)ceil(dL / h - 1e-12);
+    int Mt;
+    if (p->Mt > 0) {
+        Mt = p->Mt;
+        if (Mt < Mt_min) { set_err("Mt=%d below the minimum %d", Mt, Mt_min); return FSE_EINVAL; }
+        if (!smooth7(2 * Mt)) { set_err("2*Mt=%d does not factor into 2,3,5,7", 2 * Mt); return FSE_EINVAL; }
+    } else {
+        Mt = Mt_min;
+        while (!smooth7(2 * Mt)) ++Mt;
+    }
+    if (Mt > MAX_MT) { set_err("grid size Mt=%d above the supported %d", Mt, MAX_MT); return FSE_EINVAL; }
+    g->Mt = Mt;
+    g->n_fft = 2 * Mt;
+    g->h = h;
+    g->d = d;
+    g->m = m;
+    g->eta = eta;
+    g->alpha = 2.0 * p->xi * p->xi / eta;
+    g->Lt = Mt * h;
+    g->deltaL = g->Lt - p->L;
+    for (int k = 0; k < 3; ++k) g->x0[k] = p->box_lo[k] - 0.5 * (g->Lt - p->L);
+    int Mg = (int)floor((1.0 + sqrt(3.0)) * Mt) + 1;
+    if (Mg % 2) ++Mg;
+    g->Mg = Mg;
+    g->R = sqrt(3.0) * g->Lt;
+    g->kinf = PI / h;
+    int nc = (int)floor(p->L / p->rc);
+    if (nc < 1) nc = 1;
+    if (nc > MAX_CELLS_PER_SIDE) nc = MAX_CELLS_PER_SIDE;
+    g->ncell = nc;
+    g->cell = p->L / nc;
+    int rad[MAX_RADICES];
+    const int ns = factorize(g->n_fft, rad);
+    if (ns < 0 || ns > 7) { set_err("cannot factor n=%d", g->n_fft); return FSE_EINVAL; }
+    for (int s = 0; s < ns; ++s) g->radices[s] = rad[s];
+    return FSE_OK;
+}
+
+template <typename T> size_t tsz() { return sizeof(T); }
+
+}  // namespace
+
+struct fse_plan {
+    fse_kernel_t kernel;
+    fse_dtype_t dtype;
+    fse_params_t prm;
+    fse_geometry_t geo;
+    int batch;
+    int64_t nmax;
+    int64_t n = 0;
+    hipStream_t stream;
+    int c_in;
+    GridGeo gg;
+    CellGeo cg;
+    FftGeo fg;
+    size_t bytes = 0;
+    bool forward_valid = false;
+    std::vector<void*> allocs;
+
+    // points
+    int *key_s, *rank_s, *key_r, *rank_r, *bpack, *perm_s, *bpack_s, *perm_r, *inv_r;
+    void *coff, *coff_s, *x_r;
+    int *cnt_s, *start_s, *cnt_r, *start_r, *scan_tmp, *flag;
+    int64_t ntiles3, ncells3;
+    // sources
+    void *src_s, *src_ra, *src_rb, *adj_s, *adj_r;
+    // grids
+    void *grid, *A, *B, *phi, *phi_w;
+    double* sig64;
+    void* sig;
+    void* tw;
+    int *rev, *revinv;
+
+    template <typename X> fse_status_t alloc(X** p, size_t count) {
+        void* q = nullptr;
+        size_t b = count * sizeof(X);
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&q, b);
+        if (e != hipSuccess) {
+            set_err("hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
+            return FSE_ENOMEM;
+        }
+        allocs.push_back(q);
+        bytes += b;
+        *p = (X*)q;
+        return FSE_OK;
+    }
+    ~fse_plan() {
+        for (void* q : allocs) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+template <typename T> PointsDev<T> points(const fse_plan* p) {
+    PointsDev<T> d;
+    d.n = p->n;
+    d.perm_s = p->perm_s;
+    d.bpack_s = p->bpack_s;
+    d.coff_s = (const T*)p->coff_s;
+    d.tile_start = p->start_s;
+    d.perm_r = p->perm_r;
+    d.x_r = (const T*)p->x_r;
+    d.cell_start = p->start_r;
+    d.inv_r = p->inv_r;
+    return d;
+}
+
+#define TRY(x)                        \
+    do {                              \
+        fse_status_t s_ = (x);        \
+        if (s_ != FSE_OK) return s_;  \
+    } while (0)
+
+template <typename T> fse_status_t allocate(fse_plan* p) {
+    const int64_t nm = p->nmax, B = p->batch;
+    const int64_t Mt = p->geo.Mt, n = p->geo.n_fft, Mp = Mt + 1;
+    const int64_t M3 = Mt * Mt * Mt;
+    using V = C2<T>;
+    TRY(p->alloc(&p->key_s, nm));
+    TRY(p->alloc(&p->rank_s, nm));
+    TRY(p->alloc(&p->key_r, nm));
+    TRY(p->alloc(&p->rank_r, nm));
+    TRY(p->alloc(&p->bpack, nm));
+    TRY(p->alloc(&p->perm_s, nm));
+    TRY(p->alloc(&p->bpack_s, nm));
+    TRY(p->alloc(&p->perm_r, nm));
+    TRY(p->alloc(&p->inv_r, nm));
+    TRY(p->alloc((T**)&p->coff, 3 * nm));
+    TRY(p->alloc((T**)&p->coff_s, 3 * nm));
+    TRY(p->alloc((T**)&p->x_r, 3 * nm));
+    p->ntiles3 = (int64_t)p->gg.nt * p->gg.nt * p->gg.nt;
+    p->ncells3 = (int64_t)p->cg.ncell * p->cg.ncell * p->cg.ncell;
+    TRY(p->alloc(&p->cnt_s, p->ntiles3 + 1));
+    TRY(p->alloc(&p->start_s, p->ntiles3 + 1));
+    TRY(p->alloc(&p->cnt_r, p->ncells3 + 1));
+    TRY(p->alloc(&p->start_r, p->ncells3 + 1));
+    const size_t st = scan_tmp_ints(p->ntiles3 + 1) > scan_tmp_ints(p->ncells3 + 1)
+                          ? scan_tmp_ints(p->ntiles3 + 1) : scan_tmp_ints(p->ncells3 + 1);
+    TRY(p->alloc(&p->scan_tmp, st));
+    TRY(p->alloc(&p->flag, 1));
+    TRY(p->alloc((T**)&p->src_s, B * nm * p->c_in));
+    TRY(p->alloc((T**)&p->src_ra, B * nm * 3));
+    TRY(p->alloc((T**)&p->src_rb, p->kernel == FSE_STRESSLET ? B * nm * 3 : 1));
+    TRY(p->alloc((T**)&p->adj_s, B * nm * 3));
+    TRY(p->alloc((T**)&p->adj_r, B * nm * 3));
+    TRY(p->alloc((T**)&p->grid, B * p->c_in * M3));
+    TRY(p->alloc((V**)&p->A, B * p->c_in * Mp * Mt * Mt));
+    TRY(p->alloc((V**)&p->B, B * p->c_in * Mp * n * Mt));
+    TRY(p->alloc((T**)&p->phi, B * 3 * M3));
+    TRY(p->alloc((T**)&p->phi_w, p->kernel == FSE_STRESSLET ? 1 : B * 3 * M3));
+    TRY(p->alloc(&p->sig64, Mp * Mp * Mp));
+    TRY(p->alloc((T**)&p->sig, Mp * Mp * Mp));
+    TRY(p->alloc((T**)&p->tw, 2 * n));
+    TRY(p->alloc(&p->rev, n));
+    TRY(p->alloc(&p->revinv, n));
+    return FSE_OK;
+}
+
+template <typename T> fse_status_t upload_fft_tables(fse_plan* p) {
+    const int n = p->geo.n_fft;
+    std::vector<T> tw(2 * (size_t)n);
+    for (int e = 0; e < n; ++e) {
+        const double a = 2.0 * PI * (double)e / (double)n;
+        tw[2 * e] = (T)cos(a);
+        tw[2 * e + 1] = (T)(-sin(a));
+    }
+    std::vector<int> rev, revinv(n);
+    digit_reverse(p->fg.rad, p->fg.ns, n, rev);
+    for (int q = 0; q < n; ++q) revinv[rev[q]] = q;
+    HIPCHK(hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(p->rev, rev.data(), n * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipMemcpyAsync(p->revinv, revinv.data(), n * sizeof(int), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return FSE_OK;
+}
+
+// Section 4.3 precompute, FP64, then fold in the scalar factors.
+template <typename T> fse_status_t precompute(fse_plan* p) {
+    const int Mt = p->geo.Mt, Mg = p->geo.Mg, Mp = Mt + 1, H = Mg / 2 + 1;
+    const int64_t big = (int64_t)H * H * H > (int64_t)Mp * H * H ? (int64_t)H * H * H : (int64_t)Mp * H * H;
+    double *t0 = nullptr, *t1 = nullptr, *c1 = nullptr, *c2 = nullptr;
+    auto cleanup = [&]() {
+        if (t0) (void)hipFree(t0);
+        if (t1) (void)hipFree(t1);
+        if (c1) (void)hipFree(c1);
+        if (c2) (void)hipFree(c2);
+    };
+    if (hipMalloc(&t0, big * sizeof(double)) != hipSuccess || hipMalloc(&t1, big * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c1, (size_t)Mp * H * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c2, (size_t)Mp * Mp * sizeof(double)) != hipSuccess) {
+        cleanup();
+        set_err("precompute: out of device memory");
+        return FSE_ENOMEM;
+    }
+    // C1[j][k] = w_k cos(2 pi j k / Mg), k in [0, Mg/2]: inverse transform on Mg
+    std::vector<double> h1((size_t)Mp * H), h2((size_t)Mp * Mp);
+    for (int j = 0; j < Mp; ++j)
+        for (int k = 0; k < H; ++k) {
+            const double w = (k == 0 || k == Mg / 2) ? 1.0 : 2.0;
+            const long long e = ((long long)j * k) % Mg;
+            h1[(size_t)j * H + k] = w * cos(2.0 * PI * (double)e / (double)Mg);
+        }
+    // C2[k][j] = w_j cos(pi k j / Mt), j in [0, Mt]: forward transform on 2 Mt
+    for (int k = 0; k < Mp; ++k)
+        for (int j = 0; j < Mp; ++j) {
+            const double w = (j == 0 || j == Mt) ? 1.0 : 2.0;
+            const long long e = ((long long)k * j) % (2 * Mt);
+            h2[(size_t)k * Mp + j] = w * cos(PI * (double)e / (double)Mt);
+        }
+    hipStream_t st = p->stream;
+    fse_status_t rc = FSE_OK;
+    if (hipMemcpyAsync(c1, h1.data(), h1.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(c2, h2.data(), h2.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) {
+        cleanup();
+        set_err("precompute: copy failed");
+        return FSE_EHIP;
+    }
+    const int family = p->kernel == FSE_ROTLET ? 1 : 0;
+    launch_pre_fill(t0, Mg, p->geo.h, p->geo.R, family, st);
+    launch_pre_contract(t0, t1, c1, Mp, H, (int64_t)H * H, st);    // [j3][k1][k2]
+    launch_pre_contract(t1, t0, c1, Mp, H, (int64_t)Mp * H, st);   // [j2][j3][k1]
+    launch_pre_contract(t0, t1, c1, Mp, H, (int64_t)Mp * Mp, st);  // [j1][j2][j3]: G octant
+    launch_pre_contract(t1, t0, c2, Mp, Mp, (int64_t)Mp * Mp, st);
+    launch_pre_contract(t0, t1, c2, Mp, Mp, (int64_t)Mp * Mp, st);
+    launch_pre_contract(t1, t0, c2, Mp, Mp, (int64_t)Mp * Mp, st); // [k1][k2][k3]: mollified transform
+    const double a = p->geo.alpha;
+    const double nn = (double)p->geo.n_fft;
+    const double norm = pow(a / PI, 3.0) * pow(p->geo.h, 3.0) / (nn * nn * nn);
+    launch_pre_finalize<T>(t0, Mt, PI / p->geo.Lt, p->prm.xi, p->geo.eta, (int)p->kernel, norm, p->sig64,
+                           (T*)p->sig, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_err("precompute failed: %s", hipGetErrorString(e));
+        rc = FSE_EHIP;
+    }
+    cleanup();
+    return rc;
+}
+
+template <typename T> fse_status_t plan_init(fse_plan* p) {
+    TRY(allocate<T>(p));
+    TRY(upload_fft_tables<T>(p));
+    TRY(precompute<T>(p));
+    return FSE_OK;
+}
+
+template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T* x, int validate) {
+    hipStream_t st = p->stream;
+    launch_fill_i32(p->cnt_s, p->ntiles3 + 1, 0, st);
+    launch_fill_i32(p->cnt_r, p->ncells3 + 1, 0, st);
+    launch_fill_i32(p->flag, 1, 0, st);
+    launch_bin<T>(x, n, p->gg, p->cg, p->key_s, p->rank_s, p->key_r, p->rank_r, p->cnt_s, p->cnt_r,
+                  p->bpack, (T*)p->coff, p->flag, st);
+    launch_scan_exclusive(p->cnt_s, p->start_s, p->ntiles3 + 1, p->scan_tmp, st);
+    launch_scan_exclusive(p->cnt_r, p->start_r, p->ncells3 + 1, p->scan_tmp, st);
+    launch_scatter<T>(x, n, p->key_s, p->rank_s, p->start_s, p->key_r, p->rank_r, p->start_r, p->bpack,
+                      (const T*)p->coff, p->perm_s, p->bpack_s, (T*)p->coff_s, p->perm_r, (T*)p->x_r,
+                      p->inv_r, st);
+    LAUNCHCHK();
+    p->n = n;
+    p->forward_valid = false;
+    if (validate) {
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (flag) {
+            set_err("a point lies outside [box_lo, box_lo + L)^3 or is not finite");
+            return FSE_ERANGE;
+        }
+    }
+    return FSE_OK;
+}
+
+// spread -> FFT -> scale -> IFFT into `field`
+template <typename T> void fourier_chain(fse_plan* p, const T* src_s, T* field) {
+    hipStream_t st = p->stream;
+    PointsDev<T> pd = points<T>(p);
+    launch_spread<T>(p->gg, pd, src_s, p->c_in, p->batch, (T*)p->grid, st);
+    launch_fft_forward<T>(p->fg, p->gg, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
+                          p->rev, p->revinv, st);
+    launch_fft_zscale<T>(p->fg, p->gg, (int)p->kernel, p->B, p->c_in, p->batch, (const T*)p->sig,
+                         PI / p->geo.Lt, (const T*)p->tw, p->rev, p->revinv, st);
+    launch_fft_inverse<T>(p->fg, p->gg, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
+                          p->revinv, st);
+}
+
+double self_coef(const fse_plan* p) {
+    return p->kernel == FSE_STOKESLET ? -4.0 * p->prm.xi / sqrt(PI) : 0.0;
+}
+
+template <typename T>
+fse_status_t eval_t(fse_plan* p, const T* a, const T* b, T* u_real, T* u_four, bool combined) {
+    hipStream_t st = p->stream;
+    const int64_t n = p->n;
+    PointsDev<T> pd = points<T>(p);
+    launch_permute_sources<T>((int)p->kernel, a, b, n, p->batch, p->perm_s, (T*)p->src_s, st);
+    launch_permute3<T>(a, n, p->batch, p->perm_r, (T*)p->src_ra, st);
+    if (p->kernel == FSE_STRESSLET) launch_permute3<T>(b, n, p->batch, p->perm_r, (T*)p->src_rb, st);
+    fourier_chain<T>(p, (const T*)p->src_s, (T*)p->phi);
+    p->forward_valid = true;
+    if (combined) {
+        launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_real, st);
+        launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, p->batch,
+                       p->prm.xi, self_coef(p), u_real, 1, st);
+    } else {
+        if (u_four) launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_four, st);
+        if (u_real)
+            launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, p->batch,
+                           p->prm.xi, self_coef(p), u_real, 0, st);
+    }
+    LAUNCHCHK();
+    return FSE_OK;
+}
+
+template <typename T>
+fse_status_t adjoint_t(fse_plan* p, const T* f, const T* w, T* dsrc, T* dx, int recompute) {
+    hipStream_t st = p->stream;
+    const int64_t n = p->n;
+    PointsDev<T> pd = points<T>(p);
+    // f in spread and real-space order (also needed when the forward field is reused)
+    launch_permute_sources<T>((int)p->kernel, f, nullptr, n, p->batch, p->perm_s, (T*)p->src_s, st);
+    launch_permute3<T>(f, n, p->batch, p->perm_r, (T*)p->src_ra, st);
+    if (recompute || !p->forward_valid) {
+        fourier_chain<T>(p, (const T*)p->src_s, (T*)p->phi);
+        p->forward_valid = true;
+    }
+    launch_permute3<T>(w, n, p->batch, p->perm_s, (T*)p->adj_s, st);
+    launch_permute3<T>(w, n, p->batch, p->perm_r, (T*)p->adj_r, st);
+    fourier_chain<T>(p, (const T*)p->adj_s, (T*)p->phi_w);
+    launch_gather_grad<T>(p->gg, pd, (const T*)p->phi, (const T*)p->phi_w, (const T*)p->src_s,
+                          (const T*)p->adj_s, p->batch, dsrc, dx, st);
+    if (dsrc)
+        launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->adj_r, nullptr, p->batch, p->prm.xi,
+                       self_coef(p), dsrc, 1, st);
+    if (dx)
+        launch_real_grad<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->adj_r, p->batch,
+                            p->prm.xi, dx, st);
+    LAUNCHCHK();
+    return FSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fse_last_error(void) { return g_err; }
+
+const char* fse_status_string(fse_status_t s) {
+    switch (s) {
+        case FSE_OK: return "ok";
+        case FSE_EINVAL: return "invalid argument";
+        case FSE_ERANGE: return "point outside the box";
+        case FSE_ENOMEM: return "out of device memory";
+        case FSE_EHIP: return "HIP runtime error";
+        case FSE_EUNSUPPORTED: return "unsupported";
+        case FSE_ESTATE: return "call order violated";
+    }
+    return "unknown status";
+}
+
+fse_status_t fse_geometry(fse_kernel_t kernel, const fse_params_t* params, fse_geometry_t* out) {
+    return compute_geometry(kernel, params, out);
+}
+
+fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t* params, int32_t batch,
+                             int64_t nmax, void* stream, fse_plan_t** out) {
+    if (!out) { set_err("null plan pointer"); return FSE_EINVAL; }
+    *out = nullptr;
+    if (dtype != FSE_F32 && dtype != FSE_F64) { set_err("unknown dtype"); return FSE_EINVAL; }
+    if (batch < 1) { set_err("batch must be >= 1"); return FSE_EINVAL; }
+    if (nmax < 2 || nmax > (int64_t)1 << 30) { set_err("nmax must be in [2, 2^30]"); return FSE_EINVAL; }
+    fse_geometry_t geo;
+    TRY(compute_geometry(kernel, params, &geo));
+    fse_plan* p = new (std::nothrow) fse_plan();
+    if (!p) { set_err("host allocation failed"); return FSE_ENOMEM; }
+    p->kernel = kernel;
+    p->dtype = dtype;
+    p->prm = *params;
+    p->geo = geo;
+    p->batch = batch;
+    p->nmax = nmax;
+    p->stream = (hipStream_t)stream;
+    p->c_in = kernel == FSE_STRESSLET ? 6 : 3;
+    GridGeo& gg = p->gg;
+    gg.Mt = geo.Mt;
+    gg.n = geo.n_fft;
+    gg.P = params->P;
+    gg.TS = dtype == FSE_F32 ? 16 : 12;
+    gg.nt = (geo.Mt + gg.TS - 1) / gg.TS;
+    for (int d = 0; d < 3; ++d) gg.x0[d] = geo.x0[d];
+    gg.h = geo.h;
+    gg.ahh = geo.alpha * geo.h * geo.h;
+    CellGeo& cg = p->cg;
+    cg.ncell = geo.ncell;
+    for (int d = 0; d < 3; ++d) cg.lo[d] = params->box_lo[d];
+    cg.L = params->L;
+    cg.cell = geo.cell;
+    cg.rc2 = params->rc * params->rc;
+    FftGeo& fg = p->fg;
+    fg.n = geo.n_fft;
+    fg.ns = 0;
+    int L = fg.n;
+    for (int s = 0; s < 8 && geo.radices[s]; ++s) {
+        fg.rad[s] = geo.radices[s];
+        fg.Ls[s] = L;
+        L /= geo.radices[s];
+        fg.ns = s + 1;
+    }
+    fse_status_t rc = dtype == FSE_F32 ? plan_init<float>(p) : plan_init<double>(p);
+    if (rc != FSE_OK) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return FSE_OK;
+}
+
+fse_status_t fse_plan_geometry(const fse_plan_t* plan, fse_geometry_t* out) {
+    if (!plan || !out) { set_err("null argument"); return FSE_EINVAL; }
+    *out = plan->geo;
+    return FSE_OK;
+}
+
+fse_status_t fse_plan_set_stream(fse_plan_t* plan, void* stream) {
+    if (!plan) { set_err("null plan"); return FSE_EINVAL; }
+    plan->stream = (hipStream_t)stream;
+    return FSE_OK;
+}
+
+fse_status_t fse_set_points(fse_plan_t* plan, int64_t n, const void* x, int32_t validate) {
+    if (!plan || !x) { set_err("null argument"); return FSE_EINVAL; }
+    if (n < 2 || n > plan->nmax) { set_err("n=%lld outside [2, nmax=%lld]", (long long)n, (long long)plan->nmax); return FSE_EINVAL; }
+    return plan->dtype == FSE_F32 ? set_points_t<float>(plan, n, (const float*)x, validate)
+                                  : set_points_t<double>(plan, n, (const double*)x, validate);
+}
+
+fse_status_t fse_eval(fse_plan_t* plan, const void* a, const void* b, void* u) {
+    if (!plan || !a || !u) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->kernel == FSE_STRESSLET && !b) { set_err("stresslet needs the normals (src_b)"); return FSE_EINVAL; }
+    if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
+    return plan->dtype == FSE_F32
+               ? eval_t<float>(plan, (const float*)a, (const float*)b, (float*)u, nullptr, true)
+               : eval_t<double>(plan, (const double*)a, (const double*)b, (double*)u, nullptr, true);
+}
+
+fse_status_t fse_eval_parts(fse_plan_t* plan, const void* a, const void* b, void* u_real, void* u_fourier) {
+    if (!plan || !a) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->kernel == FSE_STRESSLET && !b) { set_err("stresslet needs the normals (src_b)"); return FSE_EINVAL; }
+    if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
+    return plan->dtype == FSE_F32
+               ? eval_t<float>(plan, (const float*)a, (const float*)b, (float*)u_real, (float*)u_fourier, false)
+               : eval_t<double>(plan, (const double*)a, (const double*)b, (double*)u_real, (double*)u_fourier,
+                                false);
+}
+
+fse_status_t fse_eval_adjoint(fse_plan_t* plan, const void* a, const void* w, void* dsrc, void* dx,
+                              int32_t recompute) {
+    if (!plan || !a || !w) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->kernel == FSE_STRESSLET) { set_err("the stresslet adjoint is not implemented"); return FSE_EUNSUPPORTED; }
+    if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
+    if (!dsrc && !dx) return FSE_OK;
+    return plan->dtype == FSE_F32
+               ? adjoint_t<float>(plan, (const float*)a, (const float*)w, (float*)dsrc, (float*)dx, recompute)
+               : adjoint_t<double>(plan, (const double*)a, (const double*)w, (double*)dsrc, (double*)dx,
+                                   recompute);
+}
+
+fse_status_t fse_plan_multiplier(fse_plan_t* plan, double* out) {
+    if (!plan || !out) { set_err("null argument"); return FSE_EINVAL; }
+    const size_t Mp = plan->geo.Mt + 1;
+    HIPCHK(hipMemcpyAsync(out, plan->sig64, Mp * Mp * Mp * sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+    HIPCHK(hipStreamSynchronize(plan->stream));
+    return FSE_OK;
+}
+
+fse_status_t fse_plan_workspace(const fse_plan_t* plan, size_t* bytes) {
+    if (!plan || !bytes) { set_err("null argument"); return FSE_EINVAL; }
+    *bytes = plan->bytes;
+    return FSE_OK;
+}
+
+void fse_plan_destroy(fse_plan_t* plan) {
+    if (!plan) return;
+    (void)hipStreamSynchronize(plan->stream);
+    delete plan;
+}
+
+}  // extern "C"

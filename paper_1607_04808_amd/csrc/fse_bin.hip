@@ -1,0 +1,225 @@
+// Binning of the points (integer work): Gaussian-window starts and offsets in
+// FP64 (the P^3 windows of the fast Gaussian gridding, Section 6.2), counting
+// sort by spreading tile and by real-space cell (the cell list of Section 5).
+#include "fse_common.h"
+
+namespace fse {
+
+namespace {
+
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Block-level exclusive scan of 4 items per thread; writes the block total.
+constexpr int SCAN_T = 256, SCAN_ITEMS = 4, SCAN_BLOCK = SCAN_T * SCAN_ITEMS;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_block(const int* in, int* out, int64_t n, int* sums) {
+    __shared__ int s[SCAN_T];
+    int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        tot += v[k];
+    }
+    s[threadIdx.x] = tot;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the per-thread totals
+    for (int o = 1; o < SCAN_T; o <<= 1) {
+        int t = (threadIdx.x >= o) ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = s[threadIdx.x] - tot;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == SCAN_T - 1 && sums) sums[blockIdx.x] = s[SCAN_T - 1];
+}
+
+__global__ void k_scan_add(int* out, int64_t n, const int* offs) {
+    int64_t i = (int64_t)blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    int add = offs[blockIdx.x];
+    for (int k = 0; k < SCAN_ITEMS; ++k, i += SCAN_T)
+        if (i < n) out[i] += add;
+}
+
+template <typename T>
+__global__ void k_bin(const T* __restrict__ x, int64_t n, GridGeo g, CellGeo c, int* key_s,
+                      int* rank_s, int* key_r, int* rank_r, int* cnt_s, int* cnt_r, int* bpack,
+                      T* coff, int* flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b[3], cl[3];
+    bool bad = false;
+    for (int d = 0; d < 3; ++d) {
+        double v = (double)x[3 * i + d];
+        if (!(v >= c.lo[d] && v < c.lo[d] + c.L)) bad = true;  // also catches NaN
+        // continuous grid coordinate and window start, FP64
+        double t = (v - g.x0[d]) / g.h;
+        double bb = floor(t - 0.5 * g.P + 1.0);
+        if (!(bb >= 0.0)) bb = 0.0;
+        if (!(bb <= (double)(g.Mt - g.P))) bb = (double)(g.Mt - g.P);
+        b[d] = (int)bb;
+        coff[3 * i + d] = (T)(t - bb - 0.5 * (g.P - 1));
+        double cc = floor((v - c.lo[d]) / c.cell);
+        if (!(cc >= 0.0)) cc = 0.0;
+        if (!(cc <= (double)(c.ncell - 1))) cc = (double)(c.ncell - 1);
+        cl[d] = (int)cc;
+    }
+    bpack[i] = b[0] | (b[1] << 10) | (b[2] << 20);
+    int ks = ((b[2] / g.TS) * g.nt + b[1] / g.TS) * g.nt + b[0] / g.TS;
+    int kr = (cl[2] * c.ncell + cl[1]) * c.ncell + cl[0];
+    key_s[i] = ks;
+    key_r[i] = kr;
+    rank_s[i] = atomicAdd(&cnt_s[ks], 1);
+    rank_r[i] = atomicAdd(&cnt_r[kr], 1);
+    if (bad) atomicOr(flag, 1);
+}
+
+template <typename T>
+__global__ void k_scatter(const T* __restrict__ x, int64_t n, const int* key_s, const int* rank_s,
+                          const int* start_s, const int* key_r, const int* rank_r, const int* start_r,
+                          const int* bpack, const T* coff, int* perm_s, int* bpack_s, T* coff_s,
+                          int* perm_r, T* x_r, int* inv_r) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int js = start_s[key_s[i]] + rank_s[i];
+    perm_s[js] = (int)i;
+    bpack_s[js] = bpack[i];
+    int jr = start_r[key_r[i]] + rank_r[i];
+    perm_r[jr] = (int)i;
+    inv_r[i] = jr;
+    for (int d = 0; d < 3; ++d) {
+        coff_s[3 * js + d] = coff[3 * i + d];
+        x_r[3 * jr + d] = x[3 * i + d];
+    }
+}
+
+// Per-point grid components in spread order.  Stokeslet/rotlet: f_l (3).
+// Stresslet: the symmetric part of f_lm = n_l q_m in the order
+// (00, 11, 22, 01, 02, 12); T_jlm is symmetric in (l, m), so the symmetric
+// part carries the whole sum.
+template <typename T>
+__global__ void k_permute_sources(int kernel, const T* __restrict__ a, const T* __restrict__ b,
+                                  int64_t n, int batch, const int* __restrict__ perm, T* out) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bm = blockIdx.y;
+    if (j >= n) return;
+    int64_t i = perm[j];
+    const T* ai = a + ((int64_t)bm * n + i) * 3;
+    if (kernel == FSE_STRESSLET) {
+        const T* ni = b + ((int64_t)bm * n + i) * 3;
+        T* o = out + ((int64_t)bm * n + j) * 6;
+        T q0 = ai[0], q1 = ai[1], q2 = ai[2], n0 = ni[0], n1 = ni[1], n2 = ni[2];
+        o[0] = n0 * q0;
+        o[1] = n1 * q1;
+        o[2] = n2 * q2;
+        o[3] = (T)0.5 * (n0 * q1 + n1 * q0);
+        o[4] = (T)0.5 * (n0 * q2 + n2 * q0);
+        o[5] = (T)0.5 * (n1 * q2 + n2 * q1);
+    } else {
+        T* o = out + ((int64_t)bm * n + j) * 3;
+        o[0] = ai[0];
+        o[1] = ai[1];
+        o[2] = ai[2];
+    }
+}
+
+template <typename T>
+__global__ void k_permute3(const T* __restrict__ a, int64_t n, const int* __restrict__ perm, T* out) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bm = blockIdx.y;
+    if (j >= n) return;
+    int64_t i = perm[j];
+    const T* ai = a + ((int64_t)bm * n + i) * 3;
+    T* o = out + ((int64_t)bm * n + j) * 3;
+    o[0] = ai[0];
+    o[1] = ai[1];
+    o[2] = ai[2];
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+size_t scan_tmp_ints(int64_t n) {
+    size_t tot = 0;
+    while (n > SCAN_BLOCK) {
+        int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+        tot += 2 * (size_t)nb + 2;
+        n = nb;
+    }
+    return tot + 2;
+}
+
+// Exclusive scan of n ints; `tmp` holds scan_tmp_ints(n) ints.
+void launch_scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t st) {
+    if (n <= 0) return;
+    int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_block, dim3(1), dim3(SCAN_T), 0, st, in, out, n, (int*)nullptr);
+        return;
+    }
+    int* sums = tmp;
+    int* offs = tmp + nb + 1;
+    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SCAN_T), 0, st, in, out, n, sums);
+    launch_scan_exclusive(sums, offs, nb, offs + nb + 1, st);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(SCAN_T), 0, st, out, n, offs);
+}
+
+template <typename T>
+void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* rank_s,
+                int* key_r, int* rank_r, int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_bin<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, g, c, key_s, rank_s,
+                       key_r, rank_r, cnt_s, cnt_r, bpack, coff, flag);
+}
+
+template <typename T>
+void launch_scatter(const T* x, int64_t n, const int* key_s, const int* rank_s, const int* start_s,
+                    const int* key_r, const int* rank_r, const int* start_r, const int* bpack,
+                    const T* coff, int* perm_s, int* bpack_s, T* coff_s, int* perm_r, T* x_r,
+                    int* inv_r, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, key_s, rank_s,
+                       start_s, key_r, rank_r, start_r, bpack, coff, perm_s, bpack_s, coff_s, perm_r,
+                       x_r, inv_r);
+}
+
+template <typename T>
+void launch_permute_sources(int kernel, const T* a, const T* b, int64_t n, int batch, const int* perm,
+                            T* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_permute_sources<T>, dim3(nblk(n, 256), batch), dim3(256), 0, st, kernel, a,
+                       b, n, batch, perm, out);
+}
+
+template <typename T>
+void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_permute3<T>, dim3(nblk(n, 256), batch), dim3(256), 0, st, a, n, perm, out);
+}
+
+#define INST(T)                                                                                     \
+    template void launch_bin<T>(const T*, int64_t, const GridGeo&, const CellGeo&, int*, int*, int*, \
+                                int*, int*, int*, int*, T*, int*, hipStream_t);                     \
+    template void launch_scatter<T>(const T*, int64_t, const int*, const int*, const int*,          \
+                                    const int*, const int*, const int*, const int*, const T*, int*, \
+                                    int*, T*, int*, T*, int*, hipStream_t);                         \
+    template void launch_permute_sources<T>(int, const T*, const T*, int64_t, int, const int*, T*,  \
+                                            hipStream_t);                                           \
+    template void launch_permute3<T>(const T*, int64_t, int, const int*, T*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace fse

@@ -1,0 +1,170 @@
+// Internal declarations shared by the HIP translation units of libfse.
+// gfx950 (CDNA4): 64-wide wavefronts, 160 KB LDS per workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fse.h"
+
+namespace fse {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// complex helpers (float2 / double2)
+// ---------------------------------------------------------------------------
+template <typename T> struct cplx;
+template <> struct cplx<float> { using type = float2; };
+template <> struct cplx<double> { using type = double2; };
+template <typename T> using C2 = typename cplx<T>::type;
+
+template <typename V> __device__ __forceinline__ V cmk(decltype(V::x) a, decltype(V::x) b) {
+    V v; v.x = a; v.y = b; return v;
+}
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return cmk<V>(a.x + b.x, a.y + b.y); }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return cmk<V>(a.x - b.x, a.y - b.y); }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+    return cmk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+    return cmk<V>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename V> __device__ __forceinline__ V cscale(V a, decltype(V::x) s) { return cmk<V>(a.x * s, a.y * s); }
+template <typename V> __device__ __forceinline__ V cconj(V a) { return cmk<V>(a.x, -a.y); }
+// multiply by -i (dir=-1) or +i (dir=+1)
+template <int DIR, typename V> __device__ __forceinline__ V cmuli(V a) {
+    return DIR < 0 ? cmk<V>(a.y, -a.x) : cmk<V>(-a.y, a.x);
+}
+
+// ---------------------------------------------------------------------------
+// cross-lane helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float readlane(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double readlane(double v, int lane) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// Order this wave's own LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// plan-level constants passed to kernels by value
+// ---------------------------------------------------------------------------
+struct GridGeo {
+    int Mt;          // grid points per side
+    int n;           // FFT size 2*Mt
+    int P;           // Gaussian support
+    int TS;          // spreading/quadrature tile side (grid points)
+    int nt;          // tiles per side = ceil(Mt/TS)
+    double x0[3];    // first grid node
+    double h;        // grid spacing
+    double ahh;      // alpha h^2: Gaussian exponent in grid units
+};
+
+struct CellGeo {
+    int ncell;       // cells per side
+    double lo[3];    // box corner
+    double L;        // box side
+    double cell;     // cell side (>= rc)
+    double rc2;      // rc^2
+};
+
+constexpr int MAX_RADICES = 12;
+struct FftGeo {
+    int n;                    // transform length
+    int ns;                   // number of radix stages
+    int rad[MAX_RADICES];     // radix per stage (DIF order)
+    int Ls[MAX_RADICES];      // block length at each stage
+};
+
+// Points binned for one evaluation (device pointers)
+template <typename T> struct PointsDev {
+    int64_t n;
+    const int* perm_s;        // spread order -> user index
+    const int* bpack_s;       // packed window start (bx | by<<10 | bz<<20), spread order
+    const T* coff_s;          // window-centre offsets (n,3), spread order, in [-0.5,0.5)
+    const int* tile_start;    // (nt^3 + 1) offsets into spread order
+    const int* perm_r;        // real-space order -> user index
+    const T* x_r;             // positions (n,3), real-space order
+    const int* cell_start;    // (ncell^3 + 1) offsets into real-space order
+    const int* inv_r;         // user index -> real-space order
+};
+
+// ---------------------------------------------------------------------------
+// launchers (one per translation unit); all enqueue on `st`
+// ---------------------------------------------------------------------------
+void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
+void launch_scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t st);
+size_t scan_tmp_ints(int64_t n);
+
+template <typename T>
+void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* rank_s,
+                int* key_r, int* rank_r, int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag,
+                hipStream_t st);
+template <typename T>
+void launch_scatter(const T* x, int64_t n, const int* key_s, const int* rank_s, const int* start_s,
+                    const int* key_r, const int* rank_r, const int* start_r, const int* bpack,
+                    const T* coff, int* perm_s, int* bpack_s, T* coff_s, int* perm_r, T* x_r,
+                    int* inv_r, hipStream_t st);
+
+// source permutation to spread order: out (batch, n, c_in) with the per-point
+// components the grid carries (f_l, or the symmetric n_l q_m for the stresslet)
+template <typename T>
+void launch_permute_sources(int kernel, const T* a, const T* b, int64_t n, int batch, const int* perm,
+                            T* out, hipStream_t st);
+// permute plain 3-vectors (batch, n, 3) by perm
+template <typename T>
+void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, hipStream_t st);
+
+template <typename T>
+void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int c_in, int batch,
+                   T* grid, hipStream_t st);
+template <typename T>
+void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int batch, T* u,
+                   hipStream_t st);
+template <typename T>
+void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f, const T* phi_w,
+                        const T* f_s, const T* w_s, int batch, T* dsrc, T* dx, hipStream_t st);
+
+template <typename T>
+void launch_fft_forward(const FftGeo& fg, const GridGeo& g, const T* grid, void* A, void* B,
+                        int ncomp, const T* tw, const int* rev, const int* revinv, hipStream_t st);
+template <typename T>
+void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* B, int c_in, int batch,
+                       const T* sig, double kscale, const T* tw, const int* rev, const int* revinv,
+                       hipStream_t st);
+template <typename T>
+void launch_fft_inverse(const FftGeo& fg, const GridGeo& g, void* B, void* A, T* field, int c_in,
+                        int batch, const T* tw, const int* rev, const int* revinv, hipStream_t st);
+
+template <typename T>
+void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* src_a_r,
+                 const T* src_b_r, int batch, double xi, double self_coef, T* u, int accumulate,
+                 hipStream_t st);
+template <typename T>
+void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
+                      int batch, double xi, T* dx, hipStream_t st);
+
+// precompute (FP64)
+void launch_pre_fill(double* out, int Mg, double h, double R, int family, hipStream_t st);
+void launch_pre_contract(const double* in, double* out, const double* Cm, int J, int K, int64_t A,
+                         hipStream_t st);
+template <typename T>
+void launch_pre_finalize(const double* Bt, int Mt, double kunit, double xi, double eta, int kernel,
+                         double norm, double* sig64, T* sig, hipStream_t st);
+
+}  // namespace fse

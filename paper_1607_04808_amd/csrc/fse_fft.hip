@@ -1,0 +1,546 @@
+// Zero-padded 3D FFT, scaling and inverse FFT (Section 6.2, steps 2-4).
+//
+// The (2Mt)^3 transform of an Mt^3 real grid is done as three pruned passes of
+// 1D transforms staged in LDS, each pass writing its output transposed so the
+// next pass reads contiguous lines:
+//   x-pass  grid[c][z][y][x] (real)  -> A[c][kx][z][y]   R2C, two real rows per
+//                                                          complex transform
+//   y-pass  A[c][kx][z][y]           -> B[c][kx][ky][z]
+//   z-pass  B[c][kx][ky][z]          -> B (in place): forward z transform,
+//           multiplication by the Fourier multiplier of eq. gridfcnsc (scalar
+//           precomputed part times the k-polynomial of eqs. AS/AT/AR), inverse z
+//           transform, keep z < Mt.  The spectrum never reaches HBM.
+//   y-inv   B -> A (keep y < Mt),  x-inv  A -> field[c][z][y][x] (C2R, keep x < Mt).
+// Only the Mt nonzero input lines are read and only the Mt kept output lines are
+// written per direction (the zero padding and the truncation of Section 6.2).
+//
+// 1D transforms: in-place mixed-radix (2,3,4,5,7,8) decimation in frequency,
+// leaving the spectrum in digit-reversed order; the inverse is the matching
+// decimation in time, which takes digit-reversed input and returns natural
+// order.  Inverses are unnormalised (1/n^3 lives in the multiplier).
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "fse_common.h"
+
+namespace fse {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small DFTs: y_k = sum_j x_j exp(DIR * 2 pi i jk / R)   (DIR = -1 forward)
+// ---------------------------------------------------------------------------
+template <typename V, int DIR> __device__ __forceinline__ void dft2(V* x) {
+    V a = cadd(x[0], x[1]), b = csub(x[0], x[1]);
+    x[0] = a;
+    x[1] = b;
+}
+template <typename V, int DIR> __device__ __forceinline__ void dft3(V* x) {
+    using T = decltype(V::x);
+    const T h3 = (T)0.86602540378443864676;
+    V s = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+    V t = csub(x[0], cscale(s, (T)0.5));
+    V e = cmuli<DIR>(cscale(d, h3));
+    x[0] = cadd(x[0], s);
+    x[1] = cadd(t, e);
+    x[2] = csub(t, e);
+}
+template <typename V, int DIR> __device__ __forceinline__ void dft4(V* x) {
+    V a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    V c = cadd(x[1], x[3]), d = cmuli<DIR>(csub(x[1], x[3]));
+    x[0] = cadd(a, c);
+    x[2] = csub(a, c);
+    x[1] = cadd(b, d);
+    x[3] = csub(b, d);
+}
+template <typename V, int DIR> __device__ __forceinline__ void dft5(V* x) {
+    using T = decltype(V::x);
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+    V a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+    V a2 = cadd(x[2], x[3]), b2 = csub(x[2], x[3]);
+    V y0 = cadd(x[0], cadd(a1, a2));
+    V t1 = cadd(x[0], cadd(cscale(a1, c1), cscale(a2, c2)));
+    V t2 = cadd(x[0], cadd(cscale(a1, c2), cscale(a2, c1)));
+    V u1 = cmuli<DIR>(cadd(cscale(b1, s1), cscale(b2, s2)));
+    V u2 = cmuli<DIR>(csub(cscale(b1, s2), cscale(b2, s1)));
+    x[0] = y0;
+    x[1] = cadd(t1, u1);
+    x[4] = csub(t1, u1);
+    x[2] = cadd(t2, u2);
+    x[3] = csub(t2, u2);
+}
+template <typename V, int DIR> __device__ __forceinline__ void dft7(V* x) {
+    using T = decltype(V::x);
+    // cos / sin (2 pi m / 7), m = 0..6
+    const T C[7] = {(T)1.0, (T)0.62348980185873353053, (T)-0.22252093395631440429,
+                    (T)-0.90096886790241912624, (T)-0.90096886790241912624,
+                    (T)-0.22252093395631440429, (T)0.62348980185873353053};
+    const T S[7] = {(T)0.0, (T)0.78183148246802980871, (T)0.97492791218182360702,
+                    (T)0.43388373911755812048, (T)-0.43388373911755812048,
+                    (T)-0.97492791218182360702, (T)-0.78183148246802980871};
+    V a[4], b[4];
+#pragma unroll
+    for (int j = 1; j <= 3; ++j) {
+        a[j] = cadd(x[j], x[7 - j]);
+        b[j] = csub(x[j], x[7 - j]);
+    }
+    V y[7];
+    y[0] = cadd(x[0], cadd(a[1], cadd(a[2], a[3])));
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        V t = x[0], u = cmk<V>((T)0, (T)0);
+#pragma unroll
+        for (int j = 1; j <= 3; ++j) {
+            const int m = (j * k) % 7;
+            t = cadd(t, cscale(a[j], C[m]));
+            u = cadd(u, cscale(b[j], S[m]));
+        }
+        u = cmuli<DIR>(u);
+        y[k] = cadd(t, u);
+        y[7 - k] = csub(t, u);
+    }
+#pragma unroll
+    for (int k = 0; k < 7; ++k) x[k] = y[k];
+}
+template <typename V, int DIR> __device__ __forceinline__ void dft8(V* x) {
+    using T = decltype(V::x);
+    const T r = (T)0.70710678118654752440;
+    V e[4] = {x[0], x[2], x[4], x[6]};
+    V o[4] = {x[1], x[3], x[5], x[7]};
+    dft4<V, DIR>(e);
+    dft4<V, DIR>(o);
+    // W = exp(DIR 2 pi i / 8)
+    V w1 = cmul(o[1], cmk<V>(r, (T)DIR * r));
+    V w2 = cmuli<DIR>(o[2]);
+    V w3 = cmul(o[3], cmk<V>(-r, (T)DIR * r));
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], w1);
+    x[5] = csub(e[1], w1);
+    x[2] = cadd(e[2], w2);
+    x[6] = csub(e[2], w2);
+    x[3] = cadd(e[3], w3);
+    x[7] = csub(e[3], w3);
+}
+
+template <typename V, int R, int DIR> __device__ __forceinline__ void dft(V* x) {
+    if constexpr (R == 2) dft2<V, DIR>(x);
+    else if constexpr (R == 3) dft3<V, DIR>(x);
+    else if constexpr (R == 4) dft4<V, DIR>(x);
+    else if constexpr (R == 5) dft5<V, DIR>(x);
+    else if constexpr (R == 7) dft7<V, DIR>(x);
+    else dft8<V, DIR>(x);
+}
+
+// One DIF butterfly: DFT of x[k*m], then twiddle output k by w_Ls^{n1 k}.
+template <typename V, int R>
+__device__ __forceinline__ void bf_dif(V* p, int m, int tstep, const V* tw) {
+    V x[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = p[k * m];
+    dft<V, R, -1>(x);
+#pragma unroll
+    for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[tstep * k]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) p[k * m] = x[k];
+}
+// Matching inverse DIT butterfly: conjugate twiddle, then inverse DFT.
+template <typename V, int R>
+__device__ __forceinline__ void bf_dit_inv(V* p, int m, int tstep, const V* tw) {
+    V x[R];
+    x[0] = p[0];
+#pragma unroll
+    for (int k = 1; k < R; ++k) x[k] = cmulc(p[k * m], tw[tstep * k]);
+    dft<V, R, 1>(x);
+#pragma unroll
+    for (int k = 0; k < R; ++k) p[k * m] = x[k];
+}
+
+template <typename V, bool INV>
+__device__ __forceinline__ void bf(int r, V* p, int m, int tstep, const V* tw) {
+    switch (r) {
+        case 2: INV ? bf_dit_inv<V, 2>(p, m, tstep, tw) : bf_dif<V, 2>(p, m, tstep, tw); break;
+        case 3: INV ? bf_dit_inv<V, 3>(p, m, tstep, tw) : bf_dif<V, 3>(p, m, tstep, tw); break;
+        case 4: INV ? bf_dit_inv<V, 4>(p, m, tstep, tw) : bf_dif<V, 4>(p, m, tstep, tw); break;
+        case 5: INV ? bf_dit_inv<V, 5>(p, m, tstep, tw) : bf_dif<V, 5>(p, m, tstep, tw); break;
+        case 7: INV ? bf_dit_inv<V, 7>(p, m, tstep, tw) : bf_dif<V, 7>(p, m, tstep, tw); break;
+        default: INV ? bf_dit_inv<V, 8>(p, m, tstep, tw) : bf_dif<V, 8>(p, m, tstep, tw); break;
+    }
+}
+
+// All stages over `nl` lines of length n stored at buf + l*ld.  Barrier after
+// every stage (and none needed before the first: callers sync after loading).
+template <typename V, bool INV>
+__device__ void fft_lines(V* buf, int nl, int ld, const FftGeo& fg, const V* tw) {
+    const int n = fg.n;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int si = 0; si < fg.ns; ++si) {
+        const int s = INV ? fg.ns - 1 - si : si;
+        const int r = fg.rad[s], Ls = fg.Ls[s], m = Ls / r, ts = n / Ls;
+        const int nbf = n / r;
+        const int tot = nl * nbf;
+        for (int q = tid; q < tot; q += nthr) {
+            const int l = q / nbf;
+            const int b = q - l * nbf;
+            const int blk = b / m;
+            const int n1 = b - blk * m;
+            bf<V, INV>(r, buf + l * ld + blk * Ls + n1, m, n1 * ts, tw);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename V>
+__device__ __forceinline__ void load_tables(V* tw, int* idx, const V* twg, const int* idxg, int n) {
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        tw[q] = twg[q];
+        idx[q] = idxg[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x-pass: R2C of ROWS real rows (paired into ROWS/2 complex lines)
+// ---------------------------------------------------------------------------
+template <typename T, int ROWS>
+__global__ __launch_bounds__(256) void k_fft_x(FftGeo fg, int Mt, const T* __restrict__ grid,
+                                              C2<T>* __restrict__ A, const C2<T>* __restrict__ twg,
+                                              const int* __restrict__ revinvg) {
+    using V = C2<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = fg.n;
+    V* tw = (V*)smem;
+    V* buf = tw + n;
+    int* revinv = (int*)(buf + (ROWS / 2) * n);
+    load_tables(tw, revinv, twg, revinvg, n);
+    const int y0 = blockIdx.x * ROWS, z = blockIdx.y, bc = blockIdx.z;
+    const int64_t M2 = (int64_t)Mt * Mt;
+    const T* src = grid + ((int64_t)bc * Mt + z) * M2;
+    for (int l = 0; l < ROWS / 2; ++l) {
+        const int ya = y0 + 2 * l, yb = ya + 1;
+        for (int x = threadIdx.x; x < n; x += blockDim.x) {
+            const T re = (x < Mt && ya < Mt) ? src[(int64_t)ya * Mt + x] : (T)0;
+            const T im = (x < Mt && yb < Mt) ? src[(int64_t)yb * Mt + x] : (T)0;
+            buf[l * n + x] = cmk<V>(re, im);
+        }
+    }
+    __syncthreads();
+    fft_lines<V, false>(buf, ROWS / 2, n, fg, tw);
+    V* dst = A + (int64_t)bc * (Mt + 1) * M2 + (int64_t)z * Mt + y0;
+    for (int q = threadIdx.x; q < (Mt + 1) * ROWS; q += blockDim.x) {
+        const int kx = q / ROWS, r = q % ROWS;
+        if (y0 + r >= Mt) continue;
+        const int l = r >> 1;
+        const V zk = buf[l * n + revinv[kx]];
+        const V zn = buf[l * n + revinv[kx == 0 ? 0 : n - kx]];
+        V X;
+        if (r & 1) X = cmk<V>((T)0.5 * (zk.y + zn.y), (T)0.5 * (zn.x - zk.x));
+        else X = cmk<V>((T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y));
+        dst[(int64_t)kx * M2 + r] = X;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y-pass forward: LZ lines (consecutive z) at fixed (c, kx)
+// ---------------------------------------------------------------------------
+template <typename T, int LZ>
+__global__ __launch_bounds__(256) void k_fft_y(FftGeo fg, int Mt, const C2<T>* __restrict__ A,
+                                              C2<T>* __restrict__ B, const C2<T>* __restrict__ twg,
+                                              const int* __restrict__ revinvg) {
+    using V = C2<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = fg.n;
+    V* tw = (V*)smem;
+    V* buf = tw + n;
+    int* revinv = (int*)(buf + LZ * n);
+    load_tables(tw, revinv, twg, revinvg, n);
+    const int z0 = blockIdx.x * LZ, kx = blockIdx.y, bc = blockIdx.z;
+    const int64_t M2 = (int64_t)Mt * Mt;
+    const V* src = A + ((int64_t)bc * (Mt + 1) + kx) * M2;
+    for (int l = 0; l < LZ; ++l) {
+        const int z = z0 + l;
+        for (int y = threadIdx.x; y < n; y += blockDim.x)
+            buf[l * n + y] = (y < Mt && z < Mt) ? src[(int64_t)z * Mt + y] : cmk<V>((T)0, (T)0);
+    }
+    __syncthreads();
+    fft_lines<V, false>(buf, LZ, n, fg, tw);
+    V* dst = B + ((int64_t)bc * (Mt + 1) + kx) * n * Mt;
+    for (int q = threadIdx.x; q < n * LZ; q += blockDim.x) {
+        const int ky = q / LZ, r = q % LZ;
+        if (z0 + r < Mt) dst[(int64_t)ky * Mt + z0 + r] = buf[r * n + revinv[ky]];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z-pass: forward z FFT, multiplier, inverse z FFT for one (kx, ky) column
+// ---------------------------------------------------------------------------
+// Apply the k-polynomial of the kernel at wavevector k (physical units) to the
+// c_in grid components g, giving 3 outputs (the scalar sigma is applied after).
+template <typename T, int KERNEL>
+__device__ __forceinline__ void kpoly(const T k[3], const C2<T>* g, C2<T>* w) {
+    using V = C2<T>;
+    const T k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    if constexpr (KERNEL == FSE_STOKESLET) {
+        // (k^2 d_jl - k_j k_l) g_l
+        const V kg = cadd(cadd(cscale(g[0], k[0]), cscale(g[1], k[1])), cscale(g[2], k[2]));
+#pragma unroll
+        for (int j = 0; j < 3; ++j) w[j] = csub(cscale(g[j], k2), cscale(kg, k[j]));
+    } else if constexpr (KERNEL == FSE_ROTLET) {
+        // -i eps_jlm g_l k_m = -i (g x k)_j
+        const V c0 = csub(cscale(g[1], k[2]), cscale(g[2], k[1]));
+        const V c1 = csub(cscale(g[2], k[0]), cscale(g[0], k[2]));
+        const V c2 = csub(cscale(g[0], k[1]), cscale(g[1], k[0]));
+        w[0] = cmuli<-1>(c0);
+        w[1] = cmuli<-1>(c1);
+        w[2] = cmuli<-1>(c2);
+    } else {
+        // -i [ k^2 (2 (G k)_j + k_j tr G) - 2 k_j (k.G.k) ],  G symmetric:
+        // g = (G00, G11, G22, G01, G02, G12)
+        const V Gk0 = cadd(cadd(cscale(g[0], k[0]), cscale(g[3], k[1])), cscale(g[4], k[2]));
+        const V Gk1 = cadd(cadd(cscale(g[3], k[0]), cscale(g[1], k[1])), cscale(g[5], k[2]));
+        const V Gk2 = cadd(cadd(cscale(g[4], k[0]), cscale(g[5], k[1])), cscale(g[2], k[2]));
+        const V tr = cadd(cadd(g[0], g[1]), g[2]);
+        const V kGk = cadd(cadd(cscale(Gk0, k[0]), cscale(Gk1, k[1])), cscale(Gk2, k[2]));
+        const V Gk[3] = {Gk0, Gk1, Gk2};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const V t = csub(cscale(cadd(cscale(Gk[j], (T)2), cscale(tr, k[j])), k2),
+                             cscale(kGk, (T)2 * k[j]));
+            w[j] = cmuli<-1>(t);
+        }
+    }
+}
+
+template <typename T, int KERNEL, int CIN>
+__global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, C2<T>* __restrict__ B,
+                                              const T* __restrict__ sig, double kscale,
+                                              const C2<T>* __restrict__ twg,
+                                              const int* __restrict__ revg) {
+    using V = C2<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = fg.n;
+    V* tw = (V*)smem;
+    V* buf = tw + n;
+    int* rev = (int*)(buf + CIN * n);
+    load_tables(tw, rev, twg, revg, n);
+    const int ky = blockIdx.x, kx = blockIdx.y, bm = blockIdx.z;
+    const int64_t lstride = (int64_t)(Mt + 1) * n * Mt;  // between components
+    V* col = B + (int64_t)bm * CIN * lstride + ((int64_t)kx * n + ky) * Mt;
+#pragma unroll
+    for (int c = 0; c < CIN; ++c)
+        for (int z = threadIdx.x; z < n; z += blockDim.x)
+            buf[c * n + z] = (z < Mt) ? col[c * lstride + z] : cmk<V>((T)0, (T)0);
+    __syncthreads();
+    fft_lines<V, false>(buf, CIN, n, fg, tw);
+    // multiplier
+    const int kys = (ky < Mt) ? ky : ky - n;
+    const bool nyx = (kx == Mt), nyy = (ky == Mt);
+    const T ks = (T)kscale;
+    const int Mp = Mt + 1;
+    const T* sigrow = sig + ((int64_t)kx * Mp + (kys < 0 ? -kys : kys)) * Mp;
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const int kzi = rev[p];
+        const int kzs = (kzi < Mt) ? kzi : kzi - n;
+        const bool nyz = (kzi == Mt);
+        V g[CIN];
+#pragma unroll
+        for (int c = 0; c < CIN; ++c) g[c] = buf[c * n + p];
+        const T s = sigrow[kzs < 0 ? -kzs : kzs];
+        T k[3] = {ks * (T)kx, ks * (T)kys, ks * (T)kzs};
+        V w[3];
+        kpoly<T, KERNEL>(k, g, w);
+        if (nyx || nyy || nyz) {
+            // Nyquist planes: use the Hermitian part of the multiplier, the mean
+            // of its values at k and at k with the Nyquist components negated.
+            T kr[3] = {nyx ? -k[0] : k[0], nyy ? -k[1] : k[1], nyz ? -k[2] : k[2]};
+            V wr[3];
+            kpoly<T, KERNEL>(kr, g, wr);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) w[j] = cscale(cadd(w[j], wr[j]), (T)0.5);
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) buf[j * n + p] = cscale(w[j], s);
+    }
+    __syncthreads();
+    fft_lines<V, true>(buf, 3, n, fg, tw);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        for (int z = threadIdx.x; z < Mt; z += blockDim.x) col[c * lstride + z] = buf[c * n + z];
+}
+
+// ---------------------------------------------------------------------------
+// y-pass inverse: LZ lines (consecutive z) at fixed (c, kx); keep y < Mt
+// ---------------------------------------------------------------------------
+template <typename T, int LZ>
+__global__ __launch_bounds__(256) void k_fft_yinv(FftGeo fg, int Mt, int c_in,
+                                                 const C2<T>* __restrict__ B, C2<T>* __restrict__ A,
+                                                 const C2<T>* __restrict__ twg,
+                                                 const int* __restrict__ revinvg) {
+    using V = C2<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = fg.n;
+    V* tw = (V*)smem;
+    V* buf = tw + n;
+    int* revinv = (int*)(buf + LZ * n);
+    load_tables(tw, revinv, twg, revinvg, n);
+    const int z0 = blockIdx.x * LZ, kx = blockIdx.y;
+    const int bm = blockIdx.z / 3, c = blockIdx.z % 3;
+    const int64_t bc = (int64_t)bm * c_in + c;
+    const int64_t M2 = (int64_t)Mt * Mt;
+    const V* src = B + (bc * (Mt + 1) + kx) * n * Mt;
+    for (int q = threadIdx.x; q < n * LZ; q += blockDim.x) {
+        const int ky = q / LZ, r = q % LZ;
+        buf[r * n + revinv[ky]] = (z0 + r < Mt) ? src[(int64_t)ky * Mt + z0 + r] : cmk<V>((T)0, (T)0);
+    }
+    __syncthreads();
+    fft_lines<V, true>(buf, LZ, n, fg, tw);
+    V* dst = A + (bc * (Mt + 1) + kx) * M2;
+    for (int l = 0; l < LZ; ++l) {
+        const int z = z0 + l;
+        if (z >= Mt) break;
+        for (int y = threadIdx.x; y < Mt; y += blockDim.x) dst[(int64_t)z * Mt + y] = buf[l * n + y];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x-pass inverse: C2R of ROWS half spectra (paired), keep x < Mt
+// ---------------------------------------------------------------------------
+template <typename T, int ROWS>
+__global__ __launch_bounds__(256) void k_fft_xinv(FftGeo fg, int Mt, int c_in,
+                                                 const C2<T>* __restrict__ A, T* __restrict__ field,
+                                                 const C2<T>* __restrict__ twg,
+                                                 const int* __restrict__ revinvg) {
+    using V = C2<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = fg.n;
+    const int Mp = Mt + 1;
+    V* tw = (V*)smem;
+    V* buf = tw + n;
+    V* H = buf + (ROWS / 2) * n;
+    int* revinv = (int*)(H + ROWS * Mp);
+    load_tables(tw, revinv, twg, revinvg, n);
+    const int y0 = blockIdx.x * ROWS, z = blockIdx.y;
+    const int bm = blockIdx.z / 3, c = blockIdx.z % 3;
+    const int64_t bc = (int64_t)bm * c_in + c, fc = (int64_t)bm * 3 + c;
+    const int64_t M2 = (int64_t)Mt * Mt;
+    const V* src = A + bc * Mp * M2 + (int64_t)z * Mt + y0;
+    for (int q = threadIdx.x; q < Mp * ROWS; q += blockDim.x) {
+        const int kx = q / ROWS, r = q % ROWS;
+        H[r * Mp + kx] = (y0 + r < Mt) ? src[(int64_t)kx * M2 + r] : cmk<V>((T)0, (T)0);
+    }
+    __syncthreads();
+    for (int l = 0; l < ROWS / 2; ++l) {
+        const V* Ha = H + (2 * l) * Mp;
+        const V* Hb = H + (2 * l + 1) * Mp;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const V xa = (k <= Mt) ? Ha[k] : cconj(Ha[n - k]);
+            const V xb = (k <= Mt) ? Hb[k] : cconj(Hb[n - k]);
+            buf[l * n + revinv[k]] = cmk<V>(xa.x - xb.y, xa.y + xb.x);
+        }
+    }
+    __syncthreads();
+    fft_lines<V, true>(buf, ROWS / 2, n, fg, tw);
+    T* dst = field + (fc * Mt + z) * M2;
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + r;
+        if (y >= Mt) break;
+        const V* line = buf + (r >> 1) * n;
+        for (int x = threadIdx.x; x < Mt; x += blockDim.x) {
+            const V v = line[x];
+            dst[(int64_t)y * Mt + x] = (r & 1) ? v.y : v.x;
+        }
+    }
+}
+
+template <typename T> constexpr int xrows() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T> constexpr int ylines() { return sizeof(T) == 4 ? 16 : 8; }
+
+// Allow the dynamic LDS a pass needs (above the 64 KB default); once per kernel.
+template <typename K> void set_lds(K kern, size_t bytes) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, size_t>> done;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& d : done)
+        if (d.first == (const void*)kern && d.second >= bytes) return;
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    done.emplace_back((const void*)kern, (size_t)160 * 1024);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_fft_forward(const FftGeo& fg, const GridGeo& g, const T* grid, void* Av, void* Bv, int ncomp,
+                        const T* tw, const int* rev, const int* revinv, hipStream_t st) {
+    using V = C2<T>;
+    (void)rev;
+    const int Mt = g.Mt, n = fg.n;
+    constexpr int R = xrows<T>(), LZ = ylines<T>();
+    V* A = (V*)Av;
+    V* B = (V*)Bv;
+    size_t shx = sizeof(V) * (size_t)n * (1 + R / 2) + sizeof(int) * n;
+    set_lds(k_fft_x<T, R>, shx);
+    hipLaunchKernelGGL((k_fft_x<T, R>), dim3((Mt + R - 1) / R, Mt, ncomp), dim3(256), shx, st, fg, Mt,
+                       grid, A, (const V*)tw, revinv);
+    size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
+    set_lds(k_fft_y<T, LZ>, shy);
+    hipLaunchKernelGGL((k_fft_y<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, ncomp), dim3(256), shy, st,
+                       fg, Mt, (const V*)A, B, (const V*)tw, revinv);
+}
+
+template <typename T>
+void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv, int c_in, int batch,
+                       const T* sig, double kscale, const T* tw, const int* rev, const int* revinv,
+                       hipStream_t st) {
+    using V = C2<T>;
+    (void)revinv;
+    const int Mt = g.Mt, n = fg.n;
+    V* B = (V*)Bv;
+    dim3 grd(n, Mt + 1, batch);
+    size_t sh = sizeof(V) * (size_t)n * (1 + c_in) + sizeof(int) * n;
+    if (kernel == FSE_STOKESLET) {
+        set_lds(k_fft_z<T, FSE_STOKESLET, 3>, sh);
+        hipLaunchKernelGGL((k_fft_z<T, FSE_STOKESLET, 3>), grd, dim3(128), sh, st, fg, Mt, B, sig,
+                           kscale, (const V*)tw, rev);
+    } else if (kernel == FSE_ROTLET) {
+        set_lds(k_fft_z<T, FSE_ROTLET, 3>, sh);
+        hipLaunchKernelGGL((k_fft_z<T, FSE_ROTLET, 3>), grd, dim3(128), sh, st, fg, Mt, B, sig, kscale,
+                           (const V*)tw, rev);
+    } else {
+        set_lds(k_fft_z<T, FSE_STRESSLET, 6>, sh);
+        hipLaunchKernelGGL((k_fft_z<T, FSE_STRESSLET, 6>), grd, dim3(128), sh, st, fg, Mt, B, sig,
+                           kscale, (const V*)tw, rev);
+    }
+}
+
+template <typename T>
+void launch_fft_inverse(const FftGeo& fg, const GridGeo& g, void* Bv, void* Av, T* field, int c_in,
+                        int batch, const T* tw, const int* rev, const int* revinv, hipStream_t st) {
+    using V = C2<T>;
+    (void)rev;
+    const int Mt = g.Mt, n = fg.n;
+    constexpr int R = xrows<T>(), LZ = ylines<T>();
+    V* A = (V*)Av;
+    V* B = (V*)Bv;
+    size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
+    set_lds(k_fft_yinv<T, LZ>, shy);
+    hipLaunchKernelGGL((k_fft_yinv<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, 3 * batch), dim3(256), shy,
+                       st, fg, Mt, c_in, (const V*)B, A, (const V*)tw, revinv);
+    size_t shx = sizeof(V) * ((size_t)n * (1 + R / 2) + (size_t)R * (Mt + 1)) + sizeof(int) * n;
+    set_lds(k_fft_xinv<T, R>, shx);
+    hipLaunchKernelGGL((k_fft_xinv<T, R>), dim3((Mt + R - 1) / R, Mt, 3 * batch), dim3(256), shx, st, fg,
+                       Mt, c_in, (const V*)A, field, (const V*)tw, revinv);
+}
+
+#define INST(T)                                                                                      \
+    template void launch_fft_forward<T>(const FftGeo&, const GridGeo&, const T*, void*, void*, int,  \
+                                        const T*, const int*, const int*, hipStream_t);              \
+    template void launch_fft_zscale<T>(const FftGeo&, const GridGeo&, int, void*, int, int, const T*, \
+                                       double, const T*, const int*, const int*, hipStream_t);       \
+    template void launch_fft_inverse<T>(const FftGeo&, const GridGeo&, void*, void*, T*, int, int,   \
+                                        const T*, const int*, const int*, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace fse

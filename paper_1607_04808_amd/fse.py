@@ -1,0 +1,290 @@
+"""Python binding of libfse (include/fse.h): argument marshalling only.
+
+Every step of the evaluation runs in the HIP library; torch supplies device
+memory and the current stream.  There is no CPU fallback: without the built
+library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libfse.so")
+
+KERNELS = {"stokeslet": 0, "stresslet": 1, "rotlet": 2}
+DTYPES = {"f32": 0, "f64": 1}
+STATUS = {0: "FSE_OK", 1: "FSE_EINVAL", 2: "FSE_ERANGE", 3: "FSE_ENOMEM", 4: "FSE_EHIP",
+          5: "FSE_EUNSUPPORTED", 6: "FSE_ESTATE"}
+EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set_stream",
+           "fse_set_points", "fse_eval", "fse_eval_parts", "fse_eval_adjoint", "fse_plan_multiplier",
+           "fse_plan_workspace", "fse_plan_destroy", "fse_status_string", "fse_last_error")
+
+
+class FseError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("xi", ctypes.c_double), ("rc", ctypes.c_double), ("M", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("box_lo", ctypes.c_double * 3), ("L", ctypes.c_double),
+                ("deltaL_rule", ctypes.c_int32), ("Mt", ctypes.c_int32), ("C", ctypes.c_double)]
+
+
+class GeometryC(ctypes.Structure):
+    _fields_ = [("Mt", ctypes.c_int32), ("n_fft", ctypes.c_int32), ("Mg", ctypes.c_int32),
+                ("ncell", ctypes.c_int32), ("h", ctypes.c_double), ("d", ctypes.c_double),
+                ("m", ctypes.c_double), ("eta", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("Lt", ctypes.c_double), ("R", ctypes.c_double), ("deltaL", ctypes.c_double),
+                ("kinf", ctypes.c_double), ("cell", ctypes.c_double), ("x0", ctypes.c_double * 3),
+                ("radices", ctypes.c_int32 * 8)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Load libfse.so; raise if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libfse.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+            L.fse_geometry.argtypes = [ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(GeometryC)]
+            L.fse_plan_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params), i32, i64, vp,
+                                          ctypes.POINTER(vp)]
+            L.fse_plan_geometry.argtypes = [vp, ctypes.POINTER(GeometryC)]
+            L.fse_plan_set_stream.argtypes = [vp, vp]
+            L.fse_set_points.argtypes = [vp, i64, vp, i32]
+            L.fse_eval.argtypes = [vp, vp, vp, vp]
+            L.fse_eval_parts.argtypes = [vp, vp, vp, vp, vp]
+            L.fse_eval_adjoint.argtypes = [vp, vp, vp, vp, vp, i32]
+            L.fse_plan_multiplier.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+            L.fse_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+            L.fse_plan_destroy.argtypes = [vp]
+            L.fse_plan_destroy.restype = None
+            L.fse_status_string.argtypes = [ctypes.c_int]
+            L.fse_status_string.restype = ctypes.c_char_p
+            L.fse_last_error.restype = ctypes.c_char_p
+            for name in EXPORTS:
+                if name not in ("fse_plan_destroy", "fse_status_string", "fse_last_error"):
+                    getattr(L, name).restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise FseError(status, lib().fse_last_error().decode())
+
+
+def make_params(xi, rc, M, P, box_lo=(0.0, 0.0, 0.0), L=1.0, deltaL_rule=0, Mt=0, C=0.0) -> Params:
+    p = Params()
+    p.xi, p.rc, p.M, p.P = float(xi), float(rc), int(M), int(P)
+    for d in range(3):
+        p.box_lo[d] = float(box_lo[d])
+    p.L, p.deltaL_rule, p.Mt, p.C = float(L), int(deltaL_rule), int(Mt), float(C)
+    return p
+
+
+@dataclass
+class Geometry:
+    Mt: int
+    n_fft: int
+    Mg: int
+    ncell: int
+    h: float
+    d: float
+    m: float
+    eta: float
+    alpha: float
+    Lt: float
+    R: float
+    deltaL: float
+    kinf: float
+    cell: float
+    x0: tuple
+    radices: tuple
+
+    @classmethod
+    def from_c(cls, g: GeometryC):
+        return cls(g.Mt, g.n_fft, g.Mg, g.ncell, g.h, g.d, g.m, g.eta, g.alpha, g.Lt, g.R, g.deltaL,
+                   g.kinf, g.cell, tuple(g.x0), tuple(r for r in g.radices if r))
+
+
+def _kid(kernel):
+    return KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+
+
+def geometry(kernel, params: Params) -> Geometry:
+    """Derived geometry (host only, no GPU needed)."""
+    g = GeometryC()
+    _check(lib().fse_geometry(_kid(kernel), ctypes.byref(params), ctypes.byref(g)))
+    return Geometry.from_c(g)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An FSE plan on the current HIP device (see fse_plan_create)."""
+
+    def __init__(self, kernel, dtype, params: Params, batch=1, nmax=2):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libfse needs a HIP device")
+        self.kernel = kernel if isinstance(kernel, str) else list(KERNELS)[kernel]
+        self.dtype = dtype
+        self.tdtype = torch.float32 if dtype == "f32" else torch.float64
+        self.batch = int(batch)
+        self.nmax = int(nmax)
+        self.params = params
+        self._h = ctypes.c_void_p()
+        _check(lib().fse_plan_create(_kid(kernel), DTYPES[dtype], ctypes.byref(params), self.batch,
+                                     self.nmax, _stream_ptr(), ctypes.byref(self._h)))
+        g = GeometryC()
+        _check(lib().fse_plan_geometry(self._h, ctypes.byref(g)))
+        self.geometry = Geometry.from_c(g)
+        self.n = 0
+        self.generation = 0
+
+    def close(self):
+        if self._h:
+            lib().fse_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().fse_plan_set_stream(self._h, _stream_ptr()))
+
+    def _prep(self, t, shape):
+        torch = _torch()
+        if t.device.type != "cuda":
+            raise ValueError("expected a device tensor")
+        t = t.to(self.tdtype).contiguous()
+        if tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape)
+        return t
+
+    def set_points(self, x, validate=True):
+        x = self._prep(x, (x.shape[0], 3))
+        self._sync_stream()
+        self._x = x  # keep alive while the plan may read it
+        _check(lib().fse_set_points(self._h, x.shape[0], _ptr(x), 1 if validate else 0))
+        self.n = x.shape[0]
+        self.generation += 1
+        return self
+
+    def _src_shape(self):
+        return (self.batch, self.n, 3)
+
+    def eval(self, a, b=None, out=None):
+        torch = _torch()
+        a = self._prep(a, self._src_shape())
+        b = None if b is None else self._prep(b, self._src_shape())
+        if out is None:
+            out = torch.empty(self._src_shape(), dtype=self.tdtype, device=a.device)
+        self._sync_stream()
+        _check(lib().fse_eval(self._h, _ptr(a), _ptr(b), _ptr(out)))
+        self.generation += 1
+        return out
+
+    def eval_parts(self, a, b=None):
+        torch = _torch()
+        a = self._prep(a, self._src_shape())
+        b = None if b is None else self._prep(b, self._src_shape())
+        uR = torch.empty(self._src_shape(), dtype=self.tdtype, device=a.device)
+        uF = torch.empty_like(uR)
+        self._sync_stream()
+        _check(lib().fse_eval_parts(self._h, _ptr(a), _ptr(b), _ptr(uR), _ptr(uF)))
+        self.generation += 1
+        return uR, uF
+
+    def adjoint(self, f, w, want_df=True, want_dx=True, recompute=True):
+        torch = _torch()
+        f = self._prep(f, self._src_shape())
+        w = self._prep(w, self._src_shape())
+        df = torch.empty(self._src_shape(), dtype=self.tdtype, device=f.device) if want_df else None
+        dx = torch.empty((self.n, 3), dtype=self.tdtype, device=f.device) if want_dx else None
+        self._sync_stream()
+        _check(lib().fse_eval_adjoint(self._h, _ptr(f), _ptr(w), _ptr(df), _ptr(dx), 1 if recompute else 0))
+        self.generation += 1
+        return df, dx
+
+    def multiplier(self):
+        Mp = self.geometry.Mt + 1
+        out = np.empty((Mp, Mp, Mp), dtype=np.float64)
+        self._sync_stream()
+        _check(lib().fse_plan_multiplier(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        _check(lib().fse_plan_workspace(self._h, ctypes.byref(b)))
+        return b.value
+
+
+def _autograd():
+    torch = _torch()
+
+    class FSEFunction(torch.autograd.Function):
+        """u = FSE sum of f at x; backward gives dL/dx and dL/df (stokeslet, rotlet)."""
+
+        @staticmethod
+        def forward(ctx, x, f, plan: Plan):
+            plan.set_points(x.detach())
+            u = plan.eval(f.detach())
+            ctx.plan = plan
+            ctx.gen = plan.generation
+            ctx.save_for_backward(x, f)
+            return u.reshape(f.shape)
+
+        @staticmethod
+        def backward(ctx, gu):
+            x, f = ctx.saved_tensors
+            plan = ctx.plan
+            recompute = plan.generation != ctx.gen
+            if recompute:
+                plan.set_points(x.detach())
+            df, dx = plan.adjoint(f.detach(), gu.detach(), want_df=ctx.needs_input_grad[1],
+                                  want_dx=ctx.needs_input_grad[0], recompute=recompute)
+            return (None if dx is None else dx.reshape(x.shape),
+                    None if df is None else df.reshape(f.shape), None)
+
+    return FSEFunction
+
+
+_FN = None
+
+
+def fse_sum(x, f, plan: Plan):
+    """Differentiable FSE sum (stokeslet or rotlet plan): u(x_m) = sum_{n != m} G(x_m - x_n) f_n."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd()
+    return _FN.apply(x, f, plan)

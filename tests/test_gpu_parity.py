@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, element by element.
+
+Tolerances (relative to the largest component of the reference, the max-norm
+of Section 8's "relative error" reading):
+  FP64: the HIP path and the oracle run the same steps (same windows, same
+        mollified kernel, same multipliers); only summation order and the FFT
+        algorithm differ, so they agree to ~1e-13; 1e-10 is asserted.
+  FP32: unit roundoff 6e-8; the spread sums ~P^3 terms per node, the FFTs add
+        ~log2(n) rounding steps, the quadrature ~P^3 terms; the observed error
+        is a few 1e-7; 2e-6 is asserted for the Fourier part and the total,
+        5e-6 for the real-space part alone (sums of ~1/r terms with cancellation).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, se
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1607_04808_amd as F  # noqa: E402
+
+DEV = "cuda:0"
+TOL = {"f64": 1e-10, "f32": 2e-6}
+TOL_REAL = {"f64": 1e-10, "f32": 5e-6}
+
+
+def relmax(u, ref):
+    u = np.asarray(u, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(u - ref).max() / np.abs(ref).max())
+
+
+def _inputs(kernel, n, seed, L=1.0, lo=(0.0, 0.0, 0.0), positions="uniform", batch=None):
+    if positions == "uniform":
+        x = W.uniform_cube(n, seed, lo=0.0, L=L) + np.asarray(lo)
+    elif positions == "blobs":
+        x = np.clip(W.gaussian_blobs(n, seed, nblobs=8, sigma=0.03), 0.0, 1.0 - 1e-9) * L + np.asarray(lo)
+    a = W.normal_strengths(n, seed + 1, batch)
+    b = W.normal_strengths(n, seed + 2, batch) if kernel == "stresslet" else None
+    return x, a, b
+
+
+def _plan(kernel, dtype, params, n, batch=1):
+    return F.Plan(kernel, dtype, params, batch=batch, nmax=n)
+
+
+def _t(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=torch.float32 if dtype == "f32" else torch.float64, device=DEV)
+
+
+def _oracle_geo(plan, params):
+    p = params
+    return se.geometry(p.xi, p.rc, p.M, p.P, tuple(p.box_lo), p.L, Mt=plan.geometry.Mt,
+                       deltaL_rule=p.deltaL_rule)
+
+
+def _as64(x, dtype):
+    """The FP32 form evaluates the FP32-rounded inputs; the oracle gets those exactly."""
+    if x is None:
+        return None
+    return np.asarray(x, dtype=np.float32).astype(np.float64) if dtype == "f32" else np.asarray(x)
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("Mt", [0, 28, 30, 35])
+def test_multiplier_matches_mollified_kernel(kernel, Mt):
+    """The precomputed scalar multiplier = eq. gridfcnsc factor x eqs. AS/AT/AR scalar x
+    the mollified kernel of Section 4.3 (oracle: literal IFFT/crop/FFT) x normalisations."""
+    params = F.make_params(6.0, 0.4, 16, 8, L=1.0, Mt=Mt)
+    plan = _plan(kernel, "f64", params, 16)
+    sig = plan.multiplier()
+    g = _oracle_geo(plan, params)
+    Kt = se.mollified_kernel(se.kernel_family(kernel), g)
+    Mp = g.Mt + 1
+    oct_ = Kt[:Mp, :Mp, :Mp]
+    kb = np.arange(Mp)
+    k2 = (math.pi / g.Lt) ** 2 * (kb[:, None, None] ** 2 + kb[None, :, None] ** 2 + kb[None, None, :] ** 2)
+    E = np.exp(-(1 - g.eta) * k2 / (4 * g.xi ** 2))
+    fac = {"stokeslet": -(1 + k2 / (4 * g.xi ** 2)) * E, "stresslet": (1 + k2 / (4 * g.xi ** 2)) * E,
+           "rotlet": E}[kernel]
+    norm = (g.alpha / math.pi) ** 3 * g.h ** 3 / g.n ** 3
+    ref = fac * oct_ * norm
+    assert relmax(sig, ref) < 1e-11
+    plan.close()
+
+
+CASES = [
+    # (n, xi, rc, M, P, Mt, L, lo)
+    (1500, 10.0, 0.32, 24, 10, 0, 1.0, (0.0, 0.0, 0.0)),
+    (777, 8.0, 0.45, 20, 13, 28, 1.3, (-0.5, 0.25, 2.0)),   # odd P, ragged n, radices 8,7
+    (2048, 12.0, 0.25, 30, 16, 45, 1.0, (0.0, 0.0, 0.0)),   # radices 5,3,3,2
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_parts_parity(kernel, dtype, case):
+    n, xi, rc, M, P, Mt, L, lo = CASES[case]
+    params = F.make_params(xi, rc, M, P, lo, L, Mt=Mt)
+    x, a, b = _inputs(kernel, n, 100 + case, L=L, lo=lo)
+    plan = _plan(kernel, dtype, params, n)
+    plan.set_points(_t(x, dtype))
+    uR, uF = plan.eval_parts(_t(a, dtype), None if b is None else _t(b, dtype))
+    uR, uF = uR.cpu().numpy()[0], uF.cpu().numpy()[0]
+    g = _oracle_geo(plan, params)
+    x64, a64, b64 = _as64(x, dtype), _as64(a, dtype), _as64(b, dtype)
+    refF = se.fourier_part(kernel, x64, a64, b64, g)
+    refR = direct.real_trunc(kernel, xi, rc, x64, a64, b64) + se.self_term(kernel, xi, a64)
+    eF, eR = relmax(uF, refF), relmax(uR, refR)
+    print("case", case, kernel, dtype, "Mt", g.Mt, "errF %.2e errR %.2e" % (eF, eR))
+    assert eF < TOL[dtype]
+    assert eR < TOL_REAL[dtype]
+    plan.close()
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
+def test_total_against_direct_sum(kernel):
+    """fse_eval = u^R + u^F + u^self, and with tight parameters it equals the
+    direct sum (the method's truncation errors below 1e-9)."""
+    n = 1200
+    params = F.make_params(6.0, 0.95, 24, 20, L=1.0, deltaL_rule=1)
+    x, a, b = _inputs(kernel, n, 7)
+    plan = _plan(kernel, "f64", params, n)
+    plan.set_points(_t(x, "f64"))
+    u = plan.eval(_t(a, "f64"), None if b is None else _t(b, "f64")).cpu().numpy()[0]
+    uR, uF = plan.eval_parts(_t(a, "f64"), None if b is None else _t(b, "f64"))
+    np.testing.assert_allclose(u, (uR + uF).cpu().numpy()[0], rtol=0, atol=1e-12 * np.abs(u).max())
+    ref = direct.direct(kernel, x, a, b)
+    mx, rms = direct.rel_errors(u, ref)
+    print(kernel, "vs direct: max %.2e rms %.2e" % (mx, rms))
+    assert mx < 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_matches_single(dtype):
+    n, B = 900, 3
+    params = F.make_params(9.0, 0.35, 22, 12, L=1.0)
+    x, a, _ = _inputs("rotlet", n, 11, batch=B)
+    pb = _plan("rotlet", dtype, params, n, batch=B)
+    pb.set_points(_t(x, dtype))
+    ub = pb.eval(_t(a, dtype)).cpu().numpy()
+    p1 = _plan("rotlet", dtype, params, n)
+    p1.set_points(_t(x, dtype))
+    for k in range(B):
+        u1 = p1.eval(_t(a[k], dtype)).cpu().numpy()[0]
+        assert relmax(ub[k], u1) < (1e-13 if dtype == "f64" else 1e-6)
+    pb.close()
+    p1.close()
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+def test_adjoint_matches_oracle(kernel):
+    n = 1000
+    params = F.make_params(8.0, 0.4, 20, 12, L=1.0)
+    x, f, _ = _inputs(kernel, n, 21)
+    w = W.normal_strengths(n, 24)
+    plan = _plan(kernel, "f64", params, n)
+    plan.set_points(_t(x, "f64"))
+    u = plan.eval(_t(f, "f64"))
+    df, dx = plan.adjoint(_t(f, "f64"), _t(w, "f64"), recompute=False)
+    uw = plan.eval(_t(w, "f64")).cpu().numpy()[0]
+    # dL/df = K w (the discrete operator is symmetric)
+    assert relmax(df.cpu().numpy()[0], uw) < 1e-12
+    g = _oracle_geo(plan, params)
+    ref = se.grad_x(kernel, x, f, w, g)
+    e = relmax(dx.cpu().numpy(), ref)
+    print(kernel, "dL/dx err %.2e" % e)
+    assert e < 1e-10
+    del u
+    plan.close()
+
+
+def test_adjoint_recompute_flag():
+    n = 600
+    params = F.make_params(8.0, 0.4, 20, 12, L=1.0)
+    x, f, _ = _inputs("stokeslet", n, 31)
+    w = W.normal_strengths(n, 32)
+    plan = _plan("stokeslet", "f64", params, n)
+    plan.set_points(_t(x, "f64"))
+    plan.eval(_t(f, "f64"))
+    d1 = plan.adjoint(_t(f, "f64"), _t(w, "f64"), recompute=False)[1].cpu().numpy()
+    plan.eval(_t(w, "f64"))  # overwrite the cached forward grid
+    d2 = plan.adjoint(_t(f, "f64"), _t(w, "f64"), recompute=True)[1].cpu().numpy()
+    np.testing.assert_allclose(d2, d1, rtol=0, atol=1e-13 * np.abs(d1).max())
+    plan.close()
+
+
+def test_autograd_function():
+    n = 500
+    params = F.make_params(8.0, 0.4, 20, 12, L=1.0)
+    x, f, _ = _inputs("stokeslet", n, 41)
+    w = W.normal_strengths(n, 42)
+    plan = _plan("stokeslet", "f64", params, n)
+    xt = _t(x, "f64").requires_grad_(True)
+    ft = _t(f, "f64").requires_grad_(True)
+    u = F.fse_sum(xt, ft, plan)
+    (u * _t(w, "f64")).sum().backward()
+    g = _oracle_geo(plan, params)
+    assert relmax(xt.grad.cpu().numpy(), se.grad_x("stokeslet", x, f, w, g)) < 1e-10
+    uw = se.evaluate("stokeslet", x, w, g=g)["u"]
+    assert relmax(ft.grad.cpu().numpy(), uw) < 1e-10
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_edge_cases_tiny_and_corners(dtype):
+    """n = 2 and 3, points on the box's lower corner and just inside its upper faces."""
+    params = F.make_params(5.0, 0.6, 12, 8, (0.0, 0.0, 0.0), 1.0)
+    top = 1.0 - 2.0 ** -20
+    for x in (np.array([[0.0, 0.0, 0.0], [top, top, top]]),
+              np.array([[0.0, 0.5, top], [top, 0.0, 0.5], [0.5, top, 0.0]])):
+        n = len(x)
+        f = W.normal_strengths(n, 50 + n)
+        plan = _plan("stokeslet", dtype, params, 8)
+        plan.set_points(_t(x, dtype))
+        uR, uF = plan.eval_parts(_t(f, dtype))
+        g = _oracle_geo(plan, params)
+        x64, f64 = _as64(x, dtype), _as64(f, dtype)
+        refF = se.fourier_part("stokeslet", x64, f64, None, g)
+        refR = direct.real_trunc("stokeslet", 5.0, 0.6, x64, f64) + se.self_term("stokeslet", 5.0, f64)
+        assert relmax(uF.cpu().numpy()[0], refF) < TOL[dtype]
+        assert relmax(uR.cpu().numpy()[0], refR) < TOL_REAL[dtype]
+        plan.close()
+
+
+def test_clustered_points():
+    n = 3000
+    params = F.make_params(14.0, 0.2, 32, 12, L=1.0)
+    x, a, _ = _inputs("stokeslet", n, 60, positions="blobs")
+    plan = _plan("stokeslet", "f64", params, n)
+    plan.set_points(_t(x, "f64"))
+    uR, uF = plan.eval_parts(_t(a, "f64"))
+    g = _oracle_geo(plan, params)
+    assert relmax(uF.cpu().numpy()[0], se.fourier_part("stokeslet", x, a, None, g)) < 1e-10
+    refR = direct.real_trunc("stokeslet", 14.0, 0.2, x, a) + se.self_term("stokeslet", 14.0, a)
+    assert relmax(uR.cpu().numpy()[0], refR) < 1e-10
+    plan.close()
+
+
+def test_out_of_box_points_rejected():
+    params = F.make_params(5.0, 0.6, 12, 8, (0.0, 0.0, 0.0), 1.0)
+    plan = _plan("stokeslet", "f64", params, 8)
+    for bad in (1.0, -1e-9, float("nan")):
+        x = np.array([[0.1, 0.2, 0.3], [0.5, bad, 0.5]])
+        with pytest.raises(F.FseError) as e:
+            plan.set_points(_t(x, "f64"))
+        assert e.value.status == 2
+    # unvalidated: the kernels clamp and still run safely
+    plan.set_points(_t(np.array([[0.1, 0.2, 0.3], [0.5, 3.0, 0.5]]), "f64"), validate=False)
+    plan.eval(_t(np.ones((2, 3)), "f64"))
+    torch.cuda.synchronize()
+    plan.close()
