@@ -159,6 +159,13 @@ fse_status_t fse_eval_adjoint(fse_plan_t *plan, const void *src_a, const void *w
  * and normalisations) to host memory `out`.  Synchronises. */
 fse_status_t fse_plan_multiplier(fse_plan_t *plan, double *out);
 
+/* Copy, for tests, the grid of the last evaluation to host memory `out` as
+ * FP64, layout (batch, components, z, y, x) with x fastest, Mt^3 per
+ * component: which = 0 the spread sources (step 1 of Section 6.2, without the
+ * Gaussian normalisation), which = 1 the scaled inverse-transformed grid that
+ * the quadrature reads (step 4).  Synchronises. */
+fse_status_t fse_plan_grid(fse_plan_t *plan, int32_t which, double *out);
+
 /* Device bytes held by the plan.  Synchronises nothing. */
 fse_status_t fse_plan_workspace(const fse_plan_t *plan, size_t *bytes);
 

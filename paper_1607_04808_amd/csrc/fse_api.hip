@@ -592,6 +592,22 @@ fse_status_t fse_plan_multiplier(fse_plan_t* plan, double* out) {
     return FSE_OK;
 }
 
+fse_status_t fse_plan_grid(fse_plan_t* plan, int32_t which, double* out) {
+    if (!plan || !out || (which != 0 && which != 1)) { set_err("bad argument"); return FSE_EINVAL; }
+    const size_t M3 = (size_t)plan->geo.Mt * plan->geo.Mt * plan->geo.Mt;
+    const size_t cnt = (size_t)plan->batch * (which == 0 ? plan->c_in : 3) * M3;
+    const void* src = which == 0 ? plan->grid : plan->phi;
+    HIPCHK(hipStreamSynchronize(plan->stream));
+    if (plan->dtype == FSE_F64) {
+        HIPCHK(hipMemcpy(out, src, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(cnt);
+        HIPCHK(hipMemcpy(tmp.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < cnt; ++i) out[i] = tmp[i];
+    }
+    return FSE_OK;
+}
+
 fse_status_t fse_plan_workspace(const fse_plan_t* plan, size_t* bytes) {
     if (!plan || !bytes) { set_err("null argument"); return FSE_EINVAL; }
     *bytes = plan->bytes;

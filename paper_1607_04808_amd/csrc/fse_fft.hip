@@ -347,7 +347,8 @@ __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, C2<T>* __restr
 #pragma unroll
         for (int c = 0; c < CIN; ++c) g[c] = buf[c * n + p];
         const T s = sigrow[kzs < 0 ? -kzs : kzs];
-        T k[3] = {ks * (T)kx, ks * (T)kys, ks * (T)kzs};
+        // wavenumbers in [-Mt, Mt): the Nyquist index carries -Mt in every direction
+        T k[3] = {ks * (T)(nyx ? -Mt : kx), ks * (T)kys, ks * (T)kzs};
         V w[3];
         kpoly<T, KERNEL>(k, g, w);
         if (nyx || nyy || nyz) {

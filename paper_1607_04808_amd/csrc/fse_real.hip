@@ -26,7 +26,7 @@ template <typename T> __device__ __forceinline__ T derfc(T x);
 template <> __device__ __forceinline__ float derfc<float>(float x) { return erfcf(x); }
 template <> __device__ __forceinline__ double derfc<double>(double x) { return erfc(x); }
 template <typename T> __device__ __forceinline__ T dexpr(T x);
-template <> __device__ __forceinline__ float dexpr<float>(float x) { return __expf(x); }
+template <> __device__ __forceinline__ float dexpr<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double dexpr<double>(double x) { return exp(x); }
 
 template <typename T, int KERNEL, int NB>

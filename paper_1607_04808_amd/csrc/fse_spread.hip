@@ -17,7 +17,7 @@ namespace fse {
 namespace {
 
 template <typename T> __device__ __forceinline__ T dexp(T x);
-template <> __device__ __forceinline__ float dexp<float>(float x) { return __expf(x); }
+template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 
 template <typename T, int NC, int TS>

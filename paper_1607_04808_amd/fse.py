@@ -22,7 +22,7 @@ STATUS = {0: "FSE_OK", 1: "FSE_EINVAL", 2: "FSE_ERANGE", 3: "FSE_ENOMEM", 4: "FS
           5: "FSE_EUNSUPPORTED", 6: "FSE_ESTATE"}
 EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set_stream",
            "fse_set_points", "fse_eval", "fse_eval_parts", "fse_eval_adjoint", "fse_plan_multiplier",
-           "fse_plan_workspace", "fse_plan_destroy", "fse_status_string", "fse_last_error")
+           "fse_plan_workspace", "fse_plan_grid", "fse_plan_destroy", "fse_status_string", "fse_last_error")
 
 
 class FseError(RuntimeError):
@@ -70,6 +70,7 @@ def lib():
             L.fse_eval_adjoint.argtypes = [vp, vp, vp, vp, vp, i32]
             L.fse_plan_multiplier.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
             L.fse_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+            L.fse_plan_grid.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
             L.fse_plan_destroy.argtypes = [vp]
             L.fse_plan_destroy.restype = None
             L.fse_status_string.argtypes = [ctypes.c_int]
@@ -241,6 +242,14 @@ class Plan:
         out = np.empty((Mp, Mp, Mp), dtype=np.float64)
         self._sync_stream()
         _check(lib().fse_plan_multiplier(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def grid(self, which):
+        """Host copy (float64) of the spread grid (0) or the scaled inverse-transformed grid (1)."""
+        Mt = self.geometry.Mt
+        nc = (6 if self.kernel == "stresslet" else 3) if which == 0 else 3
+        out = np.empty((self.batch, nc, Mt, Mt, Mt), dtype=np.float64)
+        _check(lib().fse_plan_grid(self._h, int(which), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
     def workspace_bytes(self):
