@@ -192,12 +192,15 @@ __device__ void fft_lines(V* buf, int nl, int ld, const FftGeo& fg, const V* tw)
     }
 }
 
+// Stage the twiddle and index tables in LDS; the barrier makes them visible
+// to every thread before any use.
 template <typename V>
 __device__ __forceinline__ void load_tables(V* tw, int* idx, const V* twg, const int* idxg, int n) {
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
         tw[q] = twg[q];
         idx[q] = idxg[q];
     }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
