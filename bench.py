@@ -1,0 +1,251 @@
+"""Benchmark: stokeslet targets/s at 1e-6 relative error, N = 1M, forward + adjoint,
+FP32 form (headline) and FP64 form, on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input already in HBM:
+bin/sort the points, forward FSE sum (spread, FFT, scale, IFFT, gather, real
+space), and the adjoint (dL/df and dL/dx for L = sum_m w_m . u(x_m)).
+
+Prints ONE JSON line.  `value` is the FP32-form forward+adjoint throughput;
+the FP64 form, forward-only rates, per-stage times, the roofline of the
+dominant kernel and the CPU baseline (the oracle on a bounded target sample,
+which also gives the sampled relative error) are extra fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+PEAK = {"hbm_GBs": 8000.0, "f32_TFLOPs": 157.3, "f64_TFLOPs": 78.6}
+
+# Parameters per form (calibrated against the oracle):
+# FP32 form: 1e-6 relative max-norm; FP64 form: 1e-10.
+FORMS = {
+    "f32": dict(xi=60.0, rc=0.063, M=183, P=12, tol=1e-6),
+    "f64": dict(xi=60.0, rc=0.081, M=228, P=22, tol=1e-10),
+}
+N_DEFAULT = 1_000_000
+L_BOX = 1.0 + 2.0 ** -20  # the unit cube, enlarged so FP32-rounded points stay inside
+
+
+def cube_pair_cdf(r):
+    """P(|x - y| <= r) for two uniform points in the unit cube, 0 <= r <= 1."""
+    return 4 * math.pi / 3 * r ** 3 - 1.5 * math.pi * r ** 4 + 1.6 * r ** 5 - r ** 6 / 6
+
+
+def stage_work(stage, geo, n, P, dtype, pairs, c_in=3, batch=1):
+    """Algorithmic (bytes, flops) of one launch group of a stage."""
+    s = 4 if dtype == "f32" else 8
+    Mt, nf = geo.Mt, geo.n_fft
+    Mp = Mt + 1
+    M3 = Mt ** 3
+    nc = batch * c_in
+    if stage == "fft_x":
+        return nc * (M3 * s + Mp * Mt * Mt * 2 * s), None
+    if stage == "fft_y":
+        return nc * (Mp * Mt * Mt * 2 * s + Mp * nf * Mt * 2 * s), None
+    if stage == "fft_z_scale":
+        return batch * (c_in + 3) * Mp * nf * Mt * 2 * s + Mp ** 3 * s, None
+    if stage == "fft_yinv":
+        return batch * 3 * (Mp * nf * Mt * 2 * s + Mp * Mt * Mt * 2 * s), None
+    if stage == "fft_xinv":
+        return batch * 3 * (Mp * Mt * Mt * 2 * s + M3 * s), None
+    if stage == "spread":
+        # per point and window node: 1 weight product + c_in multiply-adds
+        return nc * M3 * s + n * 4 * s, n * P ** 3 * (1 + 2 * c_in) * batch
+    if stage == "gather":
+        return batch * 3 * M3 * s + n * 4 * s, n * P ** 3 * (2 + 2 * 3) * batch
+    if stage == "gather_grad":
+        return 2 * batch * 3 * M3 * s, n * P ** 3 * batch * (2 + 12 + 6 + 6 + 6)
+    if stage in ("real", "real_grad"):
+        # per interacting pair: r^2 (5), sqrt+div (2), exp (1), erfc (1), coefficients and
+        # the 3x3 application (~25): counted as 34 flops; gradients about twice that
+        per = 34 if stage == "real" else 70
+        return None, pairs * per * batch
+    return None, None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=N_DEFAULT)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form measurement")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-targets", type=int, default=2048, help="oracle target sample size")
+    ap.add_argument("--forms", default="f32,f64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
+              "(the multi-GPU decomposition is a design note in DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1607_04808_amd as F
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    cfg_id = 0
+    x64 = W.uniform_cube(n, 1000 + cfg_id)
+    f64 = W.normal_strengths(n, 2000 + cfg_id)
+    w64 = W.normal_strengths(n, 3000 + cfg_id)
+    pair_count = n * (n - 1) * cube_pair_cdf(FORMS["f32"]["rc"])
+
+    results = {}
+    outputs = {}
+    forms = [f for f in args.forms.split(",") if f]
+    if args.no_fp64 and "f64" in forms:
+        forms.remove("f64")
+    for form in forms:
+        prm = FORMS[form]
+        tdt = torch.float32 if form == "f32" else torch.float64
+        x = torch.tensor(x64, dtype=tdt, device=dev)
+        f = torch.tensor(f64, dtype=tdt, device=dev)
+        w = torch.tensor(w64, dtype=tdt, device=dev)
+        params = F.make_params(prm["xi"], prm["rc"], prm["M"], prm["P"], (0.0, 0.0, 0.0), L_BOX)
+        t0 = time.time()
+        plan = F.Plan("stokeslet", form, params, batch=1, nmax=n)
+        torch.cuda.synchronize()
+        t_plan = time.time() - t0
+        plan.set_points(x, validate=True)
+        geo = plan.geometry
+
+        def step(adjoint=True):
+            plan.set_points(x, validate=False)
+            u = plan.eval(f)
+            if adjoint:
+                df, dx = plan.adjoint(f, w, recompute=False)
+                return u, df, dx
+            return u, None, None
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        plan.timings()
+        plan.set_timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            u, df, dx = step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        stages = plan.timings()
+        plan.set_timing(False)
+        # forward-only rate
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            step(adjoint=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_fwd = e0.elapsed_time(e1) / args.steps
+        outputs[form] = (u.cpu().numpy()[0], df.cpu().numpy()[0], dx.cpu().numpy())
+        pairs = n * (n - 1) * cube_pair_cdf(prm["rc"] / L_BOX)
+        stage_tab = {}
+        for name, (tot, cnt) in stages.items():
+            if cnt == 0:
+                continue
+            per = tot / cnt
+            b, fl = stage_work(name, geo, n, prm["P"], form, pairs / 1.0)
+            # launches per step of this stage (e.g. two spreads per forward+adjoint step)
+            stage_tab[name] = dict(ms_per_step=tot / args.steps, ms_per_launch=per, launches=cnt,
+                                   GBs=(b / per / 1e6 if b else None),
+                                   TFLOPs=(fl / per / 1e9 if fl else None))
+        results[form] = dict(params=dict(prm, Mt=geo.Mt, n_fft=geo.n_fft, eta=round(geo.eta, 4), L=L_BOX),
+                             ms_per_step=ms, ms_forward=ms_fwd, targets_per_s=n / (ms / 1e3),
+                             forward_targets_per_s=n / (ms_fwd / 1e3), plan_seconds=t_plan,
+                             workspace_GB=plan.workspace_bytes() / 1e9, stages=stage_tab)
+        plan.close()
+        del x, f, w
+        torch.cuda.empty_cache()
+
+    head = results.get("f32") or next(iter(results.values()))
+    head_form = "f32" if "f32" in results else forms[0]
+    # dominant kernel and its roofline
+    dom_name, dom = max(head["stages"].items(), key=lambda kv: kv[1]["ms_per_step"])
+    peak_alu = PEAK["f32_TFLOPs"] if head_form == "f32" else PEAK["f64_TFLOPs"]
+    if dom["GBs"] is not None and dom["TFLOPs"] is None:
+        roof = dict(kernel=dom_name, bound="hbm", achieved=round(dom["GBs"], 1), peak=PEAK["hbm_GBs"],
+                    unit="GB/s", frac=round(dom["GBs"] / PEAK["hbm_GBs"], 4), traffic=None)
+    else:
+        roof = dict(kernel=dom_name, bound="alu", achieved=round(dom["TFLOPs"], 2), peak=peak_alu,
+                    unit="TFLOP/s", frac=round(dom["TFLOPs"] / peak_alu, 4), traffic=None)
+
+    line = {
+        "metric": "stokeslet targets/s at 1e-6 rel err, N=1M; fwd+adjoint; FP32 vs FP64 form",
+        "value": round(head["targets_per_s"], 1),
+        "unit": "targets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head_form,
+        "data": "synthetic",
+        "config": {"workload": "stokeslet sum, N=%d points uniform in [0,1)^3, f and w i.i.d. N(0,1), "
+                               "forward + adjoint (dL/df, dL/dx), %s form" % (n, head_form),
+                   "n": n, "kernel": "stokeslet", "params": head["params"]},
+        "roofline": roof,
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items() if kk != "stages"}
+                  for k, v in results.items()},
+        "stages": {k: v["stages"] for k, v in results.items()},
+    }
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"], line["error"] = cpu_baseline(x64, f64, w64, outputs, args.cpu_targets)
+    print(json.dumps(line))
+
+
+def cpu_baseline(x64, f64, w64, outputs, T):
+    """The oracle (FP64 direct sum and analytic gradient) on a seeded sample of T
+    targets with all N sources; gives the CPU rate and the sampled errors."""
+    from oracle import direct
+    n = len(x64)
+    tg = np.sort(W.rng(4000).choice(n, size=min(T, n), replace=False)).astype(np.int64)
+    errs = {}
+    t0 = time.time()
+    u_ref = direct.direct("stokeslet", x64, f64, targets=tg)
+    t1 = time.time()
+    g_ref = direct.grad_direct("stokeslet", x64, f64, w64, targets=tg)
+    t2 = time.time()
+    df_ref = direct.direct("stokeslet", x64, w64, targets=tg)
+    for form, (u, df, dx) in outputs.items():
+        # the FP32 form evaluates the FP32-rounded inputs; its reference uses them
+        if form == "f32":
+            xs, fs, ws = (a.astype(np.float32).astype(np.float64) for a in (x64, f64, w64))
+            ur = direct.direct("stokeslet", xs, fs, targets=tg)
+            gr = direct.grad_direct("stokeslet", xs, fs, ws, targets=tg)
+            dr = direct.direct("stokeslet", xs, ws, targets=tg)
+        else:
+            ur, gr, dr = u_ref, g_ref, df_ref
+        errs[form] = {
+            "u": dict(zip(("max", "rms"), (float("%.3g" % e) for e in direct.rel_errors(u[tg], ur)))),
+            "dL_df": dict(zip(("max", "rms"), (float("%.3g" % e) for e in direct.rel_errors(df[tg], dr)))),
+            "dL_dx": dict(zip(("max", "rms"), (float("%.3g" % e) for e in direct.rel_errors(dx[tg], gr)))),
+            "targets_sampled": int(len(tg)),
+        }
+    cores = direct.num_threads()
+    rate = len(tg) / ((t1 - t0) + (t2 - t1))
+    base = {"value": round(rate, 2), "unit": "targets/s", "cores": cores, "kind": "oracle",
+            "sample": "%d seeded targets x %d sources, FP64 direct sum + analytic gradient "
+                      "(forward %.2fs, gradient %.2fs)" % (len(tg), n, t1 - t0, t2 - t1)}
+    return base, errs
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,20 @@ fse_status_t fse_plan_multiplier(fse_plan_t *plan, double *out);
  * the quadrature reads (step 4).  Synchronises. */
 fse_status_t fse_plan_grid(fse_plan_t *plan, int32_t which, double *out);
 
+/*
+ * Per-stage timing with HIP events recorded on the plan's stream around each
+ * kernel launch group.  Stages (index: name): 0 bin, 1 permute, 2 spread,
+ * 3 fft_x, 4 fft_y, 5 fft_z_scale, 6 fft_yinv, 7 fft_xinv, 8 gather, 9 real,
+ * 10 gather_grad, 11 real_grad.  Timing is off by default.
+ * fse_plan_timings synchronises the stream, writes the summed milliseconds
+ * (ms[FSE_NSTAGES]) and launch-group counts (launches[FSE_NSTAGES], may be
+ * NULL) since the last call, and resets them.
+ */
+#define FSE_NSTAGES 12
+fse_status_t fse_plan_set_timing(fse_plan_t *plan, int32_t enable);
+fse_status_t fse_plan_timings(fse_plan_t *plan, double *ms, int64_t *launches);
+const char *fse_stage_name(int32_t stage);
+
 /* Device bytes held by the plan.  Synchronises nothing. */
 fse_status_t fse_plan_workspace(const fse_plan_t *plan, size_t *bytes);
 

@@ -153,7 +153,51 @@ fse_status_t compute_geometry(fse_kernel_t kernel, const fse_params_t* p, fse_ge
     return FSE_OK;
 }
 
-template <typename T> size_t tsz() { return sizeof(T); }
+// Optional per-stage timing with HIP events on the plan's stream.
+enum Stage {
+    ST_BIN, ST_PERMUTE, ST_SPREAD, ST_FFTX, ST_FFTY, ST_FFTZ, ST_FFTYI, ST_FFTXI, ST_GATHER, ST_REAL,
+    ST_GGRAD, ST_RGRAD, ST_COUNT
+};
+static_assert(ST_COUNT == FSE_NSTAGES, "stage count");
+const char* const STAGE_NAMES[ST_COUNT] = {"bin",       "permute",    "spread",  "fft_x",
+                                           "fft_y",     "fft_z_scale", "fft_yinv", "fft_xinv",
+                                           "gather",    "real",       "gather_grad", "real_grad"};
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int stage; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    ~Timer() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct TimedStage {
+    Timer& t;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    TimedStage(Timer& t_, int s, hipStream_t st_) : t(t_), stage(s), st(st_) {
+        if (t.on && (a = t.get())) (void)hipEventRecord(a, st);
+    }
+    ~TimedStage() {
+        if (!a) return;
+        hipEvent_t b = t.get();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        t.recs.push_back({stage, a, b});
+    }
+};
 
 }  // namespace
 
@@ -173,6 +217,7 @@ struct fse_plan {
     size_t bytes = 0;
     bool forward_valid = false;
     std::vector<void*> allocs;
+    Timer timer;
 
     // points
     int *key_s, *rank_s, *key_r, *rank_r, *bpack, *perm_s, *bpack_s, *perm_r, *inv_r;
@@ -365,16 +410,19 @@ template <typename T> fse_status_t plan_init(fse_plan* p) {
 
 template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T* x, int validate) {
     hipStream_t st = p->stream;
-    launch_fill_i32(p->cnt_s, p->ntiles3 + 1, 0, st);
-    launch_fill_i32(p->cnt_r, p->ncells3 + 1, 0, st);
-    launch_fill_i32(p->flag, 1, 0, st);
-    launch_bin<T>(x, n, p->gg, p->cg, p->key_s, p->rank_s, p->key_r, p->rank_r, p->cnt_s, p->cnt_r,
-                  p->bpack, (T*)p->coff, p->flag, st);
-    launch_scan_exclusive(p->cnt_s, p->start_s, p->ntiles3 + 1, p->scan_tmp, st);
-    launch_scan_exclusive(p->cnt_r, p->start_r, p->ncells3 + 1, p->scan_tmp, st);
-    launch_scatter<T>(x, n, p->key_s, p->rank_s, p->start_s, p->key_r, p->rank_r, p->start_r, p->bpack,
-                      (const T*)p->coff, p->perm_s, p->bpack_s, (T*)p->coff_s, p->perm_r, (T*)p->x_r,
-                      p->inv_r, st);
+    {
+        TimedStage ts(p->timer, ST_BIN, st);
+        launch_fill_i32(p->cnt_s, p->ntiles3 + 1, 0, st);
+        launch_fill_i32(p->cnt_r, p->ncells3 + 1, 0, st);
+        launch_fill_i32(p->flag, 1, 0, st);
+        launch_bin<T>(x, n, p->gg, p->cg, p->key_s, p->rank_s, p->key_r, p->rank_r, p->cnt_s, p->cnt_r,
+                      p->bpack, (T*)p->coff, p->flag, st);
+        launch_scan_exclusive(p->cnt_s, p->start_s, p->ntiles3 + 1, p->scan_tmp, st);
+        launch_scan_exclusive(p->cnt_r, p->start_r, p->ncells3 + 1, p->scan_tmp, st);
+        launch_scatter<T>(x, n, p->key_s, p->rank_s, p->start_s, p->key_r, p->rank_r, p->start_r, p->bpack,
+                          (const T*)p->coff, p->perm_s, p->bpack_s, (T*)p->coff_s, p->perm_r, (T*)p->x_r,
+                          p->inv_r, st);
+    }
     LAUNCHCHK();
     p->n = n;
     p->forward_valid = false;
@@ -394,13 +442,23 @@ template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T*
 template <typename T> void fourier_chain(fse_plan* p, const T* src_s, T* field) {
     hipStream_t st = p->stream;
     PointsDev<T> pd = points<T>(p);
-    launch_spread<T>(p->gg, pd, src_s, p->c_in, p->batch, (T*)p->grid, st);
-    launch_fft_forward<T>(p->fg, p->gg, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
-                          p->rev, p->revinv, st);
-    launch_fft_zscale<T>(p->fg, p->gg, (int)p->kernel, p->B, p->c_in, p->batch, (const T*)p->sig,
-                         PI / p->geo.Lt, (const T*)p->tw, p->rev, p->revinv, st);
-    launch_fft_inverse<T>(p->fg, p->gg, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
-                          p->revinv, st);
+    Timer& tm = p->timer;
+    { TimedStage ts(tm, ST_SPREAD, st); launch_spread<T>(p->gg, pd, src_s, p->c_in, p->batch, (T*)p->grid, st); }
+    { TimedStage ts(tm, ST_FFTX, st);
+      launch_fft_forward<T>(p->fg, p->gg, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
+                            p->rev, p->revinv, st, 1); }
+    { TimedStage ts(tm, ST_FFTY, st);
+      launch_fft_forward<T>(p->fg, p->gg, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
+                            p->rev, p->revinv, st, 2); }
+    { TimedStage ts(tm, ST_FFTZ, st);
+      launch_fft_zscale<T>(p->fg, p->gg, (int)p->kernel, p->B, p->c_in, p->batch, (const T*)p->sig,
+                           PI / p->geo.Lt, (const T*)p->tw, p->rev, p->revinv, st); }
+    { TimedStage ts(tm, ST_FFTYI, st);
+      launch_fft_inverse<T>(p->fg, p->gg, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
+                            p->revinv, st, 1); }
+    { TimedStage ts(tm, ST_FFTXI, st);
+      launch_fft_inverse<T>(p->fg, p->gg, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
+                            p->revinv, st, 2); }
 }
 
 double self_coef(const fse_plan* p) {
@@ -412,20 +470,27 @@ fse_status_t eval_t(fse_plan* p, const T* a, const T* b, T* u_real, T* u_four, b
     hipStream_t st = p->stream;
     const int64_t n = p->n;
     PointsDev<T> pd = points<T>(p);
-    launch_permute_sources<T>((int)p->kernel, a, b, n, p->batch, p->perm_s, (T*)p->src_s, st);
-    launch_permute3<T>(a, n, p->batch, p->perm_r, (T*)p->src_ra, st);
-    if (p->kernel == FSE_STRESSLET) launch_permute3<T>(b, n, p->batch, p->perm_r, (T*)p->src_rb, st);
+    Timer& tm = p->timer;
+    {
+        TimedStage ts(tm, ST_PERMUTE, st);
+        launch_permute_sources<T>((int)p->kernel, a, b, n, p->batch, p->perm_s, (T*)p->src_s, st);
+        launch_permute3<T>(a, n, p->batch, p->perm_r, (T*)p->src_ra, st);
+        if (p->kernel == FSE_STRESSLET) launch_permute3<T>(b, n, p->batch, p->perm_r, (T*)p->src_rb, st);
+    }
     fourier_chain<T>(p, (const T*)p->src_s, (T*)p->phi);
     p->forward_valid = true;
     if (combined) {
-        launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_real, st);
-        launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, p->batch,
-                       p->prm.xi, self_coef(p), u_real, 1, st);
+        { TimedStage ts(tm, ST_GATHER, st); launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_real, st); }
+        { TimedStage ts(tm, ST_REAL, st);
+          launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, p->batch,
+                         p->prm.xi, self_coef(p), u_real, 1, st); }
     } else {
-        if (u_four) launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_four, st);
-        if (u_real)
+        if (u_four) { TimedStage ts(tm, ST_GATHER, st); launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_four, st); }
+        if (u_real) {
+            TimedStage ts(tm, ST_REAL, st);
             launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, p->batch,
                            p->prm.xi, self_coef(p), u_real, 0, st);
+        }
     }
     LAUNCHCHK();
     return FSE_OK;
@@ -436,24 +501,36 @@ fse_status_t adjoint_t(fse_plan* p, const T* f, const T* w, T* dsrc, T* dx, int 
     hipStream_t st = p->stream;
     const int64_t n = p->n;
     PointsDev<T> pd = points<T>(p);
+    Timer& tm = p->timer;
     // f in spread and real-space order (also needed when the forward field is reused)
-    launch_permute_sources<T>((int)p->kernel, f, nullptr, n, p->batch, p->perm_s, (T*)p->src_s, st);
-    launch_permute3<T>(f, n, p->batch, p->perm_r, (T*)p->src_ra, st);
+    {
+        TimedStage ts(tm, ST_PERMUTE, st);
+        launch_permute_sources<T>((int)p->kernel, f, nullptr, n, p->batch, p->perm_s, (T*)p->src_s, st);
+        launch_permute3<T>(f, n, p->batch, p->perm_r, (T*)p->src_ra, st);
+    }
     if (recompute || !p->forward_valid) {
         fourier_chain<T>(p, (const T*)p->src_s, (T*)p->phi);
         p->forward_valid = true;
     }
-    launch_permute3<T>(w, n, p->batch, p->perm_s, (T*)p->adj_s, st);
-    launch_permute3<T>(w, n, p->batch, p->perm_r, (T*)p->adj_r, st);
+    {
+        TimedStage ts(tm, ST_PERMUTE, st);
+        launch_permute3<T>(w, n, p->batch, p->perm_s, (T*)p->adj_s, st);
+        launch_permute3<T>(w, n, p->batch, p->perm_r, (T*)p->adj_r, st);
+    }
     fourier_chain<T>(p, (const T*)p->adj_s, (T*)p->phi_w);
-    launch_gather_grad<T>(p->gg, pd, (const T*)p->phi, (const T*)p->phi_w, (const T*)p->src_s,
-                          (const T*)p->adj_s, p->batch, dsrc, dx, st);
-    if (dsrc)
+    { TimedStage ts(tm, ST_GGRAD, st);
+      launch_gather_grad<T>(p->gg, pd, (const T*)p->phi, (const T*)p->phi_w, (const T*)p->src_s,
+                            (const T*)p->adj_s, p->batch, dsrc, dx, st); }
+    if (dsrc) {
+        TimedStage ts(tm, ST_REAL, st);
         launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->adj_r, nullptr, p->batch, p->prm.xi,
                        self_coef(p), dsrc, 1, st);
-    if (dx)
+    }
+    if (dx) {
+        TimedStage ts(tm, ST_RGRAD, st);
         launch_real_grad<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->adj_r, p->batch,
                             p->prm.xi, dx, st);
+    }
     LAUNCHCHK();
     return FSE_OK;
 }
@@ -606,6 +683,34 @@ fse_status_t fse_plan_grid(fse_plan_t* plan, int32_t which, double* out) {
         for (size_t i = 0; i < cnt; ++i) out[i] = tmp[i];
     }
     return FSE_OK;
+}
+
+fse_status_t fse_plan_set_timing(fse_plan_t* plan, int32_t enable) {
+    if (!plan) { set_err("null plan"); return FSE_EINVAL; }
+    plan->timer.on = enable != 0;
+    return FSE_OK;
+}
+
+fse_status_t fse_plan_timings(fse_plan_t* plan, double* ms, int64_t* launches) {
+    if (!plan || !ms) { set_err("null argument"); return FSE_EINVAL; }
+    HIPCHK(hipStreamSynchronize(plan->stream));
+    for (int s = 0; s < FSE_NSTAGES; ++s) {
+        ms[s] = 0.0;
+        if (launches) launches[s] = 0;
+    }
+    for (auto& r : plan->timer.recs) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.stage] += t;
+        if (launches) launches[r.stage] += 1;
+    }
+    plan->timer.recs.clear();
+    plan->timer.used = 0;
+    return FSE_OK;
+}
+
+const char* fse_stage_name(int32_t stage) {
+    return (stage >= 0 && stage < FSE_NSTAGES) ? STAGE_NAMES[stage] : "unknown";
 }
 
 fse_status_t fse_plan_workspace(const fse_plan_t* plan, size_t* bytes) {

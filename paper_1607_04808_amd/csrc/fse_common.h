@@ -142,14 +142,16 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
 
 template <typename T>
 void launch_fft_forward(const FftGeo& fg, const GridGeo& g, const T* grid, void* A, void* B,
-                        int ncomp, const T* tw, const int* rev, const int* revinv, hipStream_t st);
+                        int ncomp, const T* tw, const int* rev, const int* revinv, hipStream_t st,
+                        int passes = 3);  // bit 0: x pass, bit 1: y pass
 template <typename T>
 void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* B, int c_in, int batch,
                        const T* sig, double kscale, const T* tw, const int* rev, const int* revinv,
                        hipStream_t st);
 template <typename T>
 void launch_fft_inverse(const FftGeo& fg, const GridGeo& g, void* B, void* A, T* field, int c_in,
-                        int batch, const T* tw, const int* rev, const int* revinv, hipStream_t st);
+                        int batch, const T* tw, const int* rev, const int* revinv, hipStream_t st,
+                        int passes = 3);  // bit 0: inverse y pass, bit 1: inverse x pass
 
 template <typename T>
 void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* src_a_r,

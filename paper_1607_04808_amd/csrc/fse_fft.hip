@@ -475,21 +475,25 @@ template <typename K> void set_lds(K kern, size_t bytes) {
 
 template <typename T>
 void launch_fft_forward(const FftGeo& fg, const GridGeo& g, const T* grid, void* Av, void* Bv, int ncomp,
-                        const T* tw, const int* rev, const int* revinv, hipStream_t st) {
+                        const T* tw, const int* rev, const int* revinv, hipStream_t st, int passes) {
     using V = C2<T>;
     (void)rev;
     const int Mt = g.Mt, n = fg.n;
     constexpr int R = xrows<T>(), LZ = ylines<T>();
     V* A = (V*)Av;
     V* B = (V*)Bv;
-    size_t shx = sizeof(V) * (size_t)n * (1 + R / 2) + sizeof(int) * n;
-    set_lds(k_fft_x<T, R>, shx);
-    hipLaunchKernelGGL((k_fft_x<T, R>), dim3((Mt + R - 1) / R, Mt, ncomp), dim3(256), shx, st, fg, Mt,
-                       grid, A, (const V*)tw, revinv);
-    size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
-    set_lds(k_fft_y<T, LZ>, shy);
-    hipLaunchKernelGGL((k_fft_y<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, ncomp), dim3(256), shy, st,
-                       fg, Mt, (const V*)A, B, (const V*)tw, revinv);
+    if (passes & 1) {
+        size_t shx = sizeof(V) * (size_t)n * (1 + R / 2) + sizeof(int) * n;
+        set_lds(k_fft_x<T, R>, shx);
+        hipLaunchKernelGGL((k_fft_x<T, R>), dim3((Mt + R - 1) / R, Mt, ncomp), dim3(256), shx, st, fg,
+                           Mt, grid, A, (const V*)tw, revinv);
+    }
+    if (passes & 2) {
+        size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
+        set_lds(k_fft_y<T, LZ>, shy);
+        hipLaunchKernelGGL((k_fft_y<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, ncomp), dim3(256), shy,
+                           st, fg, Mt, (const V*)A, B, (const V*)tw, revinv);
+    }
 }
 
 template <typename T>
@@ -519,30 +523,35 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
 
 template <typename T>
 void launch_fft_inverse(const FftGeo& fg, const GridGeo& g, void* Bv, void* Av, T* field, int c_in,
-                        int batch, const T* tw, const int* rev, const int* revinv, hipStream_t st) {
+                        int batch, const T* tw, const int* rev, const int* revinv, hipStream_t st,
+                        int passes) {
     using V = C2<T>;
     (void)rev;
     const int Mt = g.Mt, n = fg.n;
     constexpr int R = xrows<T>(), LZ = ylines<T>();
     V* A = (V*)Av;
     V* B = (V*)Bv;
-    size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
-    set_lds(k_fft_yinv<T, LZ>, shy);
-    hipLaunchKernelGGL((k_fft_yinv<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, 3 * batch), dim3(256), shy,
-                       st, fg, Mt, c_in, (const V*)B, A, (const V*)tw, revinv);
-    size_t shx = sizeof(V) * ((size_t)n * (1 + R / 2) + (size_t)R * (Mt + 1)) + sizeof(int) * n;
-    set_lds(k_fft_xinv<T, R>, shx);
-    hipLaunchKernelGGL((k_fft_xinv<T, R>), dim3((Mt + R - 1) / R, Mt, 3 * batch), dim3(256), shx, st, fg,
-                       Mt, c_in, (const V*)A, field, (const V*)tw, revinv);
+    if (passes & 1) {
+        size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
+        set_lds(k_fft_yinv<T, LZ>, shy);
+        hipLaunchKernelGGL((k_fft_yinv<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, 3 * batch), dim3(256),
+                           shy, st, fg, Mt, c_in, (const V*)B, A, (const V*)tw, revinv);
+    }
+    if (passes & 2) {
+        size_t shx = sizeof(V) * ((size_t)n * (1 + R / 2) + (size_t)R * (Mt + 1)) + sizeof(int) * n;
+        set_lds(k_fft_xinv<T, R>, shx);
+        hipLaunchKernelGGL((k_fft_xinv<T, R>), dim3((Mt + R - 1) / R, Mt, 3 * batch), dim3(256), shx, st,
+                           fg, Mt, c_in, (const V*)A, field, (const V*)tw, revinv);
+    }
 }
 
 #define INST(T)                                                                                      \
     template void launch_fft_forward<T>(const FftGeo&, const GridGeo&, const T*, void*, void*, int,  \
-                                        const T*, const int*, const int*, hipStream_t);              \
+                                        const T*, const int*, const int*, hipStream_t, int);         \
     template void launch_fft_zscale<T>(const FftGeo&, const GridGeo&, int, void*, int, int, const T*, \
                                        double, const T*, const int*, const int*, hipStream_t);       \
     template void launch_fft_inverse<T>(const FftGeo&, const GridGeo&, void*, void*, T*, int, int,   \
-                                        const T*, const int*, const int*, hipStream_t);
+                                        const T*, const int*, const int*, hipStream_t, int);
 INST(float)
 INST(double)
 #undef INST

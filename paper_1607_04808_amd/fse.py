@@ -22,7 +22,9 @@ STATUS = {0: "FSE_OK", 1: "FSE_EINVAL", 2: "FSE_ERANGE", 3: "FSE_ENOMEM", 4: "FS
           5: "FSE_EUNSUPPORTED", 6: "FSE_ESTATE"}
 EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set_stream",
            "fse_set_points", "fse_eval", "fse_eval_parts", "fse_eval_adjoint", "fse_plan_multiplier",
-           "fse_plan_workspace", "fse_plan_grid", "fse_plan_destroy", "fse_status_string", "fse_last_error")
+           "fse_plan_workspace", "fse_plan_grid", "fse_plan_set_timing", "fse_plan_timings",
+           "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error")
+NSTAGES = 12
 
 
 class FseError(RuntimeError):
@@ -71,13 +73,17 @@ def lib():
             L.fse_plan_multiplier.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
             L.fse_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
             L.fse_plan_grid.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+            L.fse_plan_set_timing.argtypes = [vp, i32]
+            L.fse_plan_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+            L.fse_stage_name.argtypes = [i32]
+            L.fse_stage_name.restype = ctypes.c_char_p
             L.fse_plan_destroy.argtypes = [vp]
             L.fse_plan_destroy.restype = None
             L.fse_status_string.argtypes = [ctypes.c_int]
             L.fse_status_string.restype = ctypes.c_char_p
             L.fse_last_error.restype = ctypes.c_char_p
             for name in EXPORTS:
-                if name not in ("fse_plan_destroy", "fse_status_string", "fse_last_error"):
+                if name not in ("fse_plan_destroy", "fse_status_string", "fse_last_error", "fse_stage_name"):
                     getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -251,6 +257,16 @@ class Plan:
         out = np.empty((self.batch, nc, Mt, Mt, Mt), dtype=np.float64)
         _check(lib().fse_plan_grid(self._h, int(which), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+    def set_timing(self, on=True):
+        _check(lib().fse_plan_set_timing(self._h, 1 if on else 0))
+
+    def timings(self):
+        """{stage: (total ms, launch groups)} since the last call (synchronises)."""
+        ms = (ctypes.c_double * NSTAGES)()
+        cnt = (ctypes.c_int64 * NSTAGES)()
+        _check(lib().fse_plan_timings(self._h, ms, cnt))
+        return {lib().fse_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NSTAGES)}
 
     def workspace_bytes(self):
         b = ctypes.c_size_t()

@@ -121,10 +121,12 @@ def test_stage_grids(kernel):
 
 
 CASES = [
-    # (n, xi, rc, M, P, Mt, L, lo)
-    (1500, 10.0, 0.32, 24, 10, 0, 1.0, (0.0, 0.0, 0.0)),
-    (777, 8.0, 0.45, 20, 13, 28, 1.3, (-0.5, 0.25, 2.0)),   # odd P, ragged n, radices 8,7
-    (2048, 12.0, 0.25, 30, 16, 45, 1.0, (0.0, 0.0, 0.0)),   # radices 5,3,3,2
+    # (n, xi, rc, M, P, Mt, L, lo); eta = xi^2 h^2 P / (C^2 pi) < 0.7 in every case, so
+    # the middle factor exp(-(1-eta) k^2/4xi^2) of the Gaussian splitting is a
+    # smoothing (eta > 1 turns it into a deconvolution that amplifies FP32 rounding)
+    (1500, 10.0, 0.32, 24, 10, 0, 1.0, (0.0, 0.0, 0.0)),    # eta 0.58, radices 7,5,2
+    (777, 6.0, 0.6, 20, 13, 42, 1.3, (-0.5, 0.25, 2.0)),    # eta 0.66, odd P, ragged n, radices 7,4,3
+    (2048, 10.0, 0.3, 30, 16, 60, 1.0, (0.0, 0.0, 0.0)),    # eta 0.59, padded grid, radices 8,5,3
 ]
 
 
