@@ -11,7 +11,7 @@
  * stresslet T_jlm = -6 r_j r_l r_m / r^5 acting on f_lm = n_l q_m
  * (eq. def_stresslet, Section 2) or the rotlet Omega_jl = eps_jlm r_m / r^3
  * (eq. def_rotlet).  All points lie in the cube [box_lo, box_lo + L)^3
- * (Section 6.2, Section 7).
+ * (Section 5.2, Section 8).
  *
  * Conventions shared by every entry point:
  *   - Array pointers are DEVICE pointers (HIP global memory) owned by the
@@ -49,9 +49,9 @@ typedef enum {
 } fse_status_t;
 
 /*
- * Method parameters (Section 8 "Parameter selection"): the Ewald parameter
- * xi, the real-space cutoff rc (Section 5), the number of grid intervals M on
- * the box side (h = L/M) and the Gaussian support P (P^3 window, Section 6.2).
+ * Method parameters (Section 8.2 "Parameter selection"): the Ewald parameter
+ * xi, the real-space cutoff rc (Section 6), the number of grid intervals M on
+ * the box side (h = L/M) and the Gaussian support P (P^3 window, Section 5.2).
  */
 typedef struct {
     double xi;           /* Ewald split parameter, > 0                          */
@@ -61,13 +61,13 @@ typedef struct {
     double box_lo[3];    /* lower corner of the cube holding all points         */
     double L;            /* side of the cube, > 0                               */
     int32_t deltaL_rule; /* 0: deltaL = d = hP (Results section);
-                            1: deltaL from eq. deltaL_cond (Section 6.3)        */
+                            1: deltaL from eq. deltaL_cond (Section 5.3)        */
     int32_t Mt;          /* 0: the smallest grid size >= M + deltaL/h whose
                             doubled size 2*Mt factors into 2,3,5,7;
                             > 0: use this size (must be >= that minimum and
                             2*Mt must factor into 2,3,5,7)                      */
     double C;            /* Gaussian shape constant of m = C sqrt(pi P);
-                            0 selects 0.976 (Section 6.3)                       */
+                            0 selects 0.976 (Section 5.3)                       */
 } fse_params_t;
 
 /*
@@ -115,8 +115,8 @@ fse_status_t fse_plan_set_stream(fse_plan_t *plan, void *stream);
 
 /*
  * Set the n (2 <= n <= nmax) points x (device, (n,3), plan dtype): bins them
- * by grid tile (for spreading and quadrature, Section 6.2) and by real-space
- * cell (Section 5's cell list), computes each point's Gaussian window start
+ * by grid tile (for spreading and quadrature, Section 5.2) and by real-space
+ * cell (Section 6's cell list), computes each point's Gaussian window start
  * and offset in FP64, and keeps sorted copies.  Points outside the box are
  * clamped into it on the device, so no kernel ever leaves its buffers.
  * validate != 0: also synchronises the stream and returns FSE_ERANGE if any
@@ -126,7 +126,7 @@ fse_status_t fse_plan_set_stream(fse_plan_t *plan, void *stream);
 fse_status_t fse_set_points(fse_plan_t *plan, int64_t n, const void *x, int32_t validate);
 
 /*
- * u = u^R + u^F + u^self at the n points (Section 7): src_a is f (stokeslet,
+ * u = u^R + u^F + u^self at the n points (Section 8): src_a is f (stokeslet,
  * rotlet) or q (stresslet), src_b is NULL or the normals n (stresslet), both
  * (batch, n, 3); u is (batch, n, 3) and is overwritten.  The scaled,
  * inverse-transformed grid of this call is kept for fse_eval_adjoint.
@@ -135,8 +135,8 @@ fse_status_t fse_eval(fse_plan_t *plan, const void *src_a, const void *src_b, vo
 
 /*
  * The two parts separately (for tests): u_real = u^R + u^self (the truncated
- * real-space sum of Section 5 plus the stokeslet self term, eq. Slimit) and
- * u_fourier = u^F (the five steps of Section 6.2).  Either may be NULL.
+ * real-space sum of Section 6 plus the stokeslet self term, eq. Slimit) and
+ * u_fourier = u^F (the five steps of Section 5.2).  Either may be NULL.
  */
 fse_status_t fse_eval_parts(fse_plan_t *plan, const void *src_a, const void *src_b, void *u_real,
                             void *u_fourier);
@@ -161,7 +161,7 @@ fse_status_t fse_plan_multiplier(fse_plan_t *plan, double *out);
 
 /* Copy, for tests, the grid of the last evaluation to host memory `out` as
  * FP64, layout (batch, components, z, y, x) with x fastest, Mt^3 per
- * component: which = 0 the spread sources (step 1 of Section 6.2, without the
+ * component: which = 0 the spread sources (step 1 of Section 5.2, without the
  * Gaussian normalisation), which = 1 the scaled inverse-transformed grid that
  * the quadrature reads (step 4).  Synchronises. */
 fse_status_t fse_plan_grid(fse_plan_t *plan, int32_t which, double *out);

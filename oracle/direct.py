@@ -98,7 +98,7 @@ def direct(kernel, x, a, b=None, targets=None, y=None):
 
 
 def real_trunc(kernel, xi, rc, x, a, b=None, targets=None, y=None):
-    """Real-space sum over 0 < |r| <= rc (Section 5), FP64 brute force."""
+    """Real-space sum over 0 < |r| <= rc (Section 6), FP64 brute force."""
     x, a, b = _c(x), _c(a), _c(b)
     yy, skip = _targets(x, targets, y)
     out = np.zeros((len(yy), 3))

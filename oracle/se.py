@@ -8,21 +8,21 @@ use this module.  Library primitives used as steps: numpy's FFT.
 Steps (paper section -> function):
   Section 4.3 "Precomputation"        mollified_kernel()  (IFFT on M_g^3, crop to
                                        (2 Mt)^3 centred, FFT)
-  Section 6.2 "Discretization", step 1 spread()            (eq. Hx, truncated
-                                       Gaussians on a P^3 cube, Section 6.2 FGG)
+  Section 5.2 "Discretization", step 1 spread()            (eq. Hx, truncated
+                                       Gaussians on a P^3 cube, Section 5.2 FGG)
   step 2 FFT, zero-padded to (2 Mt)^3  fourier_step()
   step 3 scaling by eq. gridfcnsc with eqs. AS/AT/AR (truncated B or H)
   step 4 IFFT and truncation to Mt^3
   step 5 quadrature (eq. u_integr)     gather()
-  Section 5 real-space sum             direct.real_trunc()
+  Section 6 real-space sum             direct.real_trunc()
   eq. Slimit self term                 self_term()
-  Section 8 parameter choices          geometry()
+  Section 8.2 parameter choices          geometry()
 
 Readings of the paper taken here (all listed with their pins in the design doc):
   * grid: nodes x0 + j h, j = 0..Mt-1, x0 = box_lo - (Lt - L)/2 (the extended
-    domain of Section 6.2 centred on the box), h = L/M, Lt = Mt h.
+    domain of Section 5.2 centred on the box), h = L/M, Lt = Mt h.
   * window: P consecutive nodes per dimension starting at
-    b = floor(t - P/2 + 1), t = (x - x0)/h, computed in FP64 (Section 6.2 FGG).
+    b = floor(t - P/2 + 1), t = (x - x0)/h, computed in FP64 (Section 5.2 FGG).
   * Fourier convention: forward transform e^{-i k.x}, inverse e^{+i k.x}
     (Section 3.1), so derivatives map to +ik.  The stresslet and rotlet
     multipliers of eqs. AT and AR are used with that convention; the rotlet is
@@ -44,7 +44,7 @@ import numpy as np
 
 from . import direct
 
-C_GAUSS = 0.976  # the constant C of m = C sqrt(pi P), Section 6.3
+C_GAUSS = 0.976  # the constant C of m = C sqrt(pi P), Section 5.3
 KERNELS = ("stokeslet", "stresslet", "rotlet")
 
 
@@ -201,7 +201,7 @@ def mollified_kernel(family, g: Geometry, return_imag=False):
 
 
 # ---------------------------------------------------------------------------
-# Section 6.2: spreading and quadrature with truncated Gaussians
+# Section 5.2: spreading and quadrature with truncated Gaussians
 # ---------------------------------------------------------------------------
 
 def window(x, g: Geometry):
@@ -273,7 +273,7 @@ def gather(grid, x, g: Geometry, chunk=2048):
 
 
 # ---------------------------------------------------------------------------
-# Section 6.2 steps 2-4: FFT, scaling (eq. gridfcnsc), IFFT
+# Section 5.2 steps 2-4: FFT, scaling (eq. gridfcnsc), IFFT
 # ---------------------------------------------------------------------------
 
 def wavevectors(g: Geometry):
@@ -285,7 +285,7 @@ def wavevectors(g: Geometry):
 
 
 def fourier_step(kernel, grid, g: Geometry, Kt):
-    """Steps 2-4 of Section 6.2 for one source set.
+    """Steps 2-4 of Section 5.2 for one source set.
 
     grid: (c, Mt, Mt, Mt) real, c = 3 (stokeslet, rotlet: f_l) or 9 (stresslet:
     f_lm = n_l q_m at index 3l + m).  Kt: mollified kernel (Bt or Ht) on the
@@ -350,7 +350,7 @@ def fourier_part(kernel, x, a, b, g: Geometry, Kt=None, return_field=False):
 
 
 def evaluate(kernel, x, a, b=None, g: Geometry | None = None, Kt=None, **geo):
-    """Full FSE sum at the sources: u = u^R + u^F + u^self (Section 7)."""
+    """Full FSE sum at the sources: u = u^R + u^F + u^self (Section 8)."""
     if g is None:
         g = geometry(**geo)
     uR = direct.real_trunc(kernel, g.xi, g.rc, x, a, b)

@@ -1,6 +1,6 @@
 // Binning of the points (integer work): Gaussian-window starts and offsets in
-// FP64 (the P^3 windows of the fast Gaussian gridding, Section 6.2), counting
-// sort by spreading tile and by real-space cell (the cell list of Section 5).
+// FP64 (the P^3 windows of the fast Gaussian gridding, Section 5.2), counting
+// sort by spreading tile and by real-space cell (the cell list of Section 6).
 #include "fse_common.h"
 
 namespace fse {

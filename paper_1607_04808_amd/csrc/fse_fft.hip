@@ -1,4 +1,4 @@
-// Zero-padded 3D FFT, scaling and inverse FFT (Section 6.2, steps 2-4).
+// Zero-padded 3D FFT, scaling and inverse FFT (Section 5.2, steps 2-4).
 //
 // The (2Mt)^3 transform of an Mt^3 real grid is done as three pruned passes of
 // 1D transforms staged in LDS, each pass writing its output transposed so the
@@ -12,7 +12,7 @@
 //           transform, keep z < Mt.  The spectrum never reaches HBM.
 //   y-inv   B -> A (keep y < Mt),  x-inv  A -> field[c][z][y][x] (C2R, keep x < Mt).
 // Only the Mt nonzero input lines are read and only the Mt kept output lines are
-// written per direction (the zero padding and the truncation of Section 6.2).
+// written per direction (the zero padding and the truncation of Section 5.2).
 //
 // 1D transforms: in-place mixed-radix (2,3,4,5,7,8) decimation in frequency,
 // leaving the spectrum in digit-reversed order; the inverse is the matching

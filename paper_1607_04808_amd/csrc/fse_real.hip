@@ -1,4 +1,4 @@
-// Real-space part (Section 5): u^R(x_m) = sum_{0 < |x_m - x_n| <= rc} G^R(x_m - x_n) . f_n
+// Real-space part (Section 6): u^R(x_m) = sum_{0 < |x_m - x_n| <= rc} G^R(x_m - x_n) . f_n
 // over a cell list of cells with side >= rc (27 neighbour cells), plus the
 // stokeslet self term -4 xi/sqrt(pi) f_m (eq. Slimit).
 //

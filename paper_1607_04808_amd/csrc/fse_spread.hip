@@ -1,4 +1,4 @@
-// Gaussian gridding (Section 6.2): step 1 "spreading" (eq. Hx) and step 5
+// Gaussian gridding (Section 5.2): step 1 "spreading" (eq. Hx) and step 5
 // "quadrature" (eq. u_integr, trapezoidal rule), with Gaussians truncated to a
 // P^3 cube of grid points (fast Gaussian gridding).  The weights here are the
 // raw factors exp(-alpha |x_node - x|^2) = prod_d exp(-alpha h^2 (t_d - i_d)^2);

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the oracle, element by element.
 
 Tolerances (relative to the largest component of the reference, the max-norm
-of Section 8's "relative error" reading):
+of the Results section's "relative error" reading):
   FP64: the HIP path and the oracle run the same steps (same windows, same
         mollified kernel, same multipliers); only summation order and the FFT
         algorithm differ, so they agree to ~1e-13; 1e-10 is asserted.

@@ -23,7 +23,7 @@ def _src(kernel, n, seed, uniform=False):
 
 
 def test_geometry_relations():
-    """h = L/M, d = hP, m = C sqrt(pi P), eta = (xi d/m)^2 (Section 6.3); Mt = M + P
+    """h = L/M, d = hP, m = C sqrt(pi P), eta = (xi d/m)^2 (Section 5.3); Mt = M + P
     for deltaL = d; M_g even and above (1 + sqrt 3) Mt; R = sqrt(3) Lt."""
     g = se.geometry(xi=7.0, rc=0.63, M=48, P=16, L=2.0)
     assert g.h == 2.0 / 48 and g.Mt == 64 and g.Lt == pytest.approx(64 * 2.0 / 48)
@@ -50,7 +50,7 @@ def test_window_inside_grid_at_box_corners():
 
 def test_spread_gaussian_mass():
     """h^3 sum_p of one spread Gaussian is 1 up to the truncation at the P^3 cube
-    (eq. Hx normalisation; Section 6.3 truncation level e^{-m^2/2})."""
+    (eq. Hx normalisation; Section 5.3 truncation level e^{-m^2/2})."""
     for P in (8, 16, 24):
         g = se.geometry(xi=10.0, rc=0.3, M=32, P=P, L=1.0)
         x = W.uniform_cube(5, 40)
@@ -188,7 +188,7 @@ def test_real_error_tracks_estimate(kernel):
 
 def test_deltaL_rule_decouples_errors():
     """With Mt larger than needed, deltaL = d leaves an error floor that eq. deltaL_cond
-    removes (Section 6.3, Fig. P_errors)."""
+    removes (Section 5.3, Fig. P_errors)."""
     x = W.uniform_cube(200, 66)
     f = W.normal_strengths(200, 67)
     ref = direct.fourier_dir("stokeslet", 6.0, x, f)
