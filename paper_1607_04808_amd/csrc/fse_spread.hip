@@ -5,11 +5,20 @@
 // the normalisations (alpha/pi)^{3/2} of both steps and the quadrature weight
 // h^3 are folded into the precomputed Fourier multiplier.
 //
-// Spreading: one workgroup owns a TS^3 tile of grid nodes and accumulates in
-// LDS the contributions of every point whose window overlaps the tile (points
-// binned by the tile of their window start, so at most (1+ceil((P-1)/TS))^3
-// source tiles are visited).  Each node is written exactly once, coalesced, by
-// its owner: no global atomics and no clearing of the grid.
+// Points are binned by the bin (TB^3 nodes, TB = GridGeo::TS) holding their
+// window start, x-fastest bin order, so a row of bins is one contiguous range.
+//
+// Spreading: one workgroup owns a TC^3 core of grid nodes (TC = 2 TB) and
+// accumulates in LDS the clipped windows of every point whose window reaches
+// the core.  Candidate points are staged in LDS in chunks (coalesced loads)
+// and compacted to those that overlap; each wave then takes one point with its
+// lanes laid along x, so consecutive lanes hit consecutive LDS banks.  Every
+// node is written exactly once, coalesced, by its owner: no global atomics and
+// no clearing of the grid.
+//
+// Quadrature: one workgroup per bin stages the (TB+P-1)^3 block of the field
+// that the bin's windows cover in LDS (when it fits) and each wave reduces one
+// point at a time from LDS; otherwise the field is read from global memory.
 #include "fse_common.h"
 
 namespace fse {
@@ -20,86 +29,268 @@ template <typename T> __device__ __forceinline__ T dexp(T x);
 template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 
-template <typename T, int NC, int TS>
+// floor(a / b) for 0 <= a < 2^12 and 1 <= b <= 64 via a float reciprocal: a/b is
+// never within 1/(2b) of an integer above it, far above the rounding error.
+__device__ __forceinline__ int small_div(int a, int b) {
+    return (int)(((float)a + 0.5f) * __frcp_rn((float)b));
+}
+
+constexpr int CH = 256;  // candidate points staged per chunk
+
+template <typename T, int NC, int TB>
 __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict__ tile_start,
                                                const int* __restrict__ bpack_s,
                                                const T* __restrict__ coff_s,
                                                const T* __restrict__ src_s, int64_t n, T* grid) {
-    constexpr int TS3 = TS * TS * TS;
-    __shared__ T acc[NC * TS3];
-    const int nt = g.nt, Mt = g.Mt, P = g.P;
+    constexpr int TC = 2 * TB;
+    constexpr int TC3 = TC * TC * TC;
+    __shared__ T acc[NC * TC3];
+    __shared__ int s_bp[CH];
+    __shared__ T s_c[CH * 3];
+    __shared__ T s_v[CH * NC];
+    __shared__ T s_w[4][2][32];
+    __shared__ int s_cnt;
+
+    const int Mt = g.Mt, P = g.P, nb = g.nt;
+    const int ncore = (Mt + TC - 1) / TC;
     const int t = blockIdx.x;
-    const int tx = t % nt, ty = (t / nt) % nt, tz = t / (nt * nt);
+    const int cx = t % ncore, cy = (t / ncore) % ncore, cz = t / (ncore * ncore);
     const int bm = blockIdx.y;
-    const int lox = tx * TS, loy = ty * TS, loz = tz * TS;
-    for (int q = threadIdx.x; q < NC * TS3; q += 256) acc[q] = (T)0;
-    __syncthreads();
+    const int lox = cx * TC, loy = cy * TC, loz = cz * TC;
+    for (int q = threadIdx.x; q < NC * TC3; q += 256) acc[q] = (T)0;
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const T ahh = (T)g.ahh;
     const T half = (T)(0.5 * (P - 1));
-    const int kspan = (P - 1 + TS - 1) / TS;
-    for (int sz = max(0, tz - kspan); sz <= tz; ++sz)
-        for (int sy = max(0, ty - kspan); sy <= ty; ++sy)
-            for (int sx = max(0, tx - kspan); sx <= tx; ++sx) {
-                const int s = (sz * nt + sy) * nt + sx;
-                const int j0 = tile_start[s], j1 = tile_start[s + 1];
-                for (int j = j0 + wid; j < j1; j += 4) {
+    // bins whose window starts can reach the core: b in [lo - P + 1, lo + TC - 1] ∩ [0, Mt - P]
+    auto brange = [&](int lo, int& s0, int& s1) {
+        s0 = max(0, lo - P + 1) / TB;
+        s1 = min(Mt - P, lo + TC - 1) / TB;
+    };
+    int bx0, bx1, by0, by1, bz0, bz1;
+    brange(lox, bx0, bx1);
+    brange(loy, by0, by1);
+    brange(loz, bz0, bz1);
+    for (int sz = bz0; sz <= bz1; ++sz)
+        for (int sy = by0; sy <= by1; ++sy) {
+            const int row = (sz * nb + sy) * nb;
+            const int j0 = tile_start[row + bx0], j1 = tile_start[row + bx1 + 1];
+            for (int base = j0; base < j1; base += CH) {
+                if (threadIdx.x == 0) s_cnt = 0;
+                __syncthreads();
+                const int j = base + (int)threadIdx.x;
+                if (j < j1) {
                     const int bp = bpack_s[j];
                     const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-                    const int x0 = max(bx, lox), x1 = min(bx + P, lox + TS);
-                    const int y0 = max(by, loy), y1 = min(by + P, loy + TS);
-                    const int z0 = max(bz, loz), z1 = min(bz + P, loz + TS);
-                    if (x0 >= x1 || y0 >= y1 || z0 >= z1) continue;
-                    const T cx = coff_s[3 * (int64_t)j], cy = coff_s[3 * (int64_t)j + 1],
-                            cz = coff_s[3 * (int64_t)j + 2];
-                    // lane l holds the weight of window offset l in each dimension
-                    const T ex = cx + half - (T)lane, ey = cy + half - (T)lane, ez = cz + half - (T)lane;
-                    const T wx = dexp<T>(-ahh * ex * ex);
-                    const T wy = dexp<T>(-ahh * ey * ey);
-                    const T wz = dexp<T>(-ahh * ez * ez);
-                    T wxs[TS];
+                    const bool ov = bx < lox + TC && bx + P > lox && by < loy + TC && by + P > loy &&
+                                    bz < loz + TC && bz + P > loz;
+                    if (ov) {
+                        const int k = atomicAdd(&s_cnt, 1);
+                        s_bp[k] = bp;
+                        s_c[3 * k] = coff_s[3 * (int64_t)j];
+                        s_c[3 * k + 1] = coff_s[3 * (int64_t)j + 1];
+                        s_c[3 * k + 2] = coff_s[3 * (int64_t)j + 2];
 #pragma unroll
-                    for (int k = 0; k < TS; ++k) wxs[k] = readlane(wx, min(x0 - bx + k, 63));
+                        for (int c = 0; c < NC; ++c) s_v[NC * k + c] = src_s[((int64_t)bm * n + j) * NC + c];
+                    }
+                }
+                __syncthreads();
+                const int cnt = s_cnt;
+                for (int k = wid; k < cnt; k += 4) {
+                    const int bp = s_bp[k];
+                    const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
+                    const int x0 = max(bx, lox), x1 = min(bx + P, lox + TC);
+                    const int y0 = max(by, loy), y1 = min(by + P, loy + TC);
+                    const int z0 = max(bz, loz), z1 = min(bz + P, loz + TC);
+                    const int nx = x1 - x0, ny = y1 - y0, nz = z1 - z0;
+                    const int R = 64 / nx;
+                    const int rr = small_div(lane, nx);
+                    const int ix = lane - rr * nx;
+                    const T ex = s_c[3 * k] + half - (T)(x0 - bx + ix);
+                    const T wx = dexp<T>(-ahh * ex * ex);
+                    if (lane < ny) {
+                        const T e = s_c[3 * k + 1] + half - (T)(y0 - by + lane);
+                        s_w[wid][0][lane] = dexp<T>(-ahh * e * e);
+                    } else if (lane >= 32 && lane - 32 < nz) {
+                        const T e = s_c[3 * k + 2] + half - (T)(z0 - bz + lane - 32);
+                        s_w[wid][1][lane - 32] = dexp<T>(-ahh * e * e);
+                    }
+                    wave_lds_sync();
                     T v[NC];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) v[c] = src_s[((int64_t)bm * n + j) * NC + c];
-                    const int nx = x1 - x0, ny = y1 - y0, nyz = ny * (z1 - z0);
-                    const int xoff = x0 - lox;
-                    for (int qb = 0; qb < nyz; qb += 64) {
-                        const int q = qb + lane;
-                        const bool act = q < nyz;
-                        const int qq = act ? q : 0;
-                        const int iy = y0 + qq % ny, iz = z0 + qq / ny;
-                        const T wyz = __shfl(wy, iy - by, 64) * __shfl(wz, iz - bz, 64);
-                        if (act) {
-                            T* a = acc + ((iz - loz) * TS + (iy - loy)) * TS + xoff;
+                    for (int c = 0; c < NC; ++c) v[c] = s_v[NC * k + c];
+                    const int nrows = ny * nz;
+                    if (rr < R) {
+                        int iz = small_div(rr, ny);
+                        int iy = rr - iz * ny;
+                        T* a0 = acc + ((z0 - loz) * TC + (y0 - loy)) * TC + (x0 - lox) + ix;
+                        for (int q = rr; q < nrows; q += R) {
+                            const T w = wx * s_w[wid][0][iy] * s_w[wid][1][iz];
+                            T* a = a0 + (iz * TC + iy) * TC;
 #pragma unroll
-                            for (int k = 0; k < TS; ++k) {
-                                if (k < nx) {
-                                    const T w = wxs[k] * wyz;
-#pragma unroll
-                                    for (int c = 0; c < NC; ++c) atomicAdd(a + c * TS3 + k, w * v[c]);
-                                }
+                            for (int c = 0; c < NC; ++c) atomicAdd(a + c * TC3, w * v[c]);
+                            iy += R;
+                            while (iy >= ny) {
+                                iy -= ny;
+                                ++iz;
                             }
                         }
                     }
+                    wave_lds_sync();
                 }
+                __syncthreads();
             }
+        }
     __syncthreads();
     const int64_t M3 = (int64_t)Mt * Mt * Mt;
-    for (int q = threadIdx.x; q < TS3; q += 256) {
-        const int lx = q % TS, ly = (q / TS) % TS, lz = q / (TS * TS);
+    for (int q = threadIdx.x; q < TC3; q += 256) {
+        const int lx = q % TC, ly = (q / TC) % TC, lz = q / (TC * TC);
         const int gx = lox + lx, gy = loy + ly, gz = loz + lz;
         if (gx < Mt && gy < Mt && gz < Mt) {
             const int64_t o = ((int64_t)gz * Mt + gy) * Mt + gx;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[c * TS3 + q];
+            for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[c * TC3 + q];
         }
     }
 }
 
-// Quadrature: one wave per point, LPR lanes along x per window row.
+// ---------------------------------------------------------------------------
+// Quadrature with the bin's field block staged in LDS.  MODE 0: value gather
+// u = sum g(x - x_p) F(p) (3 components).  MODE 1: gradient part with the
+// forward field, dx = sum grad g (w . phi_f).  MODE 2: value of phi_w into
+// dsrc and dx += sum grad g (f . phi_w).
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(512) void k_gather_lds(GridGeo g, const int* __restrict__ tile_start,
+                                                   const int* __restrict__ perm_s,
+                                                   const int* __restrict__ bpack_s,
+                                                   const T* __restrict__ coff_s,
+                                                   const T* __restrict__ field, const T* __restrict__ vec_s,
+                                                   int64_t n, int batch, T* out, T* dx) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = (T*)smem_raw;
+    __shared__ T s_w[8][4][32];
+    const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
+    const int E = TB + P - 1;
+    const int E3 = E * E * E;
+    const int64_t M3 = (int64_t)Mt * Mt * Mt;
+    const int s = blockIdx.x;
+    const int j0 = tile_start[s], j1 = tile_start[s + 1];
+    if (j0 == j1) return;
+    const int tbx = s % nb, tby = (s / nb) % nb, tbz = s / (nb * nb);
+    const int lox = tbx * TB, loy = tby * TB, loz = tbz * TB;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const T ahh = (T)g.ahh;
+    const T dfac = (T)(-2.0 * g.ahh / g.h);
+    const T half = (T)(0.5 * (P - 1));
+    const int R = 64 / P;
+    const int rr = small_div(lane, P);
+    const int ix = lane - rr * P;
+    const int bm0 = MODE == 0 ? blockIdx.y : 0;
+    const int bm1 = MODE == 0 ? blockIdx.y + 1 : batch;
+    for (int bm = bm0; bm < bm1; ++bm) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < 3 * E3; q += blockDim.x) {
+            const int c = q / E3, r = q - c * E3;
+            const int x = r % E, y = (r / E) % E, z = r / (E * E);
+            const int gx = lox + x, gy = loy + y, gz = loz + z;
+            sm[q] = (gx < Mt && gy < Mt && gz < Mt)
+                        ? field[((int64_t)bm * 3 + c) * M3 + ((int64_t)gz * Mt + gy) * Mt + gx]
+                        : (T)0;
+        }
+        __syncthreads();
+        for (int j = j0 + wid; j < j1; j += nw) {
+            const int bp = bpack_s[j];
+            const int lbx = (bp & 1023) - lox, lby = ((bp >> 10) & 1023) - loy, lbz = (bp >> 20) - loz;
+            const T cx = coff_s[3 * (int64_t)j], cy = coff_s[3 * (int64_t)j + 1], cz = coff_s[3 * (int64_t)j + 2];
+            const T ex = cx + half - (T)ix;
+            const T wx = dexp<T>(-ahh * ex * ex);
+            const T dwx = dfac * ex * wx;
+            if (lane < P) {
+                const T ey = cy + half - (T)lane;
+                const T wy = dexp<T>(-ahh * ey * ey);
+                s_w[wid][0][lane] = wy;
+                s_w[wid][2][lane] = dfac * ey * wy;
+            } else if (lane >= 32 && lane - 32 < P) {
+                const T ez = cz + half - (T)(lane - 32);
+                const T wz = dexp<T>(-ahh * ez * ez);
+                s_w[wid][1][lane - 32] = wz;
+                s_w[wid][3][lane - 32] = dfac * ez * wz;
+            }
+            wave_lds_sync();
+            T v0 = 0, v1 = 0, v2 = 0;  // MODE 0/2 values
+            T g0 = 0, g1 = 0, g2 = 0;  // MODE 1/2 gradient
+            T p0 = 0, p1 = 0, p2 = 0;  // contraction vector
+            if (MODE != 0) {
+                const T* pv = vec_s + ((int64_t)bm * n + j) * 3;
+                p0 = pv[0];
+                p1 = pv[1];
+                p2 = pv[2];
+            }
+            if (rr < R) {
+                int iz = small_div(rr, P);
+                int iy = rr - iz * P;
+                const T* f0 = sm + (lbz * E + lby) * E + lbx + ix;
+                for (int q = rr; q < P * P; q += R) {
+                    const T* f = f0 + (iz * E + iy) * E;
+                    const T a0 = f[0], a1 = f[E3], a2 = f[2 * E3];
+                    const T wy = s_w[wid][0][iy], wz = s_w[wid][1][iz];
+                    if (MODE == 0) {
+                        const T w = wx * wy * wz;
+                        v0 += w * a0;
+                        v1 += w * a1;
+                        v2 += w * a2;
+                    } else {
+                        const T psi = p0 * a0 + p1 * a1 + p2 * a2;
+                        const T dwy = s_w[wid][2][iy], dwz = s_w[wid][3][iz];
+                        g0 += psi * dwx * wy * wz;
+                        g1 += psi * wx * dwy * wz;
+                        g2 += psi * wx * wy * dwz;
+                        if (MODE == 2) {
+                            const T w = wx * wy * wz;
+                            v0 += w * a0;
+                            v1 += w * a1;
+                            v2 += w * a2;
+                        }
+                    }
+                    iy += R;
+                    while (iy >= P) {
+                        iy -= P;
+                        ++iz;
+                    }
+                }
+            }
+            const int64_t i = perm_s[j];
+            if (MODE != 1) {
+                v0 = wave_sum(v0);
+                v1 = wave_sum(v1);
+                v2 = wave_sum(v2);
+                if (lane == 0 && out) {
+                    T* o = out + ((int64_t)bm * n + i) * 3;
+                    o[0] = v0;
+                    o[1] = v1;
+                    o[2] = v2;
+                }
+            }
+            if (MODE != 0) {
+                g0 = wave_sum(g0);
+                g1 = wave_sum(g1);
+                g2 = wave_sum(g2);
+                if (lane == 0 && dx) {
+                    // the first contribution (forward field, first batch member) overwrites
+                    const bool first = (MODE == 1 && bm == 0);
+                    dx[3 * i] = (first ? (T)0 : dx[3 * i]) + g0;
+                    dx[3 * i + 1] = (first ? (T)0 : dx[3 * i + 1]) + g1;
+                    dx[3 * i + 2] = (first ? (T)0 : dx[3 * i + 2]) + g2;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+// Quadrature reading the field from global memory (large P or FP64 blocks that
+// do not fit in LDS): one wave per point, LPR lanes along x per window row.
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_gather(GridGeo g, const int* __restrict__ tile_start,
                                                const int* __restrict__ perm_s,
@@ -135,6 +326,7 @@ __global__ __launch_bounds__(256) void k_gather(GridGeo g, const int* __restrict
             for (int iz = 0; iz < P; ++iz) {
                 const T wz = wx * wsh[wid][1][iz];
                 const T* fz = fb + (int64_t)iz * Mt * Mt;
+#pragma unroll 4
                 for (int iy = grp; iy < P; iy += NG) {
                     const T w = wz * wsh[wid][0][iy];
                     const T* f = fz + (int64_t)iy * Mt;
@@ -158,8 +350,8 @@ __global__ __launch_bounds__(256) void k_gather(GridGeo g, const int* __restrict
     }
 }
 
-// Adjoint quadrature.  For each point s and batch member b:
-//   dsrc_b(x_s) = quadrature of phi_w,b  (the value, as k_gather), and
+// Adjoint quadrature from global memory: for each point s and batch member b,
+//   dsrc_b(x_s) = quadrature of phi_w,b, and
 //   dx(x_s) += sum_p grad_x g(x_s - x_p) [w_b,s . phi_f,b(x_p) + f_b,s . phi_w,b(x_p)],
 // the derivative of the Gaussian windows of both the spreading and the
 // quadrature step (the discrete operator is symmetric for S and Omega).
@@ -182,7 +374,7 @@ __global__ __launch_bounds__(256) void k_gather_grad(GridGeo g, const int* __res
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int gx = lane % LPR, grp = lane / LPR;
     const T ahh = (T)g.ahh;
-    const T dfac = (T)(-2.0 * g.ahh / g.h);  // d/dx exp(-alpha h^2 e^2) = dfac * e * exp(...)
+    const T dfac = (T)(-2.0 * g.ahh / g.h);
     const T half = (T)(0.5 * (P - 1));
     for (int j = j0 + wid; j < j1; j += 4) {
         const int bp = bpack_s[j];
@@ -255,28 +447,47 @@ __global__ __launch_bounds__(256) void k_gather_grad(GridGeo g, const int* __res
     }
 }
 
-inline unsigned ntiles(const GridGeo& g) { return (unsigned)(g.nt * g.nt * g.nt); }
+inline unsigned nbins(const GridGeo& g) { return (unsigned)(g.nt * g.nt * g.nt); }
+
+// LDS bytes of the staged field block, or 0 if it does not fit
+template <typename T> size_t gather_lds_bytes(const GridGeo& g) {
+    const size_t E = (size_t)g.TS + g.P - 1;
+    const size_t b = 3 * E * E * E * sizeof(T);
+    return b <= 140 * 1024 ? b : 0;
+}
+
+template <typename K> void allow_lds(K kern) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
 
 }  // namespace
 
 template <typename T>
 void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int c_in, int batch,
                    T* grid, hipStream_t st) {
-    // tile side: 16 for FP32, 12 for FP64 (NC * TS^3 accumulators must fit in LDS)
-    constexpr int TS = sizeof(T) == 4 ? 16 : 12;
-    dim3 grd(ntiles(g), batch);
+    // bin side TB = g.TS; core side 2 TB: 16 for FP32, 12 for FP64
+    constexpr int TB = sizeof(T) == 4 ? 8 : 6;
+    const unsigned ncore = (unsigned)((g.Mt + 2 * TB - 1) / (2 * TB));
+    dim3 grd(ncore * ncore * ncore, batch);
     if (c_in == 3)
-        hipLaunchKernelGGL((k_spread<T, 3, TS>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,
+        hipLaunchKernelGGL((k_spread<T, 3, TB>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,
                            p.coff_s, src_s, p.n, grid);
     else
-        hipLaunchKernelGGL((k_spread<T, 6, TS>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,
+        hipLaunchKernelGGL((k_spread<T, 6, TB>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,
                            p.coff_s, src_s, p.n, grid);
 }
 
 template <typename T>
 void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int batch, T* u,
                    hipStream_t st) {
-    dim3 grd(ntiles(g), batch);
+    const size_t lds = gather_lds_bytes<T>(g);
+    if (lds) {
+        allow_lds(k_gather_lds<T, 0>);
+        hipLaunchKernelGGL((k_gather_lds<T, 0>), dim3(nbins(g), batch), dim3(512), lds, st, g, p.tile_start,
+                           p.perm_s, p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u, (T*)nullptr);
+        return;
+    }
+    dim3 grd(nbins(g), batch);
     if (g.P <= 16)
         hipLaunchKernelGGL((k_gather<T, 16>), grd, dim3(256), 0, st, g, p.tile_start, p.perm_s,
                            p.bpack_s, p.coff_s, field, p.n, u);
@@ -288,7 +499,18 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
 template <typename T>
 void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f, const T* phi_w,
                         const T* f_s, const T* w_s, int batch, T* dsrc, T* dx, hipStream_t st) {
-    dim3 grd(ntiles(g));
+    const size_t lds = gather_lds_bytes<T>(g);
+    if (lds && dx) {
+        // pass 1: forward field contracted with w; pass 2: phi_w value and contraction with f
+        allow_lds(k_gather_lds<T, 1>);
+        allow_lds(k_gather_lds<T, 2>);
+        hipLaunchKernelGGL((k_gather_lds<T, 1>), dim3(nbins(g)), dim3(512), lds, st, g, p.tile_start, p.perm_s,
+                           p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);
+        hipLaunchKernelGGL((k_gather_lds<T, 2>), dim3(nbins(g)), dim3(512), lds, st, g, p.tile_start, p.perm_s,
+                           p.bpack_s, p.coff_s, phi_w, f_s, p.n, batch, dsrc, dx);
+        return;
+    }
+    dim3 grd(nbins(g));
     if (g.P <= 16)
         hipLaunchKernelGGL((k_gather_grad<T, 16>), grd, dim3(256), 0, st, g, p.tile_start, p.perm_s,
                            p.bpack_s, p.coff_s, phi_f, phi_w, f_s, w_s, p.n, batch, dsrc, dx);
