@@ -460,15 +460,15 @@ __global__ __launch_bounds__(256) void k_fft_xinv(FftGeo fg, int Mt, int c_in,
 template <typename T> constexpr int xrows() { return sizeof(T) == 4 ? 16 : 8; }
 template <typename T> constexpr int ylines() { return sizeof(T) == 4 ? 16 : 8; }
 
-// Allow the dynamic LDS a pass needs (above the 64 KB default); once per kernel.
+// Raise a pass's dynamic-LDS limit to `bytes`; remembered per kernel.
 template <typename K> void set_lds(K kern, size_t bytes) {
     static std::mutex mu;
     static std::vector<std::pair<const void*, size_t>> done;
     std::lock_guard<std::mutex> lk(mu);
     for (auto& d : done)
         if (d.first == (const void*)kern && d.second >= bytes) return;
-    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    done.emplace_back((const void*)kern, (size_t)160 * 1024);
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    done.emplace_back((const void*)kern, bytes);
 }
 
 }  // namespace

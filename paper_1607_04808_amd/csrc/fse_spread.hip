@@ -19,6 +19,10 @@
 // Quadrature: one workgroup per bin stages the (TB+P-1)^3 block of the field
 // that the bin's windows cover in LDS (when it fits) and each wave reduces one
 // point at a time from LDS; otherwise the field is read from global memory.
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "fse_common.h"
 
 namespace fse {
@@ -456,8 +460,16 @@ template <typename T> size_t gather_lds_bytes(const GridGeo& g) {
     return b <= 140 * 1024 ? b : 0;
 }
 
-template <typename K> void allow_lds(K kern) {
-    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+// Raise a kernel's dynamic-LDS limit to `bytes` (static LDS comes on top and
+// the sum must stay within the 160 KB of a workgroup); remembered per kernel.
+template <typename K> void allow_lds(K kern, size_t bytes) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, size_t>> done;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& d : done)
+        if (d.first == (const void*)kern && d.second >= bytes) return;
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    done.emplace_back((const void*)kern, bytes);
 }
 
 }  // namespace
@@ -482,7 +494,7 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
                    hipStream_t st) {
     const size_t lds = gather_lds_bytes<T>(g);
     if (lds) {
-        allow_lds(k_gather_lds<T, 0>);
+        allow_lds(k_gather_lds<T, 0>, lds);
         hipLaunchKernelGGL((k_gather_lds<T, 0>), dim3(nbins(g), batch), dim3(512), lds, st, g, p.tile_start,
                            p.perm_s, p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u, (T*)nullptr);
         return;
@@ -502,8 +514,8 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
     const size_t lds = gather_lds_bytes<T>(g);
     if (lds && dx) {
         // pass 1: forward field contracted with w; pass 2: phi_w value and contraction with f
-        allow_lds(k_gather_lds<T, 1>);
-        allow_lds(k_gather_lds<T, 2>);
+        allow_lds(k_gather_lds<T, 1>, lds);
+        allow_lds(k_gather_lds<T, 2>, lds);
         hipLaunchKernelGGL((k_gather_lds<T, 1>), dim3(nbins(g)), dim3(512), lds, st, g, p.tile_start, p.perm_s,
                            p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);
         hipLaunchKernelGGL((k_gather_lds<T, 2>), dim3(nbins(g)), dim3(512), lds, st, g, p.tile_start, p.perm_s,
