@@ -12,8 +12,9 @@
 // with e = exp(-xi^2 r^2), erfc = erfc(xi r).
 //
 // One workgroup per cell: one thread per target, source chunks of the 27
-// neighbour cells staged in LDS.  Points are in cell order, so each chunk is a
-// contiguous, coalesced read.
+// neighbour cells staged in LDS (three x-adjacent cells are one contiguous
+// range in cell order, so each chunk is a coalesced read), hits queued per
+// thread and evaluated wave-wide.
 #include "fse_common.h"
 
 namespace fse {
@@ -22,23 +23,77 @@ namespace {
 
 constexpr double INV_SQRTPI = 0.56418958354775628695;
 
-template <typename T> __device__ __forceinline__ T derfc(T x);
-template <> __device__ __forceinline__ float derfc<float>(float x) { return erfcf(x); }
-template <> __device__ __forceinline__ double derfc<double>(double x) { return erfc(x); }
-template <typename T> __device__ __forceinline__ T dexpr(T x);
-template <> __device__ __forceinline__ float dexpr<float>(float x) { return expf(x); }
-template <> __device__ __forceinline__ double dexpr<double>(double x) { return exp(x); }
+// Radial factors of a pair at squared distance r2 > 0:
+// r, 1/r, e = exp(-xi^2 r^2) and ec = erfc(xi r).
+// FP64: the library functions.  FP32: hardware rsqrt/exp2/rcp, and
+// erfc(x) = e t Q(t), t = 1/(1 + p x), with Q of degree 10 fitted for a
+// relative error of about 3e-7 in FP32 over all x >= 0 (the generator is
+// fit_erfcx.py beside this file).
+template <typename T>
+__device__ __forceinline__ void radial(T xi, T xi2, T r2, T& r, T& ir, T& e, T& ec);
 
-template <typename T, int KERNEL, int NB>
+template <>
+__device__ __forceinline__ void radial<double>(double xi, double xi2, double r2, double& r, double& ir,
+                                               double& e, double& ec) {
+    r = sqrt(r2);
+    ir = 1.0 / r;
+    e = exp(-xi2 * r2);
+    ec = erfc(xi * r);
+}
+
+template <>
+__device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, float& r, float& ir, float& e,
+                                              float& ec) {
+    constexpr float LOG2E = 1.44269504f;
+    ir = __builtin_amdgcn_rsqf(r2);
+    r = r2 * ir;
+    e = __builtin_amdgcn_exp2f(-(xi2 * r2) * LOG2E);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.4f, xi * r, 1.0f));
+    float q = -0.0292195667f;
+    q = fmaf(q, t, 0.140469076f);
+    q = fmaf(q, t, -0.235575206f);
+    q = fmaf(q, t, 0.137618668f);
+    q = fmaf(q, t, -0.046936828f);
+    q = fmaf(q, t, 0.0839353831f);
+    q = fmaf(q, t, 0.11900294f);
+    q = fmaf(q, t, 0.171740179f);
+    q = fmaf(q, t, 0.20761365f);
+    q = fmaf(q, t, 0.225675863f);
+    q = fmaf(q, t, 0.225675835f);
+    ec = e * t * q;
+}
+
+constexpr int QCAP = 64;  // queued hits per thread before the wave flushes
+// Far-away position for padding slots and idle lanes: every distance to it
+// exceeds rc (its square may overflow to +inf, which fails the test as well).
+constexpr double FAR = 1e18;
+
+template <typename T>
+struct __align__(4 * sizeof(T)) Pos4 {
+    T x, y, z, pad;
+};
+
+// One pass over the pairs 0 < |x_t - x_s| <= rc of the targets of one cell.
+// Every thread owns one target.  For each LDS chunk of neighbour sources the
+// thread first tests all candidates and queues the hits (chunk indices) in a
+// private LDS queue; the wave then evaluates the queued pairs together, so the
+// erfc/exp work runs only for interacting pairs instead of for every candidate
+// that some lane of the wave happens to hit.
+//   GRAD = false: out = (accumulate ? out : 0) + sum_b-wise u^R + self_coef a   (NB batch members)
+//   GRAD = true:  out(dx) += sum_b sum_pairs grad_r[w_t . G^R f_s + sgn w_s . G^R f_t]
+template <typename T, int KERNEL, int NB, bool GRAD>
 __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict__ cell_start,
                                              const T* __restrict__ x_r, const T* __restrict__ a_r,
-                                             const T* __restrict__ b_r, int64_t n, int batch, T xi,
-                                             T self_coef, const int* __restrict__ perm_r, T* u,
-                                             int accumulate) {
-    constexpr int CH = 256;
-    constexpr int NS = (KERNEL == FSE_STRESSLET) ? 6 : 3;  // source values per point per batch
-    __shared__ T xs[CH * 3];
-    __shared__ T ss[NB][CH * NS];
+                                             const T* __restrict__ b_r, const T* __restrict__ w_r,
+                                             int64_t n, int batch, T xi, T self_coef,
+                                             const int* __restrict__ perm_r, T* out, int accumulate) {
+    constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
+    // sources per LDS chunk: 512, or 256 when the staged values are wide
+    constexpr int CH = (NB * NS * sizeof(T) <= 24) ? 512 : 256;
+    __shared__ Pos4<T> xs[CH];
+    __shared__ T ss[NB][NS][CH];
+    __shared__ unsigned short qd[QCAP][256];
+    const int tid = threadIdx.x;
     const int nc = cg.ncell;
     const int cell = blockIdx.x;
     const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
@@ -48,242 +103,212 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     const T xi2 = xi * xi;
     const T c2x = (T)(2.0 * INV_SQRTPI) * xi;       // 2 xi / sqrt(pi)
     const T c4x3 = (T)(4.0 * INV_SQRTPI) * xi * xi2;  // 4 xi^3 / sqrt(pi)
-    for (int tb = t0; tb < t1; tb += CH) {
-        const int j = tb + (int)threadIdx.x;
+    const T sgn = (KERNEL == FSE_STOKESLET) ? (T)1 : (T)-1;
+    for (int tb = t0; tb < t1; tb += 256) {
+        const int j = tb + tid;
         const bool act = j < t1;
-        T xt0 = 0, xt1 = 0, xt2 = 0;
+        T xt0 = (T)FAR, xt1 = (T)FAR, xt2 = (T)FAR;
         if (act) {
             xt0 = x_r[3 * (int64_t)j];
             xt1 = x_r[3 * (int64_t)j + 1];
             xt2 = x_r[3 * (int64_t)j + 2];
         }
+        // target-side values for the gradient: f_t, w_t per batch member
+        T ft[NB][3], wt[NB][3];
         T acc[NB][3];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b][0] = acc[b][1] = acc[b][2] = (T)0;
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                acc[b][d] = (T)0;
+                ft[b][d] = wt[b][d] = (T)0;
+                if (GRAD && act && b0 + b < batch) {
+                    ft[b][d] = a_r[((int64_t)(b0 + b) * n + j) * 3 + d];
+                    wt[b][d] = w_r[((int64_t)(b0 + b) * n + j) * 3 + d];
+                }
+            }
+        T g0 = 0, g1 = 0, g2 = 0;
+        int qn = 0;
+        const bool wave_active = __any(act);
+
+        auto eval = [&](int kk) {
+            const Pos4<T> ps = xs[kk];
+            const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
+            const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
+            T r, ir, e, ec;
+            radial<T>(xi, xi2, r2, r, ir, e, ec);
+            if constexpr (!GRAD) {
+                if constexpr (KERNEL == FSE_STOKESLET) {
+                    const T cd = ec * ir - c2x * e;
+                    const T c1 = (ec * ir + c2x * e) * ir * ir;  // on r r^T
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const T f0 = ss[b][0][kk], f1 = ss[b][1][kk], f2 = ss[b][2][kk];
+                        const T rf = (r0 * f0 + r1 * f1 + r2v * f2) * c1;
+                        acc[b][0] += cd * f0 + rf * r0;
+                        acc[b][1] += cd * f1 + rf * r1;
+                        acc[b][2] += cd * f2 + rf * r2v;
+                    }
+                } else if constexpr (KERNEL == FSE_ROTLET) {
+                    const T c = (ec * ir * ir + c2x * e * ir) * ir;  // on f x r
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const T f0 = ss[b][0][kk], f1 = ss[b][1][kk], f2 = ss[b][2][kk];
+                        acc[b][0] += c * (f1 * r2v - f2 * r1);
+                        acc[b][1] += c * (f2 * r0 - f0 * r2v);
+                        acc[b][2] += c * (f0 * r1 - f1 * r0);
+                    }
+                } else {
+                    const T A1 = -(T)2 * ir * ((T)3 * ec * ir + c2x * ((T)3 + (T)2 * xi2 * r2) * e);
+                    const T A2 = c4x3 * r * e;
+                    const T h0 = r0 * ir, h1 = r1 * ir, h2 = r2v * ir;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const T q0 = ss[b][0][kk], q1 = ss[b][1][kk], q2 = ss[b][2][kk];
+                        const T n0 = ss[b][3][kk], n1 = ss[b][4][kk], n2 = ss[b][5][kk];
+                        const T hq = h0 * q0 + h1 * q1 + h2 * q2;
+                        const T hn = h0 * n0 + h1 * n1 + h2 * n2;
+                        const T nq = n0 * q0 + n1 * q1 + n2 * q2;
+                        const T s1c = A1 * hn * hq + A2 * nq;
+                        acc[b][0] += s1c * h0 + A2 * (n0 * hq + q0 * hn);
+                        acc[b][1] += s1c * h1 + A2 * (n1 * hq + q1 * hn);
+                        acc[b][2] += s1c * h2 + A2 * (n2 * hq + q2 * hn);
+                    }
+                }
+            } else {
+                const T rv[3] = {r0, r1, r2v};
+                if constexpr (KERNEL == FSE_STOKESLET) {
+                    // w.S^R f = a(r) (w.f) + (b(r)/r^2) (w.r)(f.r)
+                    const T b_ = ec * ir + c2x * e;
+                    const T da = -ec * ir * ir - c2x * e * ir + c4x3 * r * e;
+                    const T db = -ec * ir * ir - c2x * e * ir - c4x3 * r * e;
+                    const T Bc = b_ * ir * ir;
+                    const T dB = db * ir * ir - (T)2 * b_ * ir * ir * ir;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const T fn[3] = {ss[b][0][kk], ss[b][1][kk], ss[b][2][kk]};
+                        const T wn[3] = {ss[b][3][kk], ss[b][4][kk], ss[b][5][kk]};
+                        const T* fp = ft[b];
+                        const T* wp = wt[b];
+                        const T wf1 = wp[0] * fn[0] + wp[1] * fn[1] + wp[2] * fn[2];
+                        const T wr1 = wp[0] * rv[0] + wp[1] * rv[1] + wp[2] * rv[2];
+                        const T fr1 = fn[0] * rv[0] + fn[1] * rv[1] + fn[2] * rv[2];
+                        const T wf2 = wn[0] * fp[0] + wn[1] * fp[1] + wn[2] * fp[2];
+                        const T wr2 = wn[0] * rv[0] + wn[1] * rv[1] + wn[2] * rv[2];
+                        const T fr2 = fp[0] * rv[0] + fp[1] * rv[1] + fp[2] * rv[2];
+                        const T rad = (da * (wf1 + sgn * wf2) + dB * (wr1 * fr1 + sgn * wr2 * fr2)) * ir;
+                        g0 += rad * rv[0] + Bc * (wp[0] * fr1 + fn[0] * wr1 + sgn * (wn[0] * fr2 + fp[0] * wr2));
+                        g1 += rad * rv[1] + Bc * (wp[1] * fr1 + fn[1] * wr1 + sgn * (wn[1] * fr2 + fp[1] * wr2));
+                        g2 += rad * rv[2] + Bc * (wp[2] * fr1 + fn[2] * wr1 + sgn * (wn[2] * fr2 + fp[2] * wr2));
+                    }
+                } else {
+                    // w.Omega^R f = psi(r) r.(w x f), psi = rho/r
+                    const T rho = ec * ir * ir + c2x * e * ir;
+                    const T drho = -(T)2 * ec * ir * ir * ir - (T)2 * c2x * e * ir * ir - c4x3 * e;
+                    const T psi = rho * ir;
+                    const T dpsi = drho * ir - rho * ir * ir;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const T fn[3] = {ss[b][0][kk], ss[b][1][kk], ss[b][2][kk]};
+                        const T wn[3] = {ss[b][3][kk], ss[b][4][kk], ss[b][5][kk]};
+                        const T* fp = ft[b];
+                        const T* wp = wt[b];
+                        const T cc0 = (wp[1] * fn[2] - wp[2] * fn[1]) + sgn * (wn[1] * fp[2] - wn[2] * fp[1]);
+                        const T cc1 = (wp[2] * fn[0] - wp[0] * fn[2]) + sgn * (wn[2] * fp[0] - wn[0] * fp[2]);
+                        const T cc2 = (wp[0] * fn[1] - wp[1] * fn[0]) + sgn * (wn[0] * fp[1] - wn[1] * fp[0]);
+                        const T rc = (rv[0] * cc0 + rv[1] * cc1 + rv[2] * cc2) * dpsi * ir;
+                        g0 += rc * rv[0] + psi * cc0;
+                        g1 += rc * rv[1] + psi * cc1;
+                        g2 += rc * rv[2] + psi * cc2;
+                    }
+                }
+            }
+        };
+        auto flush = [&]() {
+            for (int e = 0; __any(e < qn); ++e)
+                if (e < qn) eval((int)qd[e][tid]);
+            qn = 0;
+        };
+
         for (int dz = -1; dz <= 1; ++dz) {
             const int nz = cz + dz;
             if (nz < 0 || nz >= nc) continue;
             for (int dy = -1; dy <= 1; ++dy) {
                 const int ny = cy + dy;
                 if (ny < 0 || ny >= nc) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int nx = cx + dx;
-                    if (nx < 0 || nx >= nc) continue;
-                    const int nb = (nz * nc + ny) * nc + nx;
-                    const int s0 = cell_start[nb], s1 = cell_start[nb + 1];
-                    for (int sb = s0; sb < s1; sb += CH) {
-                        __syncthreads();
-                        const int k = sb + (int)threadIdx.x;
+                const int row = (nz * nc + ny) * nc;
+                // the three x-neighbour cells are contiguous in cell order
+                const int s0 = cell_start[row + max(cx - 1, 0)];
+                const int s1 = cell_start[row + min(cx + 1, nc - 1) + 1];
+                for (int sb = s0; sb < s1; sb += CH) {
+                    __syncthreads();
+                    for (int q = tid; q < CH; q += 256) {
+                        const int k = sb + q;
+                        Pos4<T> ps;
+                        ps.x = ps.y = ps.z = -(T)FAR;
+                        ps.pad = (T)0;
                         if (k < s1) {
-                            xs[3 * threadIdx.x] = x_r[3 * (int64_t)k];
-                            xs[3 * threadIdx.x + 1] = x_r[3 * (int64_t)k + 1];
-                            xs[3 * threadIdx.x + 2] = x_r[3 * (int64_t)k + 2];
+                            ps.x = x_r[3 * (int64_t)k];
+                            ps.y = x_r[3 * (int64_t)k + 1];
+                            ps.z = x_r[3 * (int64_t)k + 2];
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 if (b0 + b < batch) {
                                     const T* ap = a_r + ((int64_t)(b0 + b) * n + k) * 3;
 #pragma unroll
-                                    for (int d = 0; d < 3; ++d) ss[b][NS * threadIdx.x + d] = ap[d];
+                                    for (int d = 0; d < 3; ++d) ss[b][d][q] = ap[d];
                                     if (NS == 6) {
-                                        const T* bp = b_r + ((int64_t)(b0 + b) * n + k) * 3;
+                                        const T* bp = (GRAD ? w_r : b_r) + ((int64_t)(b0 + b) * n + k) * 3;
 #pragma unroll
-                                        for (int d = 0; d < 3; ++d) ss[b][NS * threadIdx.x + 3 + d] = bp[d];
+                                        for (int d = 0; d < 3; ++d) ss[b][3 + d][q] = bp[d];
                                     }
-                                }
-                            }
-                        }
-                        __syncthreads();
-                        if (!act) continue;
-                        const int cnt = min(CH, s1 - sb);
-                        for (int kk = 0; kk < cnt; ++kk) {
-                            const T r0 = xt0 - xs[3 * kk], r1 = xt1 - xs[3 * kk + 1], r2v = xt2 - xs[3 * kk + 2];
-                            const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
-                            if (r2 > rc2 || sb + kk == j) continue;
-                            const T r = sqrt(r2);
-                            const T ir = (T)1 / r;
-                            const T e = dexpr<T>(-xi2 * r2);
-                            const T ec = derfc<T>(xi * r);
-                            if constexpr (KERNEL == FSE_STOKESLET) {
-                                const T cd = ec * ir - c2x * e;
-                                const T c1 = (ec * ir + c2x * e) * ir * ir;  // on r r^T
-#pragma unroll
-                                for (int b = 0; b < NB; ++b) {
-                                    const T* f = &ss[b][3 * kk];
-                                    const T rf = (r0 * f[0] + r1 * f[1] + r2v * f[2]) * c1;
-                                    acc[b][0] += cd * f[0] + rf * r0;
-                                    acc[b][1] += cd * f[1] + rf * r1;
-                                    acc[b][2] += cd * f[2] + rf * r2v;
-                                }
-                            } else if constexpr (KERNEL == FSE_ROTLET) {
-                                const T c = (ec * ir * ir + c2x * e * ir) * ir;  // on f x r
-#pragma unroll
-                                for (int b = 0; b < NB; ++b) {
-                                    const T* f = &ss[b][3 * kk];
-                                    acc[b][0] += c * (f[1] * r2v - f[2] * r1);
-                                    acc[b][1] += c * (f[2] * r0 - f[0] * r2v);
-                                    acc[b][2] += c * (f[0] * r1 - f[1] * r0);
-                                }
-                            } else {
-                                const T A1 = -(T)2 * ir * ((T)3 * ec * ir + c2x * ((T)3 + (T)2 * xi2 * r2) * e);
-                                const T A2 = c4x3 * r * e;
-                                const T h0 = r0 * ir, h1 = r1 * ir, h2 = r2v * ir;
-#pragma unroll
-                                for (int b = 0; b < NB; ++b) {
-                                    const T* q = &ss[b][6 * kk];
-                                    const T* nn = q + 3;
-                                    const T hq = h0 * q[0] + h1 * q[1] + h2 * q[2];
-                                    const T hn = h0 * nn[0] + h1 * nn[1] + h2 * nn[2];
-                                    const T nq = nn[0] * q[0] + nn[1] * q[1] + nn[2] * q[2];
-                                    const T s1c = A1 * hn * hq + A2 * nq;
-                                    acc[b][0] += s1c * h0 + A2 * (nn[0] * hq + q[0] * hn);
-                                    acc[b][1] += s1c * h1 + A2 * (nn[1] * hq + q[1] * hn);
-                                    acc[b][2] += s1c * h2 + A2 * (nn[2] * hq + q[2] * hn);
-                                }
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        if (act) {
-            const int64_t i = perm_r[j];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                if (b0 + b >= batch) break;
-                T* o = u + ((int64_t)(b0 + b) * n + i) * 3;
-                const T* a = a_r + ((int64_t)(b0 + b) * n + j) * 3;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const T prev = accumulate ? o[d] : (T)0;
-                    o[d] = prev + acc[b][d] + self_coef * a[d];
-                }
-            }
-        }
-    }
-}
-
-// Real-space gradient of L = sum_b sum_m w_bm . u^R_b(x_m):
-//   dx_p += sum_{0<|r|<=rc} sum_b [ grad_r(w_bp . G^R(r) f_bn) + s grad_r(w_bn . G^R(r) f_bp) ],
-// r = x_p - x_n, s = +1 for the even stokeslet, -1 for the odd rotlet.
-template <typename T, int KERNEL>
-__global__ __launch_bounds__(256) void k_real_grad(CellGeo cg, const int* __restrict__ cell_start,
-                                                  const T* __restrict__ x_r, const T* __restrict__ f_r,
-                                                  const T* __restrict__ w_r, int64_t n, int batch, T xi,
-                                                  const int* __restrict__ perm_r, T* dx) {
-    constexpr int CH = 128;
-    __shared__ T xs[CH * 3];
-    __shared__ T fs[CH * 3];
-    __shared__ T ws[CH * 3];
-    const int nc = cg.ncell;
-    const int cell = blockIdx.x;
-    const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
-    const int t0 = cell_start[cell], t1 = cell_start[cell + 1];
-    const T rc2 = (T)cg.rc2;
-    const T xi2 = xi * xi;
-    const T c2x = (T)(2.0 * INV_SQRTPI) * xi;
-    const T c4x3 = (T)(4.0 * INV_SQRTPI) * xi * xi2;
-    const T sgn = (KERNEL == FSE_STOKESLET) ? (T)1 : (T)-1;
-    for (int tb = t0; tb < t1; tb += CH) {
-        const int j = tb + (int)threadIdx.x;
-        const bool act = (int)threadIdx.x < CH && j < t1;
-        T xt0 = 0, xt1 = 0, xt2 = 0;
-        if (act) {
-            xt0 = x_r[3 * (int64_t)j];
-            xt1 = x_r[3 * (int64_t)j + 1];
-            xt2 = x_r[3 * (int64_t)j + 2];
-        }
-        T g0 = 0, g1 = 0, g2 = 0;
-        for (int bm = 0; bm < batch; ++bm) {
-            T fp[3] = {0, 0, 0}, wp[3] = {0, 0, 0};
-            if (act) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    fp[d] = f_r[((int64_t)bm * n + j) * 3 + d];
-                    wp[d] = w_r[((int64_t)bm * n + j) * 3 + d];
-                }
-            }
-            for (int dz = -1; dz <= 1; ++dz) {
-                const int nz = cz + dz;
-                if (nz < 0 || nz >= nc) continue;
-                for (int dy = -1; dy <= 1; ++dy) {
-                    const int ny = cy + dy;
-                    if (ny < 0 || ny >= nc) continue;
-                    for (int ddx = -1; ddx <= 1; ++ddx) {
-                        const int nx = cx + ddx;
-                        if (nx < 0 || nx >= nc) continue;
-                        const int nb = (nz * nc + ny) * nc + nx;
-                        const int s0 = cell_start[nb], s1 = cell_start[nb + 1];
-                        for (int sb = s0; sb < s1; sb += CH) {
-                            __syncthreads();
-                            const int k = sb + (int)threadIdx.x;
-                            if ((int)threadIdx.x < CH && k < s1) {
-#pragma unroll
-                                for (int d = 0; d < 3; ++d) {
-                                    xs[3 * threadIdx.x + d] = x_r[3 * (int64_t)k + d];
-                                    fs[3 * threadIdx.x + d] = f_r[((int64_t)bm * n + k) * 3 + d];
-                                    ws[3 * threadIdx.x + d] = w_r[((int64_t)bm * n + k) * 3 + d];
-                                }
-                            }
-                            __syncthreads();
-                            if (!act) continue;
-                            const int cnt = min(CH, s1 - sb);
-                            for (int kk = 0; kk < cnt; ++kk) {
-                                const T r[3] = {xt0 - xs[3 * kk], xt1 - xs[3 * kk + 1], xt2 - xs[3 * kk + 2]};
-                                const T r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                                if (r2 > rc2 || sb + kk == j) continue;
-                                const T rr = sqrt(r2);
-                                const T ir = (T)1 / rr;
-                                const T e = dexpr<T>(-xi2 * r2);
-                                const T ec = derfc<T>(xi * rr);
-                                const T* fn = &fs[3 * kk];
-                                const T* wn = &ws[3 * kk];
-                                if constexpr (KERNEL == FSE_STOKESLET) {
-                                    // w.S^R f = A (w.f) + Bc (w.r)(f.r), A = a(r), Bc = b(r)/r^2
-                                    const T a_ = ec * ir - c2x * e;
-                                    const T b_ = ec * ir + c2x * e;
-                                    const T da = -ec * ir * ir - c2x * e * ir + c4x3 * rr * e;
-                                    const T db = -ec * ir * ir - c2x * e * ir - c4x3 * rr * e;
-                                    const T Bc = b_ * ir * ir;
-                                    const T dB = db * ir * ir - (T)2 * b_ * ir * ir * ir;
-                                    (void)a_;
-                                    // term 1: (w_p, f_n); term 2: (w_n, f_p) with sign sgn
-                                    const T wf1 = wp[0] * fn[0] + wp[1] * fn[1] + wp[2] * fn[2];
-                                    const T wr1 = wp[0] * r[0] + wp[1] * r[1] + wp[2] * r[2];
-                                    const T fr1 = fn[0] * r[0] + fn[1] * r[1] + fn[2] * r[2];
-                                    const T wf2 = wn[0] * fp[0] + wn[1] * fp[1] + wn[2] * fp[2];
-                                    const T wr2 = wn[0] * r[0] + wn[1] * r[1] + wn[2] * r[2];
-                                    const T fr2 = fp[0] * r[0] + fp[1] * r[1] + fp[2] * r[2];
-                                    const T rad = (da * (wf1 + sgn * wf2) + dB * (wr1 * fr1 + sgn * wr2 * fr2)) * ir;
-                                    g0 += rad * r[0] + Bc * (wp[0] * fr1 + fn[0] * wr1 + sgn * (wn[0] * fr2 + fp[0] * wr2));
-                                    g1 += rad * r[1] + Bc * (wp[1] * fr1 + fn[1] * wr1 + sgn * (wn[1] * fr2 + fp[1] * wr2));
-                                    g2 += rad * r[2] + Bc * (wp[2] * fr1 + fn[2] * wr1 + sgn * (wn[2] * fr2 + fp[2] * wr2));
                                 } else {
-                                    // w.Omega^R f = psi(r) r.(w x f), psi = rho/r
-                                    const T rho = ec * ir * ir + c2x * e * ir;
-                                    const T drho = -(T)2 * ec * ir * ir * ir - (T)2 * c2x * e * ir * ir - c4x3 * e;
-                                    const T psi = rho * ir;
-                                    const T dpsi = drho * ir - rho * ir * ir;
-                                    const T c1[3] = {wp[1] * fn[2] - wp[2] * fn[1], wp[2] * fn[0] - wp[0] * fn[2],
-                                                     wp[0] * fn[1] - wp[1] * fn[0]};
-                                    const T c2[3] = {wn[1] * fp[2] - wn[2] * fp[1], wn[2] * fp[0] - wn[0] * fp[2],
-                                                     wn[0] * fp[1] - wn[1] * fp[0]};
-                                    const T cc[3] = {c1[0] + sgn * c2[0], c1[1] + sgn * c2[1], c1[2] + sgn * c2[2]};
-                                    const T rc = (r[0] * cc[0] + r[1] * cc[1] + r[2] * cc[2]) * dpsi * ir;
-                                    g0 += rc * r[0] + psi * cc[0];
-                                    g1 += rc * r[1] + psi * cc[1];
-                                    g2 += rc * r[2] + psi * cc[2];
+#pragma unroll
+                                    for (int d = 0; d < NS; ++d) ss[b][d][q] = (T)0;
                                 }
                             }
                         }
+                        xs[q] = ps;
                     }
+                    __syncthreads();
+                    if (!wave_active) continue;
+                    // candidates in groups of 8 (padding slots are far away);
+                    // the self pair and coincident points (r^2 = 0) are skipped
+                    const int cnt8 = (min(CH, s1 - sb) + 7) & ~7;
+                    for (int k8 = 0; k8 < cnt8; k8 += 8) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const Pos4<T> ps = xs[k8 + u];
+                            const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
+                            const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
+                            qd[qn][tid] = (unsigned short)(k8 + u);
+                            qn += (r2 <= rc2 && r2 > (T)0) ? 1 : 0;
+                        }
+                        if (__any(qn > QCAP - 8)) flush();
+                    }
+                    flush();
                 }
             }
         }
         if (act) {
             const int64_t i = perm_r[j];
-            dx[3 * i] += g0;
-            dx[3 * i + 1] += g1;
-            dx[3 * i + 2] += g2;
+            if constexpr (!GRAD) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (b0 + b >= batch) break;
+                    T* o = out + ((int64_t)(b0 + b) * n + i) * 3;
+                    const T* a = a_r + ((int64_t)(b0 + b) * n + j) * 3;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const T prev = accumulate ? o[d] : (T)0;
+                        o[d] = prev + acc[b][d] + self_coef * a[d];
+                    }
+                }
+            } else {
+                out[3 * i] += g0;
+                out[3 * i + 1] += g1;
+                out[3 * i + 2] += g2;
+            }
         }
     }
 }
@@ -297,9 +322,9 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const int NBc = batch == 1 ? 1 : 4;
     dim3 grd(ncells, (batch + NBc - 1) / NBc);
-#define LAUNCH(K, NB)                                                                                \
-    hipLaunchKernelGGL((k_real<T, K, NB>), grd, dim3(256), 0, st, c, p.cell_start, p.x_r, src_a_r, \
-                       src_b_r, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate)
+#define LAUNCH(K, NB)                                                                                     \
+    hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(256), 0, st, c, p.cell_start, p.x_r, src_a_r, \
+                       src_b_r, (const T*)nullptr, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate)
     if (kernel == FSE_STOKESLET) {
         if (NBc == 1) LAUNCH(FSE_STOKESLET, 1); else LAUNCH(FSE_STOKESLET, 4);
     } else if (kernel == FSE_ROTLET) {
@@ -314,12 +339,21 @@ template <typename T>
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
                       int batch, double xi, T* dx, hipStream_t st) {
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
-    if (kernel == FSE_STOKESLET)
-        hipLaunchKernelGGL((k_real_grad<T, FSE_STOKESLET>), dim3(ncells), dim3(128), 0, st, c,
-                           p.cell_start, p.x_r, f_r, w_r, p.n, batch, (T)xi, p.perm_r, dx);
-    else
-        hipLaunchKernelGGL((k_real_grad<T, FSE_ROTLET>), dim3(ncells), dim3(128), 0, st, c,
-                           p.cell_start, p.x_r, f_r, w_r, p.n, batch, (T)xi, p.perm_r, dx);
+    // batch members in groups of 4 per pass; each pass adds to dx
+    for (int b0 = 0; b0 < batch; b0 += 4) {
+        const int nb = batch - b0 < 4 ? batch - b0 : 4;
+        const T* f = f_r + (int64_t)b0 * p.n * 3;
+        const T* w = w_r + (int64_t)b0 * p.n * 3;
+#define LAUNCHG(K, NB)                                                                                  \
+        hipLaunchKernelGGL((k_real<T, K, NB, true>), dim3(ncells), dim3(256), 0, st, c, p.cell_start, p.x_r, \
+                           f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)0, p.perm_r, dx, 1)
+        if (kernel == FSE_STOKESLET) {
+            if (nb == 1) LAUNCHG(FSE_STOKESLET, 1); else LAUNCHG(FSE_STOKESLET, 4);
+        } else {
+            if (nb == 1) LAUNCHG(FSE_ROTLET, 1); else LAUNCHG(FSE_ROTLET, 4);
+        }
+#undef LAUNCHG
+    }
 }
 
 #define INST(T)                                                                                     \

@@ -8,13 +8,9 @@
 // Points are binned by the bin (TB^3 nodes, TB = GridGeo::TS) holding their
 // window start, x-fastest bin order, so a row of bins is one contiguous range.
 //
-// Spreading: one workgroup owns a TC^3 core of grid nodes (TC = 2 TB) and
-// accumulates in LDS the clipped windows of every point whose window reaches
-// the core.  Candidate points are staged in LDS in chunks (coalesced loads)
-// and compacted to those that overlap; each wave then takes one point with its
-// lanes laid along x, so consecutive lanes hit consecutive LDS banks.  Every
-// node is written exactly once, coalesced, by its owner: no global atomics and
-// no clearing of the grid.
+// Spreading: output-stationary (see k_spread); every node is written exactly
+// once, coalesced, by the thread that owns it: no atomics, no clearing of the
+// grid, and a deterministic summation order.
 //
 // Quadrature: one workgroup per bin stages the (TB+P-1)^3 block of the field
 // that the bin's windows cover in LDS (when it fits) and each wave reduces one
@@ -36,45 +32,52 @@ template <> __device__ __forceinline__ double dexp<double>(double x) { return ex
 // floor(a / b) for 0 <= a < 2^12 and 1 <= b <= 64 via a float reciprocal: a/b is
 // never within 1/(2b) of an integer above it, far above the rounding error.
 __device__ __forceinline__ int small_div(int a, int b) {
-    return (int)(((float)a + 0.5f) * __frcp_rn((float)b));
+    return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
 }
 
-constexpr int CH = 256;  // candidate points staged per chunk
-
-template <typename T, int NC, int TB>
+// Output-stationary spreading.  The workgroup (256 threads) owns a 16 x 16 x TZ
+// core of grid nodes; thread (tx, ty) keeps the z-column (tx, ty, 0..TZ-1) of
+// the core in registers for every component, so no accumulation ever needs an
+// atomic (LDS float atomics are slow on this hardware).  Candidate points,
+// those of the bins whose window starts can reach the core, are staged in LDS
+// in chunks of CH, compacted to the ones whose window overlaps the core, and
+// their 3P one-dimensional Gaussian factors are computed cooperatively into
+// LDS.  Every thread then walks the chunk's points in order (a fixed order, so
+// the result is deterministic): a wave whose 16 x 4 block of columns misses a
+// point's window skips it, and the point's z-range inside the core is a
+// wave-uniform (scalar) loop bound.
+template <typename T, int NC, int PMAX, int TZ, int CH>
 __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict__ tile_start,
                                                const int* __restrict__ bpack_s,
                                                const T* __restrict__ coff_s,
                                                const T* __restrict__ src_s, int64_t n, T* grid) {
-    constexpr int TC = 2 * TB;
-    constexpr int TC3 = TC * TC * TC;
-    __shared__ T acc[NC * TC3];
+    __shared__ T s_w[CH][3][PMAX];
+    __shared__ T s_c[CH][3];
+    __shared__ T s_v[CH][NC];
     __shared__ int s_bp[CH];
-    __shared__ T s_c[CH * 3];
-    __shared__ T s_v[CH * NC];
-    __shared__ T s_w[4][2][32];
     __shared__ int s_cnt;
 
-    const int Mt = g.Mt, P = g.P, nb = g.nt;
-    const int ncore = (Mt + TC - 1) / TC;
+    const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
+    const int ncxy = (Mt + 15) / 16, ncz = (Mt + TZ - 1) / TZ;
     const int t = blockIdx.x;
-    const int cx = t % ncore, cy = (t / ncore) % ncore, cz = t / (ncore * ncore);
+    const int cx = t % ncxy, cy = (t / ncxy) % ncxy, cz = t / (ncxy * ncxy);
     const int bm = blockIdx.y;
-    const int lox = cx * TC, loy = cy * TC, loz = cz * TC;
-    for (int q = threadIdx.x; q < NC * TC3; q += 256) acc[q] = (T)0;
-
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lox = cx * 16, loy = cy * 16, loz = cz * TZ;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int gx = lox + tx, gy = loy + ty;
     const T ahh = (T)g.ahh;
     const T half = (T)(0.5 * (P - 1));
-    // bins whose window starts can reach the core: b in [lo - P + 1, lo + TC - 1] ∩ [0, Mt - P]
-    auto brange = [&](int lo, int& s0, int& s1) {
-        s0 = max(0, lo - P + 1) / TB;
-        s1 = min(Mt - P, lo + TC - 1) / TB;
-    };
-    int bx0, bx1, by0, by1, bz0, bz1;
-    brange(lox, bx0, bx1);
-    brange(loy, by0, by1);
-    brange(loz, bz0, bz1);
+
+    T acc[TZ][NC];
+#pragma unroll
+    for (int z = 0; z < TZ; ++z)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[z][c] = (T)0;
+
+    // bins holding window starts b in [lo - P + 1, lo + ext - 1] ∩ [0, Mt - P]
+    const int bx0 = max(0, lox - P + 1) / TB, bx1 = min(Mt - P, lox + 15) / TB;
+    const int by0 = max(0, loy - P + 1) / TB, by1 = min(Mt - P, loy + 15) / TB;
+    const int bz0 = max(0, loz - P + 1) / TB, bz1 = min(Mt - P, loz + TZ - 1) / TB;
     for (int sz = bz0; sz <= bz1; ++sz)
         for (int sy = by0; sy <= by1; ++sy) {
             const int row = (sz * nb + sy) * nb;
@@ -82,78 +85,68 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
             for (int base = j0; base < j1; base += CH) {
                 if (threadIdx.x == 0) s_cnt = 0;
                 __syncthreads();
-                const int j = base + (int)threadIdx.x;
-                if (j < j1) {
-                    const int bp = bpack_s[j];
-                    const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-                    const bool ov = bx < lox + TC && bx + P > lox && by < loy + TC && by + P > loy &&
-                                    bz < loz + TC && bz + P > loz;
-                    if (ov) {
-                        const int k = atomicAdd(&s_cnt, 1);
-                        s_bp[k] = bp;
-                        s_c[3 * k] = coff_s[3 * (int64_t)j];
-                        s_c[3 * k + 1] = coff_s[3 * (int64_t)j + 1];
-                        s_c[3 * k + 2] = coff_s[3 * (int64_t)j + 2];
+                if ((int)threadIdx.x < CH) {
+                    const int j = base + (int)threadIdx.x;
+                    if (j < j1) {
+                        const int bp = bpack_s[j];
+                        const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
+                        const bool ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy &&
+                                        bz <= loz + TZ - 1 && bz + P > loz;
+                        if (ov) {
+                            const int k = atomicAdd(&s_cnt, 1);
+                            s_bp[k] = bp;
+                            s_c[k][0] = coff_s[3 * (int64_t)j];
+                            s_c[k][1] = coff_s[3 * (int64_t)j + 1];
+                            s_c[k][2] = coff_s[3 * (int64_t)j + 2];
 #pragma unroll
-                        for (int c = 0; c < NC; ++c) s_v[NC * k + c] = src_s[((int64_t)bm * n + j) * NC + c];
+                            for (int c = 0; c < NC; ++c) s_v[k][c] = src_s[((int64_t)bm * n + j) * NC + c];
+                        }
                     }
                 }
                 __syncthreads();
                 const int cnt = s_cnt;
-                for (int k = wid; k < cnt; k += 4) {
-                    const int bp = s_bp[k];
+                // 1D Gaussian factors of the compacted points
+                for (int q = threadIdx.x; q < cnt * 3 * P; q += 256) {
+                    const int k = q / (3 * P), r = q - k * 3 * P;
+                    const int d = r / P, i = r - d * P;
+                    const T e = s_c[k][d] + half - (T)i;
+                    s_w[k][d][i] = dexp<T>(-ahh * e * e);
+                }
+                __syncthreads();
+                for (int k = 0; k < cnt; ++k) {
+                    const int bp = __builtin_amdgcn_readfirstlane(s_bp[k]);
                     const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-                    const int x0 = max(bx, lox), x1 = min(bx + P, lox + TC);
-                    const int y0 = max(by, loy), y1 = min(by + P, loy + TC);
-                    const int z0 = max(bz, loz), z1 = min(bz + P, loz + TC);
-                    const int nx = x1 - x0, ny = y1 - y0, nz = z1 - z0;
-                    const int R = 64 / nx;
-                    const int rr = small_div(lane, nx);
-                    const int ix = lane - rr * nx;
-                    const T ex = s_c[3 * k] + half - (T)(x0 - bx + ix);
-                    const T wx = dexp<T>(-ahh * ex * ex);
-                    if (lane < ny) {
-                        const T e = s_c[3 * k + 1] + half - (T)(y0 - by + lane);
-                        s_w[wid][0][lane] = dexp<T>(-ahh * e * e);
-                    } else if (lane >= 32 && lane - 32 < nz) {
-                        const T e = s_c[3 * k + 2] + half - (T)(z0 - bz + lane - 32);
-                        s_w[wid][1][lane - 32] = dexp<T>(-ahh * e * e);
-                    }
-                    wave_lds_sync();
+                    const int ix = gx - bx, iy = gy - by;
+                    const bool in = (unsigned)ix < (unsigned)P && (unsigned)iy < (unsigned)P;
+                    if (!__any(in)) continue;
+                    const T wxy = in ? s_w[k][0][in ? ix : 0] * s_w[k][1][in ? iy : 0] : (T)0;
                     T v[NC];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) v[c] = s_v[NC * k + c];
-                    const int nrows = ny * nz;
-                    if (rr < R) {
-                        int iz = small_div(rr, ny);
-                        int iy = rr - iz * ny;
-                        T* a0 = acc + ((z0 - loz) * TC + (y0 - loy)) * TC + (x0 - lox) + ix;
-                        for (int q = rr; q < nrows; q += R) {
-                            const T w = wx * s_w[wid][0][iy] * s_w[wid][1][iz];
-                            T* a = a0 + (iz * TC + iy) * TC;
+                    for (int c = 0; c < NC; ++c) v[c] = s_v[k][c];
+                    const int zlo = max(bz, loz) - loz, zhi = min(bz + P, loz + TZ) - loz;
+                    const T* wz = &s_w[k][2][loz - bz];
 #pragma unroll
-                            for (int c = 0; c < NC; ++c) atomicAdd(a + c * TC3, w * v[c]);
-                            iy += R;
-                            while (iy >= ny) {
-                                iy -= ny;
-                                ++iz;
-                            }
+                    for (int z = 0; z < TZ; ++z) {
+                        if (z >= zlo && z < zhi) {
+                            const T w = wxy * wz[z];
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) acc[z][c] += w * v[c];
                         }
                     }
-                    wave_lds_sync();
                 }
                 __syncthreads();
             }
         }
-    __syncthreads();
-    const int64_t M3 = (int64_t)Mt * Mt * Mt;
-    for (int q = threadIdx.x; q < TC3; q += 256) {
-        const int lx = q % TC, ly = (q / TC) % TC, lz = q / (TC * TC);
-        const int gx = lox + lx, gy = loy + ly, gz = loz + lz;
-        if (gx < Mt && gy < Mt && gz < Mt) {
-            const int64_t o = ((int64_t)gz * Mt + gy) * Mt + gx;
+    if (gx < Mt && gy < Mt) {
+        const int64_t M3 = (int64_t)Mt * Mt * Mt;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[c * TC3 + q];
+        for (int z = 0; z < TZ; ++z) {
+            const int gz = loz + z;
+            if (gz < Mt) {
+                const int64_t o = ((int64_t)gz * Mt + gy) * Mt + gx;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[z][c];
+            }
         }
     }
 }
@@ -477,16 +470,19 @@ template <typename K> void allow_lds(K kern, size_t bytes) {
 template <typename T>
 void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int c_in, int batch,
                    T* grid, hipStream_t st) {
-    // bin side TB = g.TS; core side 2 TB: 16 for FP32, 12 for FP64
-    constexpr int TB = sizeof(T) == 4 ? 8 : 6;
-    const unsigned ncore = (unsigned)((g.Mt + 2 * TB - 1) / (2 * TB));
-    dim3 grd(ncore * ncore * ncore, batch);
-    if (c_in == 3)
-        hipLaunchKernelGGL((k_spread<T, 3, TB>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,
-                           p.coff_s, src_s, p.n, grid);
-    else
-        hipLaunchKernelGGL((k_spread<T, 6, TB>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,
-                           p.coff_s, src_s, p.n, grid);
+    // cores of 16 x 16 x TZ nodes: TZ = 16 (FP32) or 8 (FP64) register accumulators per component
+    constexpr int TZ = sizeof(T) == 4 ? 16 : 8;
+    const unsigned ncxy = (unsigned)((g.Mt + 15) / 16), ncz = (unsigned)((g.Mt + TZ - 1) / TZ);
+    dim3 grd(ncxy * ncxy * ncz, batch);
+#define SPREAD(NC, PM, CHK)                                                                                  \
+    hipLaunchKernelGGL((k_spread<T, NC, PM, TZ, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s, \
+                       p.coff_s, src_s, p.n, grid)
+    if (sizeof(T) == 4 && g.P <= 16) {
+        if (c_in == 3) SPREAD(3, 16, 128); else SPREAD(6, 16, 128);
+    } else {
+        if (c_in == 3) SPREAD(3, 32, 64); else SPREAD(6, 32, 64);
+    }
+#undef SPREAD
 }
 
 template <typename T>
