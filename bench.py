@@ -85,7 +85,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=2048, help="oracle target sample size")
     ap.add_argument("--forms", default="f32,f64")
+    ap.add_argument("--set", action="append", default=[], metavar="FORM.KEY=VALUE",
+                    help="override a parameter of a form, e.g. f32.xi=90 (repeatable)")
     args = ap.parse_args()
+    for item in args.set:
+        key, val = item.split("=", 1)
+        form, name = key.split(".", 1)
+        if form not in FORMS or name not in FORMS[form]:
+            ap.error("unknown parameter %s" % key)
+        FORMS[form][name] = type(FORMS[form][name])(float(val))
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
               "(the multi-GPU decomposition is a design note in DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -100,7 +108,6 @@ def main():
     x64 = W.uniform_cube(n, 1000 + cfg_id)
     f64 = W.normal_strengths(n, 2000 + cfg_id)
     w64 = W.normal_strengths(n, 3000 + cfg_id)
-    pair_count = n * (n - 1) * cube_pair_cdf(FORMS["f32"]["rc"])
 
     results = {}
     outputs = {}
