@@ -581,7 +581,7 @@ fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
     gg.Mt = geo.Mt;
     gg.n = geo.n_fft;
     gg.P = params->P;
-    gg.TS = dtype == FSE_F32 ? 8 : 6;  // bin side; spreading cores are 2 bins per side
+    gg.TS = bin_side(dtype == FSE_F32 ? 4 : 8, gg.P);  // bin side of the point binning
     gg.nt = (geo.Mt + gg.TS - 1) / gg.TS;
     for (int d = 0; d < 3; ++d) gg.x0[d] = geo.x0[d];
     gg.h = geo.h;

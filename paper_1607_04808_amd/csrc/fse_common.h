@@ -133,6 +133,8 @@ void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, 
 template <typename T>
 void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int c_in, int batch,
                    T* grid, hipStream_t st);
+// bin side (grid points) of the point binning for the element size and P
+int bin_side(int elem_bytes, int P);
 template <typename T>
 void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int batch, T* u,
                    hipStream_t st);

@@ -29,8 +29,9 @@ template <typename T> __device__ __forceinline__ T dexp(T x);
 template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 
-// floor(a / b) for 0 <= a < 2^12 and 1 <= b <= 64 via a float reciprocal: a/b is
-// never within 1/(2b) of an integer above it, far above the rounding error.
+// floor(a / b) for 0 <= a < 2^21 and b >= 1 via a float reciprocal: (a + 0.5) / b
+// lies at least 1/(2b) from the integers on both sides, and the relative error
+// of (a + 0.5) * rcp(b) (about 1.5 ulp) keeps it within (a + 0.5) 2^-22.4 / b < 1/(2b).
 __device__ __forceinline__ int small_div(int a, int b) {
     return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
 }
@@ -152,136 +153,154 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Quadrature with the bin's field block staged in LDS.  MODE 0: value gather
-// u = sum g(x - x_p) F(p) (3 components).  MODE 1: gradient part with the
-// forward field, dx = sum grad g (w . phi_f).  MODE 2: value of phi_w into
-// dsrc and dx += sum grad g (f . phi_w).
+// Quadrature with the bin's field block staged in LDS, NCS of the 3 field
+// components at a time (3 when the (TB+P-1)^3 block of all of them fits,
+// else 1).  One wave per point; lane l owns the window rows r = l, l + 64, ...
+// (r = iy + P iz) and sums along x with the x-weights broadcast from LDS, so
+// every LDS read of the field feeds one or two FMAs and no index arithmetic.
+//   MODE 0: u = sum g F (value).
+//   MODE 1: dx  = sum grad g (p . F), p = the point's vector (the forward
+//           field contracted with w; the first contribution overwrites).
+//   MODE 2: out = sum g F and dx += sum grad g (p . F).
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
-__global__ __launch_bounds__(512) void k_gather_lds(GridGeo g, const int* __restrict__ tile_start,
-                                                   const int* __restrict__ perm_s,
-                                                   const int* __restrict__ bpack_s,
-                                                   const T* __restrict__ coff_s,
-                                                   const T* __restrict__ field, const T* __restrict__ vec_s,
-                                                   int64_t n, int batch, T* out, T* dx) {
+constexpr int GW = 4;  // waves per quadrature workgroup
+
+template <typename T, int MODE, int NCS>
+__global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __restrict__ tile_start,
+                                                       const int* __restrict__ perm_s,
+                                                       const int* __restrict__ bpack_s,
+                                                       const T* __restrict__ coff_s,
+                                                       const T* __restrict__ field,
+                                                       const T* __restrict__ vec_s, int64_t n, int batch,
+                                                       T* out, T* dx) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = (T*)smem_raw;
-    __shared__ T s_w[8][4][32];
+    // per wave: wx, wy, wz, dwx, dwy, dwz; zero beyond P
+    __shared__ __align__(16) T s_w[GW][6][32];
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
-    const int E = TB + P - 1;
-    const int E3 = E * E * E;
+    const int E = TB + P - 1, E2 = E * E, E3 = E2 * E;
+    const int E3S = E3 + 4;  // component stride: 4 zero pads absorb the x-unroll overrun
     const int64_t M3 = (int64_t)Mt * Mt * Mt;
     const int s = blockIdx.x;
     const int j0 = tile_start[s], j1 = tile_start[s + 1];
     if (j0 == j1) return;
     const int tbx = s % nb, tby = (s / nb) % nb, tbz = s / (nb * nb);
     const int lox = tbx * TB, loy = tby * TB, loz = tbz * TB;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const T ahh = (T)g.ahh;
     const T dfac = (T)(-2.0 * g.ahh / g.h);
     const T half = (T)(0.5 * (P - 1));
-    const int R = 64 / P;
-    const int rr = small_div(lane, P);
-    const int ix = lane - rr * P;
+    const int PP = P * P, P4 = (P + 3) & ~3;
     const int bm0 = MODE == 0 ? blockIdx.y : 0;
     const int bm1 = MODE == 0 ? blockIdx.y + 1 : batch;
     for (int bm = bm0; bm < bm1; ++bm) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < 3 * E3; q += blockDim.x) {
-            const int c = q / E3, r = q - c * E3;
-            const int x = r % E, y = (r / E) % E, z = r / (E * E);
-            const int gx = lox + x, gy = loy + y, gz = loz + z;
-            sm[q] = (gx < Mt && gy < Mt && gz < Mt)
-                        ? field[((int64_t)bm * 3 + c) * M3 + ((int64_t)gz * Mt + gy) * Mt + gx]
-                        : (T)0;
-        }
-        __syncthreads();
-        for (int j = j0 + wid; j < j1; j += nw) {
-            const int bp = bpack_s[j];
-            const int lbx = (bp & 1023) - lox, lby = ((bp >> 10) & 1023) - loy, lbz = (bp >> 20) - loz;
-            const T cx = coff_s[3 * (int64_t)j], cy = coff_s[3 * (int64_t)j + 1], cz = coff_s[3 * (int64_t)j + 2];
-            const T ex = cx + half - (T)ix;
-            const T wx = dexp<T>(-ahh * ex * ex);
-            const T dwx = dfac * ex * wx;
-            if (lane < P) {
-                const T ey = cy + half - (T)lane;
-                const T wy = dexp<T>(-ahh * ey * ey);
-                s_w[wid][0][lane] = wy;
-                s_w[wid][2][lane] = dfac * ey * wy;
-            } else if (lane >= 32 && lane - 32 < P) {
-                const T ez = cz + half - (T)(lane - 32);
-                const T wz = dexp<T>(-ahh * ez * ez);
-                s_w[wid][1][lane - 32] = wz;
-                s_w[wid][3][lane - 32] = dfac * ez * wz;
+        for (int cs = 0; cs < 3; cs += NCS) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < NCS * E3S; q += 64 * GW) {
+                const int c = NCS == 1 ? 0 : small_div(q, E3S);
+                const int r = q - c * E3S;
+                T v = (T)0;
+                if (r < E3) {
+                    const int z = small_div(r, E2), rem = r - z * E2;
+                    const int y = small_div(rem, E), x = rem - y * E;
+                    const int gx = lox + x, gy = loy + y, gz = loz + z;
+                    if (gx < Mt && gy < Mt && gz < Mt)
+                        v = field[((int64_t)bm * 3 + cs + c) * M3 + ((int64_t)gz * Mt + gy) * Mt + gx];
+                }
+                sm[q] = v;
             }
-            wave_lds_sync();
-            T v0 = 0, v1 = 0, v2 = 0;  // MODE 0/2 values
-            T g0 = 0, g1 = 0, g2 = 0;  // MODE 1/2 gradient
-            T p0 = 0, p1 = 0, p2 = 0;  // contraction vector
-            if (MODE != 0) {
-                const T* pv = vec_s + ((int64_t)bm * n + j) * 3;
-                p0 = pv[0];
-                p1 = pv[1];
-                p2 = pv[2];
-            }
-            if (rr < R) {
-                int iz = small_div(rr, P);
-                int iy = rr - iz * P;
-                const T* f0 = sm + (lbz * E + lby) * E + lbx + ix;
-                for (int q = rr; q < P * P; q += R) {
-                    const T* f = f0 + (iz * E + iy) * E;
-                    const T a0 = f[0], a1 = f[E3], a2 = f[2 * E3];
-                    const T wy = s_w[wid][0][iy], wz = s_w[wid][1][iz];
-                    if (MODE == 0) {
-                        const T w = wx * wy * wz;
-                        v0 += w * a0;
-                        v1 += w * a1;
-                        v2 += w * a2;
-                    } else {
-                        const T psi = p0 * a0 + p1 * a1 + p2 * a2;
-                        const T dwy = s_w[wid][2][iy], dwz = s_w[wid][3][iz];
-                        g0 += psi * dwx * wy * wz;
-                        g1 += psi * wx * dwy * wz;
-                        g2 += psi * wx * wy * dwz;
-                        if (MODE == 2) {
-                            const T w = wx * wy * wz;
-                            v0 += w * a0;
-                            v1 += w * a1;
-                            v2 += w * a2;
+            __syncthreads();
+            for (int j = j0 + wid; j < j1; j += GW) {
+                const int bp = bpack_s[j];
+                const int lbx = (bp & 1023) - lox, lby = ((bp >> 10) & 1023) - loy, lbz = (bp >> 20) - loz;
+                {
+                    // 1-D weights: lanes 0-31 x, lanes 32-63 y, then lanes 0-31 z
+                    const int d = lane >> 5, i = lane & 31;
+                    const T c0 = coff_s[3 * (int64_t)j + d];
+                    const T e = c0 + half - (T)i;
+                    const T w = i < P ? dexp<T>(-ahh * e * e) : (T)0;
+                    s_w[wid][d][i] = w;
+                    s_w[wid][3 + d][i] = dfac * e * w;
+                    if (d == 0) {
+                        const T ez = coff_s[3 * (int64_t)j + 2] + half - (T)i;
+                        const T wz = i < P ? dexp<T>(-ahh * ez * ez) : (T)0;
+                        s_w[wid][2][i] = wz;
+                        s_w[wid][5][i] = dfac * ez * wz;
+                    }
+                }
+                wave_lds_sync();
+                T pv[NCS];
+#pragma unroll
+                for (int c = 0; c < NCS; ++c) pv[c] = MODE != 0 ? vec_s[((int64_t)bm * n + j) * 3 + cs + c] : (T)0;
+                T v[NCS];
+#pragma unroll
+                for (int c = 0; c < NCS; ++c) v[c] = (T)0;
+                T g0 = 0, g1 = 0, g2 = 0;
+                const T* wxr = s_w[wid][0];
+                const T* dwxr = s_w[wid][3];
+                for (int r = lane; r < PP; r += 64) {
+                    const int iz = small_div(r, P), iy = r - iz * P;
+                    const T* row = sm + ((lbz + iz) * E + lby + iy) * E + lbx;
+                    T S[NCS], D[NCS];
+#pragma unroll
+                    for (int c = 0; c < NCS; ++c) S[c] = D[c] = (T)0;
+                    for (int ix = 0; ix < P4; ix += 4) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const T wxu = wxr[ix + u];
+                            const T dwxu = MODE != 0 ? dwxr[ix + u] : (T)0;
+#pragma unroll
+                            for (int c = 0; c < NCS; ++c) {
+                                const T a = row[c * E3S + ix + u];
+                                S[c] += wxu * a;
+                                if (MODE != 0) D[c] += dwxu * a;
+                            }
                         }
                     }
-                    iy += R;
-                    while (iy >= P) {
-                        iy -= P;
-                        ++iz;
+                    const T wy = s_w[wid][1][iy], wz = s_w[wid][2][iz];
+                    if (MODE != 1) {
+                        const T wyz = wy * wz;
+#pragma unroll
+                        for (int c = 0; c < NCS; ++c) v[c] += wyz * S[c];
+                    }
+                    if (MODE != 0) {
+                        T Sp = 0, Dp = 0;
+#pragma unroll
+                        for (int c = 0; c < NCS; ++c) {
+                            Sp += pv[c] * S[c];
+                            Dp += pv[c] * D[c];
+                        }
+                        const T dwy = s_w[wid][4][iy], dwz = s_w[wid][5][iz];
+                        g0 += wy * wz * Dp;
+                        g1 += dwy * wz * Sp;
+                        g2 += wy * dwz * Sp;
                     }
                 }
-            }
-            const int64_t i = perm_s[j];
-            if (MODE != 1) {
-                v0 = wave_sum(v0);
-                v1 = wave_sum(v1);
-                v2 = wave_sum(v2);
-                if (lane == 0 && out) {
-                    T* o = out + ((int64_t)bm * n + i) * 3;
-                    o[0] = v0;
-                    o[1] = v1;
-                    o[2] = v2;
+                const int64_t i = perm_s[j];
+                if (MODE != 1) {
+#pragma unroll
+                    for (int c = 0; c < NCS; ++c) v[c] = wave_sum(v[c]);
+                    if (lane == 0 && out) {
+                        T* o = out + ((int64_t)bm * n + i) * 3 + cs;
+#pragma unroll
+                        for (int c = 0; c < NCS; ++c) o[c] = v[c];
+                    }
                 }
-            }
-            if (MODE != 0) {
-                g0 = wave_sum(g0);
-                g1 = wave_sum(g1);
-                g2 = wave_sum(g2);
-                if (lane == 0 && dx) {
-                    // the first contribution (forward field, first batch member) overwrites
-                    const bool first = (MODE == 1 && bm == 0);
-                    dx[3 * i] = (first ? (T)0 : dx[3 * i]) + g0;
-                    dx[3 * i + 1] = (first ? (T)0 : dx[3 * i + 1]) + g1;
-                    dx[3 * i + 2] = (first ? (T)0 : dx[3 * i + 2]) + g2;
+                if (MODE != 0) {
+                    g0 = wave_sum(g0);
+                    g1 = wave_sum(g1);
+                    g2 = wave_sum(g2);
+                    if (lane == 0 && dx) {
+                        // the first contribution (forward field, first batch member,
+                        // first component pass) overwrites; the same lane adds the rest
+                        const bool first = (MODE == 1 && bm == 0 && cs == 0);
+                        dx[3 * i] = (first ? (T)0 : dx[3 * i]) + g0;
+                        dx[3 * i + 1] = (first ? (T)0 : dx[3 * i + 1]) + g1;
+                        dx[3 * i + 2] = (first ? (T)0 : dx[3 * i + 2]) + g2;
+                    }
                 }
+                wave_lds_sync();
             }
-            wave_lds_sync();
         }
     }
 }
@@ -446,11 +465,16 @@ __global__ __launch_bounds__(256) void k_gather_grad(GridGeo g, const int* __res
 
 inline unsigned nbins(const GridGeo& g) { return (unsigned)(g.nt * g.nt * g.nt); }
 
-// LDS bytes of the staged field block, or 0 if it does not fit
-template <typename T> size_t gather_lds_bytes(const GridGeo& g) {
+// Components staged per pass (3 or 1) of the LDS quadrature and its dynamic
+// LDS bytes, or 0 if even one component's block does not fit.
+template <typename T> int gather_ncs(const GridGeo& g, size_t* bytes) {
     const size_t E = (size_t)g.TS + g.P - 1;
-    const size_t b = 3 * E * E * E * sizeof(T);
-    return b <= 140 * 1024 ? b : 0;
+    const size_t comp = (E * E * E + 4) * sizeof(T);
+    const size_t limit = 160 * 1024 - GW * 6 * 32 * sizeof(T);
+    if (3 * comp <= limit) { *bytes = 3 * comp; return 3; }
+    if (comp <= limit) { *bytes = comp; return 1; }
+    *bytes = 0;
+    return 0;
 }
 
 // Raise a kernel's dynamic-LDS limit to `bytes` (static LDS comes on top and
@@ -488,11 +512,19 @@ void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int 
 template <typename T>
 void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int batch, T* u,
                    hipStream_t st) {
-    const size_t lds = gather_lds_bytes<T>(g);
-    if (lds) {
-        allow_lds(k_gather_lds<T, 0>, lds);
-        hipLaunchKernelGGL((k_gather_lds<T, 0>), dim3(nbins(g), batch), dim3(512), lds, st, g, p.tile_start,
-                           p.perm_s, p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u, (T*)nullptr);
+    size_t lds = 0;
+    const int ncs = gather_ncs<T>(g, &lds);
+    if (ncs) {
+        const dim3 grd(nbins(g), batch);
+        if (ncs == 3) {
+            allow_lds(k_gather_lds<T, 0, 3>, lds);
+            hipLaunchKernelGGL((k_gather_lds<T, 0, 3>), grd, dim3(64 * GW), lds, st, g, p.tile_start, p.perm_s,
+                               p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u, (T*)nullptr);
+        } else {
+            allow_lds(k_gather_lds<T, 0, 1>, lds);
+            hipLaunchKernelGGL((k_gather_lds<T, 0, 1>), grd, dim3(64 * GW), lds, st, g, p.tile_start, p.perm_s,
+                               p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u, (T*)nullptr);
+        }
         return;
     }
     dim3 grd(nbins(g), batch);
@@ -507,15 +539,23 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
 template <typename T>
 void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f, const T* phi_w,
                         const T* f_s, const T* w_s, int batch, T* dsrc, T* dx, hipStream_t st) {
-    const size_t lds = gather_lds_bytes<T>(g);
-    if (lds && dx) {
+    if (!dx) {
+        if (dsrc) launch_gather<T>(g, p, phi_w, batch, dsrc, st);
+        return;
+    }
+    size_t lds = 0;
+    const int ncs = gather_ncs<T>(g, &lds);
+    if (ncs) {
         // pass 1: forward field contracted with w; pass 2: phi_w value and contraction with f
-        allow_lds(k_gather_lds<T, 1>, lds);
-        allow_lds(k_gather_lds<T, 2>, lds);
-        hipLaunchKernelGGL((k_gather_lds<T, 1>), dim3(nbins(g)), dim3(512), lds, st, g, p.tile_start, p.perm_s,
-                           p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);
-        hipLaunchKernelGGL((k_gather_lds<T, 2>), dim3(nbins(g)), dim3(512), lds, st, g, p.tile_start, p.perm_s,
-                           p.bpack_s, p.coff_s, phi_w, f_s, p.n, batch, dsrc, dx);
+#define GGRAD(NC)                                                                                              \
+    allow_lds(k_gather_lds<T, 1, NC>, lds);                                                                    \
+    allow_lds(k_gather_lds<T, 2, NC>, lds);                                                                    \
+    hipLaunchKernelGGL((k_gather_lds<T, 1, NC>), dim3(nbins(g)), dim3(64 * GW), lds, st, g, p.tile_start,      \
+                       p.perm_s, p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);                \
+    hipLaunchKernelGGL((k_gather_lds<T, 2, NC>), dim3(nbins(g)), dim3(64 * GW), lds, st, g, p.tile_start,      \
+                       p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n, batch, dsrc, dx)
+        if (ncs == 3) { GGRAD(3); } else { GGRAD(1); }
+#undef GGRAD
         return;
     }
     dim3 grd(nbins(g));
@@ -525,6 +565,18 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
     else
         hipLaunchKernelGGL((k_gather_grad<T, 32>), grd, dim3(256), 0, st, g, p.tile_start, p.perm_s,
                            p.bpack_s, p.coff_s, phi_f, phi_w, f_s, w_s, p.n, batch, dsrc, dx);
+}
+
+// Bin side for the point binning: the largest side <= 7 (FP32) or <= 6 (FP64)
+// whose quadrature block still fits in LDS for one component, at least 2.
+int bin_side(int elem_bytes, int P) {
+    const int tb_max = elem_bytes == 4 ? 7 : 6;
+    const size_t limit = 160 * 1024 - GW * 6 * 32 * (size_t)elem_bytes;
+    for (int tb = tb_max; tb >= 2; --tb) {
+        const size_t E = (size_t)tb + P - 1;
+        if ((E * E * E + 4) * elem_bytes <= limit) return tb;
+    }
+    return elem_bytes == 4 ? 7 : 6;  // too large for LDS: the quadrature reads global memory
 }
 
 #define INST(T)                                                                                      \
