@@ -15,6 +15,9 @@
 // neighbour cells staged in LDS (three x-adjacent cells are one contiguous
 // range in cell order, so each chunk is a coalesced read), hits queued per
 // thread and evaluated wave-wide.
+#include <algorithm>
+#include <cmath>
+
 #include "fse_common.h"
 
 namespace fse {
@@ -104,7 +107,8 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     const T c2x = (T)(2.0 * INV_SQRTPI) * xi;       // 2 xi / sqrt(pi)
     const T c4x3 = (T)(4.0 * INV_SQRTPI) * xi * xi2;  // 4 xi^3 / sqrt(pi)
     const T sgn = (KERNEL == FSE_STOKESLET) ? (T)1 : (T)-1;
-    for (int tb = t0; tb < t1; tb += 256) {
+    const int nthr = blockDim.x;
+    for (int tb = t0; tb < t1; tb += nthr) {
         const int j = tb + tid;
         const bool act = j < t1;
         T xt0 = (T)FAR, xt1 = (T)FAR, xt2 = (T)FAR;
@@ -135,6 +139,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             const Pos4<T> ps = xs[kk];
             const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
             const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
+            if (r2 == (T)0) return;
             T r, ir, e, ec;
             radial<T>(xi, xi2, r2, r, ir, e, ec);
             if constexpr (!GRAD) {
@@ -242,7 +247,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                 const int s1 = cell_start[row + min(cx + 1, nc - 1) + 1];
                 for (int sb = s0; sb < s1; sb += CH) {
                     __syncthreads();
-                    for (int q = tid; q < CH; q += 256) {
+                    for (int q = tid; q < CH; q += nthr) {
                         const int k = sb + q;
                         Pos4<T> ps;
                         ps.x = ps.y = ps.z = -(T)FAR;
@@ -272,8 +277,9 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                     }
                     __syncthreads();
                     if (!wave_active) continue;
-                    // candidates in groups of 8 (padding slots are far away);
-                    // the self pair and coincident points (r^2 = 0) are skipped
+                    // candidates in groups of 8 (padding slots are far away); the
+                    // self pair and coincident points (r^2 = 0) are queued and
+                    // skipped when evaluated
                     const int cnt8 = (min(CH, s1 - sb) + 7) & ~7;
                     for (int k8 = 0; k8 < cnt8; k8 += 8) {
 #pragma unroll
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                             const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
                             const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
                             qd[qn][tid] = (unsigned short)(k8 + u);
-                            qn += (r2 <= rc2 && r2 > (T)0) ? 1 : 0;
+                            qn += r2 <= rc2 ? 1 : 0;
                         }
                         if (__any(qn > QCAP - 8)) flush();
                     }
@@ -313,6 +319,14 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     }
 }
 
+// Threads per cell workgroup: whole waves covering a typical cell (mean plus
+// two standard deviations of a Poisson count), at most 256; fuller cells loop.
+unsigned real_threads(int64_t n, unsigned ncells) {
+    const double mean = (double)n / ncells;
+    const int waves = (int)std::ceil((mean + 2.0 * std::sqrt(mean)) / 64.0);
+    return 64u * (unsigned)std::min(4, std::max(1, waves));
+}
+
 }  // namespace
 
 template <typename T>
@@ -322,8 +336,9 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const int NBc = batch == 1 ? 1 : 4;
     dim3 grd(ncells, (batch + NBc - 1) / NBc);
+    const unsigned thr = real_threads(p.n, ncells);
 #define LAUNCH(K, NB)                                                                                     \
-    hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(256), 0, st, c, p.cell_start, p.x_r, src_a_r, \
+    hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), 0, st, c, p.cell_start, p.x_r, src_a_r, \
                        src_b_r, (const T*)nullptr, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate)
     if (kernel == FSE_STOKESLET) {
         if (NBc == 1) LAUNCH(FSE_STOKESLET, 1); else LAUNCH(FSE_STOKESLET, 4);
@@ -339,13 +354,14 @@ template <typename T>
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
                       int batch, double xi, T* dx, hipStream_t st) {
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
+    const unsigned thr = real_threads(p.n, ncells);
     // batch members in groups of 4 per pass; each pass adds to dx
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
         const T* f = f_r + (int64_t)b0 * p.n * 3;
         const T* w = w_r + (int64_t)b0 * p.n * 3;
 #define LAUNCHG(K, NB)                                                                                  \
-        hipLaunchKernelGGL((k_real<T, K, NB, true>), dim3(ncells), dim3(256), 0, st, c, p.cell_start, p.x_r, \
+        hipLaunchKernelGGL((k_real<T, K, NB, true>), dim3(ncells), dim3(thr), 0, st, c, p.cell_start, p.x_r, \
                            f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)0, p.perm_r, dx, 1)
         if (kernel == FSE_STOKESLET) {
             if (nb == 1) LAUNCHG(FSE_STOKESLET, 1); else LAUNCHG(FSE_STOKESLET, 4);

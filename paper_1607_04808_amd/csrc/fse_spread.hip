@@ -305,6 +305,190 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// Quadrature sweeping z: one workgroup owns an xy tile of KX x KX bins and a
+// run of bins along z.  The field planes the current z-bin's windows touch
+// (TB + P - 1 of them, over the (KX TB + P - 1)^2 xy footprint) sit in an LDS
+// ring; moving one bin up in z replaces only TB planes, so each plane is read
+// from global memory once per sweep instead of once per bin it overlaps.  Per
+// point the work is that of the quadrature above (one wave per point, lanes
+// over window rows).
+// ---------------------------------------------------------------------------
+constexpr int CW = 8;  // waves per sweeping workgroup
+
+template <typename T, int MODE, int NCS>
+__global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int segb,
+                                                       const int* __restrict__ tile_start,
+                                                       const int* __restrict__ perm_s,
+                                                       const int* __restrict__ bpack_s,
+                                                       const T* __restrict__ coff_s,
+                                                       const T* __restrict__ field,
+                                                       const T* __restrict__ vec_s, int64_t n, int batch,
+                                                       T* out, T* dx) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = (T*)smem_raw;
+    __shared__ __align__(16) T s_w[CW][6][32];
+    const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
+    const int X = KX * TB, E = X + P - 1, E2 = E * E, EZ = TB + P - 1;
+    const int CS = EZ * E2 + 4;  // component stride; 4 zero pads absorb the x-unroll overrun
+    const int64_t M3 = (int64_t)Mt * Mt * Mt;
+    const int ncx = (nb + KX - 1) / KX;
+    const int cx = blockIdx.x % ncx, cy = blockIdx.x / ncx;
+    const int lox = cx * X, loy = cy * X;
+    const int tz0 = blockIdx.y * segb, tz1 = min(nb, tz0 + segb);
+    if (tz0 >= tz1) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const T ahh = (T)g.ahh;
+    const T dfac = (T)(-2.0 * g.ahh / g.h);
+    const T half = (T)(0.5 * (P - 1));
+    const int PP = P * P, P4 = (P + 3) & ~3;
+    const int bm0 = MODE == 0 ? blockIdx.z : 0;
+    const int bm1 = MODE == 0 ? blockIdx.z + 1 : batch;
+    const int bx0 = cx * KX, bx1 = min(nb, bx0 + KX) - 1;
+    const int by0 = cy * KX, by1 = min(nb, by0 + KX) - 1;
+    // value of plane z, in-plane index t, component c of the current field
+    auto load = [&](const T* fb, int c, int z, int t) -> T {
+        const int y = small_div(t, E), x = t - y * E;
+        const int gx = lox + x, gy = loy + y;
+        if (gx < Mt && gy < Mt && z < Mt) return fb[(int64_t)c * M3 + ((int64_t)z * Mt + gy) * Mt + gx];
+        return (T)0;
+    };
+    for (int bm = bm0; bm < bm1; ++bm) {
+        for (int cs = 0; cs < 3; cs += NCS) {
+            const T* fb = field + ((int64_t)bm * 3 + cs) * M3;
+            // initial ring: planes [tz0 TB, tz0 TB + EZ)
+            __syncthreads();
+            {
+                const int tot = NCS * EZ * E2;
+                for (int q = tid; q < tot; q += 64 * CW) {
+                    const int c = NCS == 1 ? 0 : small_div(q, EZ * E2);
+                    const int r = q - c * EZ * E2;
+                    const int pz = small_div(r, E2), t = r - pz * E2;
+                    const int z = tz0 * TB + pz;
+                    sm[c * CS + (z % EZ) * E2 + t] = load(fb, c, z, t);
+                }
+                if (tid < NCS * 4) sm[(tid >> 2) * CS + EZ * E2 + (tid & 3)] = (T)0;
+            }
+            __syncthreads();
+            for (int tz = tz0; tz < tz1; ++tz) {
+                const int z0 = tz * TB;
+                if (tz > tz0) {
+                    // planes [z0 - TB + EZ, z0 + EZ) replace [z0 - TB, z0) in the ring
+                    __syncthreads();
+                    const int ptot = NCS * TB * E2;
+                    for (int q = tid; q < ptot; q += 64 * CW) {
+                        const int c = NCS == 1 ? 0 : small_div(q, TB * E2);
+                        const int r = q - c * TB * E2;
+                        const int pz = small_div(r, E2), t = r - pz * E2;
+                        const int z = z0 - TB + EZ + pz;
+                        sm[c * CS + (z % EZ) * E2 + t] = load(fb, c, z, t);
+                    }
+                    __syncthreads();
+                }
+                // the points of the z-bin tz in this tile (one contiguous range per bin row)
+                for (int by = by0; by <= by1; ++by) {
+                    const int rowb = (tz * nb + by) * nb;
+                    const int j0 = tile_start[rowb + bx0], j1 = tile_start[rowb + bx1 + 1];
+                    for (int j = j0 + wid; j < j1; j += CW) {
+                        const int bp = bpack_s[j];
+                        const int lbx = (bp & 1023) - lox, lby = ((bp >> 10) & 1023) - loy, bz = bp >> 20;
+                        {
+                            // 1-D weights: lanes 0-31 x, lanes 32-63 y, then lanes 0-31 z
+                            const int d = lane >> 5, i = lane & 31;
+                            const T c0 = coff_s[3 * (int64_t)j + d];
+                            const T e = c0 + half - (T)i;
+                            const T w = i < P ? dexp<T>(-ahh * e * e) : (T)0;
+                            s_w[wid][d][i] = w;
+                            s_w[wid][3 + d][i] = dfac * e * w;
+                            if (d == 0) {
+                                const T ez = coff_s[3 * (int64_t)j + 2] + half - (T)i;
+                                const T wz = i < P ? dexp<T>(-ahh * ez * ez) : (T)0;
+                                s_w[wid][2][i] = wz;
+                                s_w[wid][5][i] = dfac * ez * wz;
+                            }
+                        }
+                        wave_lds_sync();
+                        T pv[NCS];
+#pragma unroll
+                        for (int c = 0; c < NCS; ++c)
+                            pv[c] = MODE != 0 ? vec_s[((int64_t)bm * n + j) * 3 + cs + c] : (T)0;
+                        T v[NCS];
+#pragma unroll
+                        for (int c = 0; c < NCS; ++c) v[c] = (T)0;
+                        T g0 = 0, g1 = 0, g2 = 0;
+                        const T* wxr = s_w[wid][0];
+                        const T* dwxr = s_w[wid][3];
+                        for (int r = lane; r < PP; r += 64) {
+                            const int iz = small_div(r, P), iy = r - iz * P;
+                            const int zz = bz + iz;
+                            const int slot = zz - small_div(zz, EZ) * EZ;
+                            const T* row = sm + (slot * E + lby + iy) * E + lbx;
+                            T S[NCS], D[NCS];
+#pragma unroll
+                            for (int c = 0; c < NCS; ++c) S[c] = D[c] = (T)0;
+                            for (int ix = 0; ix < P4; ix += 4) {
+#pragma unroll
+                                for (int u = 0; u < 4; ++u) {
+                                    const T wxu = wxr[ix + u];
+                                    const T dwxu = MODE != 0 ? dwxr[ix + u] : (T)0;
+#pragma unroll
+                                    for (int c = 0; c < NCS; ++c) {
+                                        const T a = row[c * CS + ix + u];
+                                        S[c] += wxu * a;
+                                        if (MODE != 0) D[c] += dwxu * a;
+                                    }
+                                }
+                            }
+                            const T wy = s_w[wid][1][iy], wz = s_w[wid][2][iz];
+                            if (MODE != 1) {
+                                const T wyz = wy * wz;
+#pragma unroll
+                                for (int c = 0; c < NCS; ++c) v[c] += wyz * S[c];
+                            }
+                            if (MODE != 0) {
+                                T Sp = 0, Dp = 0;
+#pragma unroll
+                                for (int c = 0; c < NCS; ++c) {
+                                    Sp += pv[c] * S[c];
+                                    Dp += pv[c] * D[c];
+                                }
+                                const T dwy = s_w[wid][4][iy], dwz = s_w[wid][5][iz];
+                                g0 += wy * wz * Dp;
+                                g1 += dwy * wz * Sp;
+                                g2 += wy * dwz * Sp;
+                            }
+                        }
+                        const int64_t i = perm_s[j];
+                        if (MODE != 1) {
+#pragma unroll
+                            for (int c = 0; c < NCS; ++c) v[c] = wave_sum(v[c]);
+                            if (lane == 0 && out) {
+                                T* o = out + ((int64_t)bm * n + i) * 3 + cs;
+#pragma unroll
+                                for (int c = 0; c < NCS; ++c) o[c] = v[c];
+                            }
+                        }
+                        if (MODE != 0) {
+                            g0 = wave_sum(g0);
+                            g1 = wave_sum(g1);
+                            g2 = wave_sum(g2);
+                            if (lane == 0 && dx) {
+                                // the first contribution (forward field, first batch member,
+                                // first component pass) overwrites; the same lane adds the rest
+                                const bool first = (MODE == 1 && bm == 0 && cs == 0);
+                                dx[3 * i] = (first ? (T)0 : dx[3 * i]) + g0;
+                                dx[3 * i + 1] = (first ? (T)0 : dx[3 * i + 1]) + g1;
+                                dx[3 * i + 2] = (first ? (T)0 : dx[3 * i + 2]) + g2;
+                            }
+                        }
+                        wave_lds_sync();
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Quadrature reading the field from global memory (large P or FP64 blocks that
 // do not fit in LDS): one wave per point, LPR lanes along x per window row.
 template <typename T, int LPR>
@@ -509,9 +693,51 @@ void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int 
 #undef SPREAD
 }
 
+// Sweeping-quadrature configuration: components per pass, tile side in bins,
+// z-bins per workgroup and dynamic LDS bytes; ncs = 0 when it does not fit.
+struct ColCfg {
+    int ncs, kx, segb, nseg, ncol;
+    size_t lds;
+};
+
+template <typename T> ColCfg col_config(const GridGeo& g) {
+    ColCfg best{0, 0, 0, 0, 0, 0};
+    const size_t limit = 160 * 1024 - CW * 6 * 32 * sizeof(T);
+    // all components per pass when they fit; one-bin tiles measured as fast as
+    // two-bin ones (less LDS, two workgroups per CU)
+    const int opts[3][2] = {{3, 1}, {1, 2}, {1, 1}};
+    for (auto& o : opts) {
+        const int ncs = o[0], kx = o[1];
+        const size_t E = (size_t)kx * g.TS + g.P - 1, EZ = (size_t)g.TS + g.P - 1;
+        const size_t lds = ncs * (EZ * E * E + 4) * sizeof(T);
+        if (lds > limit) continue;
+        const int ncx = (g.nt + kx - 1) / kx;
+        const int per_cu = (int)((160 * 1024) / (lds + CW * 6 * 32 * sizeof(T)));
+        const int target = 2 * 256 * (per_cu < 1 ? 1 : per_cu);
+        int nseg = (target + ncx * ncx - 1) / (ncx * ncx);
+        nseg = nseg < 1 ? 1 : (nseg > g.nt ? g.nt : nseg);
+        const int segb = (g.nt + nseg - 1) / nseg;
+        best = ColCfg{ncs, kx, segb, (g.nt + segb - 1) / segb, ncx * ncx, lds};
+        break;
+    }
+    return best;
+}
+
 template <typename T>
 void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int batch, T* u,
                    hipStream_t st) {
+    const ColCfg cc = col_config<T>(g);
+    if (cc.ncs) {
+        const dim3 grd(cc.ncol, cc.nseg, batch);
+#define GCOL(NC)                                                                                               \
+    allow_lds(k_gather_col<T, 0, NC>, cc.lds);                                                                 \
+    hipLaunchKernelGGL((k_gather_col<T, 0, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb,            \
+                       p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u,  \
+                       (T*)nullptr)
+        if (cc.ncs == 3) { GCOL(3); } else { GCOL(1); }
+#undef GCOL
+        return;
+    }
     size_t lds = 0;
     const int ncs = gather_ncs<T>(g, &lds);
     if (ncs) {
@@ -541,6 +767,21 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
                         const T* f_s, const T* w_s, int batch, T* dsrc, T* dx, hipStream_t st) {
     if (!dx) {
         if (dsrc) launch_gather<T>(g, p, phi_w, batch, dsrc, st);
+        return;
+    }
+    const ColCfg cc = col_config<T>(g);
+    if (cc.ncs) {
+        const dim3 grd(cc.ncol, cc.nseg, 1);
+        // pass 1: forward field contracted with w; pass 2: phi_w value and contraction with f
+#define GCOLG(NC)                                                                                              \
+    allow_lds(k_gather_col<T, 1, NC>, cc.lds);                                                                 \
+    allow_lds(k_gather_col<T, 2, NC>, cc.lds);                                                                 \
+    hipLaunchKernelGGL((k_gather_col<T, 1, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb,            \
+                       p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);  \
+    hipLaunchKernelGGL((k_gather_col<T, 2, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb,            \
+                       p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n, batch, dsrc, dx)
+        if (cc.ncs == 3) { GCOLG(3); } else { GCOLG(1); }
+#undef GCOLG
         return;
     }
     size_t lds = 0;
