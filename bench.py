@@ -31,8 +31,8 @@ PEAK = {"hbm_GBs": 8000.0, "f32_TFLOPs": 157.3, "f64_TFLOPs": 78.6}
 # Parameters per form (calibrated against the oracle):
 # FP32 form: 1e-6 relative max-norm; FP64 form: 1e-10.
 FORMS = {
-    "f32": dict(xi=60.0, rc=0.063, M=183, P=12, tol=1e-6),
-    "f64": dict(xi=60.0, rc=0.081, M=228, P=22, tol=1e-10),
+    "f32": dict(xi=80.0, rc=0.04725, M=246, P=12, tol=1e-6),
+    "f64": dict(xi=80.0, rc=0.06075, M=304, P=20, tol=1e-10),
 }
 N_DEFAULT = 1_000_000
 L_BOX = 1.0 + 2.0 ** -20  # the unit cube, enlarged so FP32-rounded points stay inside

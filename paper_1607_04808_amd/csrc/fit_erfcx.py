@@ -1,22 +1,27 @@
-"""Fit of the FP32 complementary error function used by the real-space kernels.
+"""Fits of the complementary error function used by the real-space kernels.
 
-erfc(x) = exp(-x^2) * t * Q(t),  t = 1 / (1 + p x),  x >= 0,
+Both write erfc(x) = exp(-x^2) * t * Q(t) with t = 1 / (1 + p x), x >= 0, the
+form of the rational-in-t approximations of Abramowitz & Stegun 7.1.25-7.1.28,
+with a longer Q fitted here for small relative error of
+erfcx(x) = exp(x^2) erfc(x):
 
-the form of the rational-in-t approximations of Abramowitz & Stegun 7.1.25-7.1.28
-with a polynomial Q of higher degree.  Q is fitted here by iteratively
-reweighted least squares for small relative error of erfcx(x) = exp(x^2) erfc(x)
-over all t in (0, 1], i.e. all x >= 0 (Q(0) = p / sqrt(pi) from the asymptote
-erfcx(x) ~ 1 / (x sqrt(pi))).  Run it to print the coefficient table and the
-achieved maximum relative error in FP64 and with FP32 Horner evaluation.
+* FP32: p = 0.4, Q a degree-10 polynomial in t, fitted by iteratively
+  reweighted least squares over all t in (0, 1] (all x >= 0).
+* FP64: p = 0.5, Q a degree-20 Chebyshev series in s = 2 (t - t0) / (1 - t0) - 1,
+  t0 = 1 / (1 + p XMAX), fitted by weighted least squares at Chebyshev nodes
+  against a 40-digit reference, for x in [0, XMAX]; beyond XMAX, erfc(x) is
+  below 1e-44 and the kernels evaluate the series at s = -1.
+
+Run it to print both coefficient tables and their maximum relative errors.
 """
 import numpy as np
 from scipy.special import erfc, erfcx
 
-P_T = 0.4
-DEGREE = 10
+P32, DEG32 = 0.4, 10
+P64, DEG64, XMAX64 = 0.5, 20, 10.0
 
 
-def fit(p=P_T, degree=DEGREE, iters=60):
+def fit32(p=P32, degree=DEG32, iters=60):
     t = np.concatenate([np.cos(np.linspace(0, np.pi / 2, 20000)), np.linspace(1e-6, 1, 20000)])
     t = t[(t > 0) & (t <= 1)]
     x = (1 / t - 1) / p
@@ -32,7 +37,7 @@ def fit(p=P_T, degree=DEGREE, iters=60):
     return c, float(np.abs(rel).max())
 
 
-def fp32_error(c, p=P_T, xmax=9.0):
+def fp32_error(c, p=P32, xmax=9.0):
     f32 = np.float32
     x = np.linspace(0, xmax, 200001).astype(f32)
     t = f32(1) / (f32(1) + f32(p) * x)
@@ -45,7 +50,29 @@ def fp32_error(c, p=P_T, xmax=9.0):
     return float(np.abs(approx[m] / ref[m] - 1).max())
 
 
+def fit64(p=P64, degree=DEG64, xmax=XMAX64, nodes=3000):
+    import mpmath as mp
+    mp.mp.dps = 40
+    t0 = 1 / (1 + p * xmax)
+    s = np.cos(np.linspace(0, np.pi, nodes))
+    t = t0 + (s + 1) / 2 * (1 - t0)
+    x = (1 / t - 1) / p
+    y = np.array([float(mp.erfc(mp.mpf(v)) * mp.exp(mp.mpf(v) ** 2)) for v in x]) / t
+    V = np.polynomial.chebyshev.chebvander(s, degree)
+    c, *_ = np.linalg.lstsq(V / y[:, None], np.ones_like(y), rcond=None)
+    # check on a dense grid (reference: scipy erfcx, accurate to a few ulp)
+    s2 = np.linspace(-1, 1, 20001)
+    t2 = t0 + (s2 + 1) / 2 * (1 - t0)
+    x2 = (1 / t2 - 1) / p
+    rel = np.polynomial.chebyshev.chebval(s2, c) / (erfcx(x2) / t2) - 1
+    return c, t0, float(np.abs(rel).max())
+
+
 if __name__ == "__main__":
-    c, e = fit()
-    print("p = %.9g, degree %d, max rel err (fp64) %.3g, (fp32 Horner) %.3g" % (P_T, DEGREE, e, fp32_error(c)))
+    c, e = fit32()
+    print("FP32: p = %.9g, degree %d, max rel err (fp64 eval) %.3g, (fp32 Horner) %.3g"
+          % (P32, DEG32, e, fp32_error(c)))
     print(", ".join("%.9gf" % v for v in c))
+    c, t0, e = fit64()
+    print("FP64: p = %.17g, degree %d, t0 = %.17g, max rel err %.3g" % (P64, DEG64, t0, e))
+    print(",\n".join("%.17g" % v for v in c))

@@ -27,21 +27,49 @@ namespace {
 constexpr double INV_SQRTPI = 0.56418958354775628695;
 
 // Radial factors of a pair at squared distance r2 > 0:
-// r, 1/r, e = exp(-xi^2 r^2) and ec = erfc(xi r).
-// FP64: the library functions.  FP32: hardware rsqrt/exp2/rcp, and
-// erfc(x) = e t Q(t), t = 1/(1 + p x), with Q of degree 10 fitted for a
-// relative error of about 3e-7 in FP32 over all x >= 0 (the generator is
-// fit_erfcx.py beside this file).
+// r, 1/r, e = exp(-xi^2 r^2) and ec = erfc(xi r), with
+// erfc(x) = e t Q(t), t = 1/(1 + p x), Q fitted for small relative error of
+// exp(x^2) erfc(x) (the generator and its error report are fit_erfcx.py
+// beside this file):
+//   FP32: p = 0.4, Q a degree-10 polynomial in t, relative error about 3e-7
+//         in FP32 for all x >= 0; hardware rsqrt, exp2 and rcp.
+//   FP64: p = 0.5, Q a degree-20 Chebyshev series in s = 2(t - t0)/(1 - t0) - 1,
+//         t0 = 1/6 (x <= 10; s is clamped at -1 beyond, where erfc < 1e-44),
+//         relative error about 3e-15; the reciprocal of 1 + p x from the
+//         hardware estimate and two Newton steps.
 template <typename T>
 __device__ __forceinline__ void radial(T xi, T xi2, T r2, T& r, T& ir, T& e, T& ec);
+
+__constant__ double ERFC_CHEB64[21] = {
+    0.62088859609968661,     0.33031317717291347,     0.048190528012879576,    0.0013007898942622317,
+    -0.00067070511569872345, -3.7277111326298097e-05, 1.4963307669145149e-05,  3.0797536323925218e-07,
+    -4.1390867160614104e-07, 2.5753677315551033e-08,  9.9127889901883903e-09,  -1.9949429131729499e-09,
+    -6.7533070604464365e-11, 7.9914175529419191e-11,  -1.0272660257690479e-11, -1.2644162927243331e-12,
+    6.3097653465346595e-13,  -7.0177374122948254e-14, -1.1900996748257948e-14, 5.5584172623120927e-15,
+    -6.8688868596316233e-16};
 
 template <>
 __device__ __forceinline__ void radial<double>(double xi, double xi2, double r2, double& r, double& ir,
                                                double& e, double& ec) {
-    r = sqrt(r2);
-    ir = 1.0 / r;
+    ir = rsqrt(r2);
+    r = r2 * ir;
     e = exp(-xi2 * r2);
-    ec = erfc(xi * r);
+    const double d = fma(0.5 * xi, r, 1.0);
+    double t = __builtin_amdgcn_rcp(d);
+    t = fma(t, fma(-d, t, 1.0), t);
+    t = fma(t, fma(-d, t, 1.0), t);
+    // s = 2 (t - 1/6) / (5/6) - 1 = 2.4 t - 1.4
+    const double s = fmax(fma(2.4, t, -1.4), -1.0);
+    const double s2 = 2.0 * s;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = 20; k >= 1; --k) {
+        const double b0 = fma(s2, b1, ERFC_CHEB64[k] - b2);
+        b2 = b1;
+        b1 = b0;
+    }
+    const double q = fma(s, b1, ERFC_CHEB64[0] - b2);
+    ec = e * t * q;
 }
 
 template <>
@@ -66,7 +94,7 @@ __device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, flo
     ec = e * t * q;
 }
 
-constexpr int QCAP = 64;  // queued hits per thread before the wave flushes
+constexpr int QCAP = 32;  // queued hits per thread before the wave flushes
 // Far-away position for padding slots and idle lanes: every distance to it
 // exceeds rc (its square may overflow to +inf, which fails the test as well).
 constexpr double FAR = 1e18;
@@ -93,7 +121,8 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
     // sources per LDS chunk: 512, or 256 when the staged values are wide
     constexpr int CH = (NB * NS * sizeof(T) <= 24) ? 512 : 256;
-    __shared__ Pos4<T> xs[CH];
+    __shared__ Pos4<T> xs[CH];  // source positions
+    __shared__ Pos4<T> xq[CH];  // test form: -2 (x - o), |x - o|^2 about the cell corner o
     __shared__ T ss[NB][NS][CH];
     __shared__ unsigned short qd[QCAP][256];
     const int tid = threadIdx.x;
@@ -103,6 +132,11 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     const int b0 = blockIdx.y * NB;
     const int t0 = cell_start[cell], t1 = cell_start[cell + 1];
     const T rc2 = (T)cg.rc2;
+    // the candidate test uses |xl|^2 + |xs_l|^2 - 2 xl . xs_l in coordinates about
+    // the cell corner, slightly widened (its rounding is ~1e-7 of rc^2 in FP32);
+    // the exact r^2 <= rc^2 decides when a queued pair is evaluated
+    const T rc2t = rc2 * (T)(1.0 + 1.0 / 65536);
+    const T ox = (T)(cg.lo[0] + cx * cg.cell), oy = (T)(cg.lo[1] + cy * cg.cell), oz = (T)(cg.lo[2] + cz * cg.cell);
     const T xi2 = xi * xi;
     const T c2x = (T)(2.0 * INV_SQRTPI) * xi;       // 2 xi / sqrt(pi)
     const T c4x3 = (T)(4.0 * INV_SQRTPI) * xi * xi2;  // 4 xi^3 / sqrt(pi)
@@ -111,12 +145,15 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     for (int tb = t0; tb < t1; tb += nthr) {
         const int j = tb + tid;
         const bool act = j < t1;
-        T xt0 = (T)FAR, xt1 = (T)FAR, xt2 = (T)FAR;
+        T xt0 = 0, xt1 = 0, xt2 = 0;
         if (act) {
             xt0 = x_r[3 * (int64_t)j];
             xt1 = x_r[3 * (int64_t)j + 1];
             xt2 = x_r[3 * (int64_t)j + 2];
         }
+        const T xl0 = xt0 - ox, xl1 = xt1 - oy, xl2 = xt2 - oz;
+        // idle lanes: a squared norm beyond any cutoff
+        const T At = act ? xl0 * xl0 + xl1 * xl1 + xl2 * xl2 : (T)FAR;
         // target-side values for the gradient: f_t, w_t per batch member
         T ft[NB][3], wt[NB][3];
         T acc[NB][3];
@@ -132,14 +169,18 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                 }
             }
         T g0 = 0, g1 = 0, g2 = 0;
-        int qn = 0;
+        // this thread's hit queue: column tid of qd, QROW entries per row
+        constexpr int QROW = 256;
+        unsigned short* const q0 = &qd[0][tid];
+        unsigned short* const qlim = q0 + (QCAP - 8) * QROW;
+        unsigned short* qp = q0;
         const bool wave_active = __any(act);
 
         auto eval = [&](int kk) {
             const Pos4<T> ps = xs[kk];
             const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
             const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
-            if (r2 == (T)0) return;
+            if (r2 == (T)0 || r2 > rc2) return;
             T r, ir, e, ec;
             radial<T>(xi, xi2, r2, r, ir, e, ec);
             if constexpr (!GRAD) {
@@ -230,9 +271,10 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             }
         };
         auto flush = [&]() {
+            const int qn = (int)(qp - q0) / QROW;
             for (int e = 0; __any(e < qn); ++e)
-                if (e < qn) eval((int)qd[e][tid]);
-            qn = 0;
+                if (e < qn) eval((int)q0[e * QROW]);
+            qp = q0;
         };
 
         for (int dz = -1; dz <= 1; ++dz) {
@@ -249,13 +291,19 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                     __syncthreads();
                     for (int q = tid; q < CH; q += nthr) {
                         const int k = sb + q;
-                        Pos4<T> ps;
-                        ps.x = ps.y = ps.z = -(T)FAR;
-                        ps.pad = (T)0;
+                        Pos4<T> ps, pq;
+                        ps.x = ps.y = ps.z = ps.pad = (T)0;
+                        pq.x = pq.y = pq.z = (T)0;
+                        pq.pad = (T)FAR;  // padding slot: never within the cutoff
                         if (k < s1) {
                             ps.x = x_r[3 * (int64_t)k];
                             ps.y = x_r[3 * (int64_t)k + 1];
                             ps.z = x_r[3 * (int64_t)k + 2];
+                            const T l0 = ps.x - ox, l1 = ps.y - oy, l2 = ps.z - oz;
+                            pq.x = (T)-2 * l0;
+                            pq.y = (T)-2 * l1;
+                            pq.z = (T)-2 * l2;
+                            pq.pad = l0 * l0 + l1 * l1 + l2 * l2;
 #pragma unroll
                             for (int b = 0; b < NB; ++b) {
                                 if (b0 + b < batch) {
@@ -274,6 +322,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                             }
                         }
                         xs[q] = ps;
+                        xq[q] = pq;
                     }
                     __syncthreads();
                     if (!wave_active) continue;
@@ -284,13 +333,12 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                     for (int k8 = 0; k8 < cnt8; k8 += 8) {
 #pragma unroll
                         for (int u = 0; u < 8; ++u) {
-                            const Pos4<T> ps = xs[k8 + u];
-                            const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
-                            const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
-                            qd[qn][tid] = (unsigned short)(k8 + u);
-                            qn += r2 <= rc2 ? 1 : 0;
+                            const Pos4<T> pq = xq[k8 + u];
+                            const T r2 = fma(xl0, pq.x, fma(xl1, pq.y, fma(xl2, pq.z, At + pq.pad)));
+                            *qp = (unsigned short)(k8 + u);
+                            qp += r2 <= rc2t ? QROW : 0;
                         }
-                        if (__any(qn > QCAP - 8)) flush();
+                        if (__any(qp > qlim)) flush();
                     }
                     flush();
                 }
