@@ -521,15 +521,15 @@ fse_status_t adjoint_t(fse_plan* p, const T* f, const T* w, T* dsrc, T* dx, int 
     { TimedStage ts(tm, ST_GGRAD, st);
       launch_gather_grad<T>(p->gg, pd, (const T*)p->phi, (const T*)p->phi_w, (const T*)p->src_s,
                             (const T*)p->adj_s, p->batch, dsrc, dx, st); }
-    if (dsrc) {
+    if (dx) {
+        // gradient and (when requested) the real-space part of K w in one pass over the pairs
+        TimedStage ts(tm, ST_RGRAD, st);
+        launch_real_grad<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->adj_r, p->batch,
+                            p->prm.xi, self_coef(p), dx, dsrc, st);
+    } else if (dsrc) {
         TimedStage ts(tm, ST_REAL, st);
         launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->adj_r, nullptr, p->batch, p->prm.xi,
                        self_coef(p), dsrc, 1, st);
-    }
-    if (dx) {
-        TimedStage ts(tm, ST_RGRAD, st);
-        launch_real_grad<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->adj_r, p->batch,
-                            p->prm.xi, dx, st);
     }
     LAUNCHCHK();
     return FSE_OK;

@@ -160,8 +160,10 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
                  const T* src_b_r, int batch, double xi, double self_coef, T* u, int accumulate,
                  hipStream_t st);
 template <typename T>
+// dx += real-space gradient; when dsrc is given, also dsrc += the real-space
+// part of K w (with the self term) in the same pass
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
-                      int batch, double xi, T* dx, hipStream_t st);
+                      int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st);
 
 // precompute (FP64)
 void launch_pre_fill(double* out, int Mg, double h, double R, int family, hipStream_t st);

@@ -112,12 +112,15 @@ struct __align__(4 * sizeof(T)) Pos4 {
 // that some lane of the wave happens to hit.
 //   GRAD = false: out = (accumulate ? out : 0) + sum_b-wise u^R + self_coef a   (NB batch members)
 //   GRAD = true:  out(dx) += sum_b sum_pairs grad_r[w_t . G^R f_s + sgn w_s . G^R f_t]
-template <typename T, int KERNEL, int NB, bool GRAD>
+//   WVAL (with GRAD): also out2 += sum_pairs G^R w_s + self_coef w_t per batch
+//                 member (the real-space part of dL/df = K w), in the same pass
+template <typename T, int KERNEL, int NB, bool GRAD, bool WVAL = false>
 __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict__ cell_start,
                                              const T* __restrict__ x_r, const T* __restrict__ a_r,
                                              const T* __restrict__ b_r, const T* __restrict__ w_r,
                                              int64_t n, int batch, T xi, T self_coef,
-                                             const int* __restrict__ perm_r, T* out, int accumulate) {
+                                             const int* __restrict__ perm_r, T* out, int accumulate,
+                                             T* out2) {
     constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
     // sources per LDS chunk: 512, or 256 when the staged values are wide
     constexpr int CH = (NB * NS * sizeof(T) <= 24) ? 512 : 256;
@@ -243,6 +246,13 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                         const T wr2 = wn[0] * rv[0] + wn[1] * rv[1] + wn[2] * rv[2];
                         const T fr2 = fp[0] * rv[0] + fp[1] * rv[1] + fp[2] * rv[2];
                         const T rad = (da * (wf1 + sgn * wf2) + dB * (wr1 * fr1 + sgn * wr2 * fr2)) * ir;
+                        if constexpr (WVAL) {
+                            const T a_ = ec * ir - c2x * e;
+                            const T bw = Bc * wr2;
+                            acc[b][0] += a_ * wn[0] + bw * rv[0];
+                            acc[b][1] += a_ * wn[1] + bw * rv[1];
+                            acc[b][2] += a_ * wn[2] + bw * rv[2];
+                        }
                         g0 += rad * rv[0] + Bc * (wp[0] * fr1 + fn[0] * wr1 + sgn * (wn[0] * fr2 + fp[0] * wr2));
                         g1 += rad * rv[1] + Bc * (wp[1] * fr1 + fn[1] * wr1 + sgn * (wn[1] * fr2 + fp[1] * wr2));
                         g2 += rad * rv[2] + Bc * (wp[2] * fr1 + fn[2] * wr1 + sgn * (wn[2] * fr2 + fp[2] * wr2));
@@ -263,6 +273,11 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                         const T cc1 = (wp[2] * fn[0] - wp[0] * fn[2]) + sgn * (wn[2] * fp[0] - wn[0] * fp[2]);
                         const T cc2 = (wp[0] * fn[1] - wp[1] * fn[0]) + sgn * (wn[0] * fp[1] - wn[1] * fp[0]);
                         const T rc = (rv[0] * cc0 + rv[1] * cc1 + rv[2] * cc2) * dpsi * ir;
+                        if constexpr (WVAL) {
+                            acc[b][0] += psi * (wn[1] * rv[2] - wn[2] * rv[1]);
+                            acc[b][1] += psi * (wn[2] * rv[0] - wn[0] * rv[2]);
+                            acc[b][2] += psi * (wn[0] * rv[1] - wn[1] * rv[0]);
+                        }
                         g0 += rc * rv[0] + psi * cc0;
                         g1 += rc * rv[1] + psi * cc1;
                         g2 += rc * rv[2] + psi * cc2;
@@ -362,6 +377,15 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                 out[3 * i] += g0;
                 out[3 * i + 1] += g1;
                 out[3 * i + 2] += g2;
+                if constexpr (WVAL) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        if (b0 + b >= batch) break;
+                        T* o = out2 + ((int64_t)(b0 + b) * n + i) * 3;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) o[d] += acc[b][d] + self_coef * wt[b][d];
+                    }
+                }
             }
         }
     }
@@ -387,7 +411,8 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned thr = real_threads(p.n, ncells);
 #define LAUNCH(K, NB)                                                                                     \
     hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), 0, st, c, p.cell_start, p.x_r, src_a_r, \
-                       src_b_r, (const T*)nullptr, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate)
+                       src_b_r, (const T*)nullptr, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate,  \
+                       (T*)nullptr)
     if (kernel == FSE_STOKESLET) {
         if (NBc == 1) LAUNCH(FSE_STOKESLET, 1); else LAUNCH(FSE_STOKESLET, 4);
     } else if (kernel == FSE_ROTLET) {
@@ -400,22 +425,27 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
 
 template <typename T>
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
-                      int batch, double xi, T* dx, hipStream_t st) {
+                      int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st) {
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = real_threads(p.n, ncells);
-    // batch members in groups of 4 per pass; each pass adds to dx
+    // batch members in groups of 4 per pass; each pass adds to dx (and dsrc)
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
         const T* f = f_r + (int64_t)b0 * p.n * 3;
         const T* w = w_r + (int64_t)b0 * p.n * 3;
-#define LAUNCHG(K, NB)                                                                                  \
-        hipLaunchKernelGGL((k_real<T, K, NB, true>), dim3(ncells), dim3(thr), 0, st, c, p.cell_start, p.x_r, \
-                           f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)0, p.perm_r, dx, 1)
+        T* ds = dsrc ? dsrc + (int64_t)b0 * p.n * 3 : nullptr;
+#define LAUNCHG(K, NB, WV)                                                                                \
+        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(ncells), dim3(thr), 0, st, c, p.cell_start, \
+                           p.x_r, f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)self_coef, p.perm_r, dx, 1, ds)
+#define LAUNCHK(K)                                                                                        \
+        if (ds) { if (nb == 1) LAUNCHG(K, 1, true); else LAUNCHG(K, 4, true); }                           \
+        else { if (nb == 1) LAUNCHG(K, 1, false); else LAUNCHG(K, 4, false); }
         if (kernel == FSE_STOKESLET) {
-            if (nb == 1) LAUNCHG(FSE_STOKESLET, 1); else LAUNCHG(FSE_STOKESLET, 4);
+            LAUNCHK(FSE_STOKESLET)
         } else {
-            if (nb == 1) LAUNCHG(FSE_ROTLET, 1); else LAUNCHG(FSE_ROTLET, 4);
+            LAUNCHK(FSE_ROTLET)
         }
+#undef LAUNCHK
 #undef LAUNCHG
     }
 }
@@ -424,7 +454,7 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
     template void launch_real<T>(int, const CellGeo&, const PointsDev<T>&, const T*, const T*, int, \
                                  double, double, T*, int, hipStream_t);                             \
     template void launch_real_grad<T>(int, const CellGeo&, const PointsDev<T>&, const T*, const T*, \
-                                      int, double, T*, hipStream_t);
+                                      int, double, double, T*, T*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST
