@@ -37,34 +37,38 @@ __device__ __forceinline__ int small_div(int a, int b) {
 }
 
 // Output-stationary spreading.  The workgroup (256 threads) owns a 16 x 16 x TZ
-// core of grid nodes; thread (tx, ty) keeps the z-column (tx, ty, 0..TZ-1) of
-// the core in registers for every component, so no accumulation ever needs an
-// atomic (LDS float atomics are slow on this hardware).  Candidate points,
-// those of the bins whose window starts can reach the core, are staged in LDS
-// in chunks of CH, compacted to the ones whose window overlaps the core, and
-// their 3P one-dimensional Gaussian factors are computed cooperatively into
-// LDS.  Every thread then walks the chunk's points in order (a fixed order, so
-// the result is deterministic): a wave whose 16 x 4 block of columns misses a
-// point's window skips it, and the point's z-range inside the core is a
-// wave-uniform (scalar) loop bound.
-template <typename T, int NC, int PMAX, int TZ, int CH>
+// core of grid nodes; each wave covers an 8 x 8 tile of its columns and each
+// thread keeps the z-column (x, y, 0..TZ-1) of the core in registers for every
+// component, so no accumulation ever needs an atomic (LDS float atomics are
+// slow on this hardware).  Candidate points, those of the bins whose window
+// starts can reach the core, are staged in LDS in chunks of CH, compacted to
+// the ones whose window overlaps the core, and their Gaussian factors at the
+// core's 16 + 16 + TZ node offsets (zero outside the window) are computed
+// cooperatively into LDS.  Every thread then walks the chunk's points in
+// order (a fixed order, so the result is deterministic): a wave whose tile
+// misses a point's window skips it, the point's z-factors come in as one
+// broadcast, and its z-range inside the core is a wave-uniform bound.
+template <typename T, int NC, int TZ, int CH>
 __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict__ tile_start,
                                                const int* __restrict__ bpack_s,
                                                const T* __restrict__ coff_s,
                                                const T* __restrict__ src_s, int64_t n, T* grid) {
-    __shared__ T s_w[CH][3][PMAX];
+    constexpr int NW = 32 + TZ;  // factors per point: x (16), y (16), z (TZ)
+    __shared__ __align__(16) T s_w[CH][NW];
     __shared__ T s_c[CH][3];
     __shared__ T s_v[CH][NC];
     __shared__ int s_bp[CH];
     __shared__ int s_cnt;
 
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
-    const int ncxy = (Mt + 15) / 16, ncz = (Mt + TZ - 1) / TZ;
+    const int ncxy = (Mt + 15) / 16;
     const int t = blockIdx.x;
     const int cx = t % ncxy, cy = (t / ncxy) % ncxy, cz = t / (ncxy * ncxy);
     const int bm = blockIdx.y;
     const int lox = cx * 16, loy = cy * 16, loz = cz * TZ;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wx0 = (wid & 1) * 8, wy0 = (wid >> 1) * 8;  // the wave's 8 x 8 tile in the core
+    const int tx = wx0 + (lane & 7), ty = wy0 + (lane >> 3);
     const int gx = lox + tx, gy = loy + ty;
     const T ahh = (T)g.ahh;
     const T half = (T)(0.5 * (P - 1));
@@ -106,26 +110,37 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                 }
                 __syncthreads();
                 const int cnt = s_cnt;
-                // 1D Gaussian factors of the compacted points
-                for (int q = threadIdx.x; q < cnt * 3 * P; q += 256) {
-                    const int k = q / (3 * P), r = q - k * 3 * P;
-                    const int d = r / P, i = r - d * P;
-                    const T e = s_c[k][d] + half - (T)i;
-                    s_w[k][d][i] = dexp<T>(-ahh * e * e);
+                // Gaussian factors at the core's node offsets, zero outside the window
+                for (int q = threadIdx.x; q < cnt * NW; q += 256) {
+                    const int k = small_div(q, NW), r = q - k * NW;
+                    const int d = r < 16 ? 0 : (r < 32 ? 1 : 2);
+                    const int o = r - 16 * d;
+                    const int bp = s_bp[k];
+                    const int b = d == 0 ? (bp & 1023) : (d == 1 ? ((bp >> 10) & 1023) : (bp >> 20));
+                    const int lo = d == 0 ? lox : (d == 1 ? loy : loz);
+                    const int i = lo + o - b;  // index inside the window
+                    T w = (T)0;
+                    if (i >= 0 && i < P) {
+                        const T e = s_c[k][d] + half - (T)i;
+                        w = dexp<T>(-ahh * e * e);
+                    }
+                    s_w[k][r] = w;
                 }
                 __syncthreads();
                 for (int k = 0; k < cnt; ++k) {
                     const int bp = __builtin_amdgcn_readfirstlane(s_bp[k]);
                     const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-                    const int ix = gx - bx, iy = gy - by;
-                    const bool in = (unsigned)ix < (unsigned)P && (unsigned)iy < (unsigned)P;
-                    if (!__any(in)) continue;
-                    const T wxy = in ? s_w[k][0][in ? ix : 0] * s_w[k][1][in ? iy : 0] : (T)0;
+                    // does the window reach this wave's 8 x 8 tile?
+                    if (bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 || by + P <= loy + wy0)
+                        continue;
+                    const T wxy = s_w[k][tx] * s_w[k][16 + ty];
                     T v[NC];
 #pragma unroll
                     for (int c = 0; c < NC; ++c) v[c] = s_v[k][c];
+                    T wz[TZ];
+#pragma unroll
+                    for (int z = 0; z < TZ; ++z) wz[z] = s_w[k][32 + z];
                     const int zlo = max(bz, loz) - loz, zhi = min(bz + P, loz + TZ) - loz;
-                    const T* wz = &s_w[k][2][loz - bz];
 #pragma unroll
                     for (int z = 0; z < TZ; ++z) {
                         if (z >= zlo && z < zhi) {
@@ -682,14 +697,10 @@ void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int 
     constexpr int TZ = sizeof(T) == 4 ? 16 : 8;
     const unsigned ncxy = (unsigned)((g.Mt + 15) / 16), ncz = (unsigned)((g.Mt + TZ - 1) / TZ);
     dim3 grd(ncxy * ncxy * ncz, batch);
-#define SPREAD(NC, PM, CHK)                                                                                  \
-    hipLaunchKernelGGL((k_spread<T, NC, PM, TZ, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s, \
+#define SPREAD(NC, CHK)                                                                                      \
+    hipLaunchKernelGGL((k_spread<T, NC, TZ, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,     \
                        p.coff_s, src_s, p.n, grid)
-    if (sizeof(T) == 4 && g.P <= 16) {
-        if (c_in == 3) SPREAD(3, 16, 128); else SPREAD(6, 16, 128);
-    } else {
-        if (c_in == 3) SPREAD(3, 32, 64); else SPREAD(6, 32, 64);
-    }
+    if (c_in == 3) SPREAD(3, 128); else SPREAD(6, 128);
 #undef SPREAD
 }
 
