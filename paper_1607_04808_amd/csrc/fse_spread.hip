@@ -140,13 +140,17 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                     T wz[TZ];
 #pragma unroll
                     for (int z = 0; z < TZ; ++z) wz[z] = s_w[k][32 + z];
+                    // z in groups of 4 that meet the window (the factors are zero outside it)
                     const int zlo = max(bz, loz) - loz, zhi = min(bz + P, loz + TZ) - loz;
 #pragma unroll
-                    for (int z = 0; z < TZ; ++z) {
-                        if (z >= zlo && z < zhi) {
-                            const T w = wxy * wz[z];
+                    for (int z4 = 0; z4 < TZ; z4 += 4) {
+                        if (z4 < zhi && z4 + 4 > zlo) {
 #pragma unroll
-                            for (int c = 0; c < NC; ++c) acc[z][c] += w * v[c];
+                            for (int z = z4; z < z4 + 4; ++z) {
+                                const T w = wxy * wz[z];
+#pragma unroll
+                                for (int c = 0; c < NC; ++c) acc[z][c] += w * v[c];
+                            }
                         }
                     }
                 }
