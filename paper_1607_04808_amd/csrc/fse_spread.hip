@@ -15,6 +15,7 @@
 // Quadrature: one workgroup per bin stages the (TB+P-1)^3 block of the field
 // that the bin's windows cover in LDS (when it fits) and each wave reduces one
 // point at a time from LDS; otherwise the field is read from global memory.
+#include <algorithm>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
 constexpr int CW = 8;  // waves per sweeping workgroup
 
 template <typename T, int MODE, int NCS>
-__global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int segb,
+__global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int segb, int ES, int PS,
                                                        const int* __restrict__ tile_start,
                                                        const int* __restrict__ perm_s,
                                                        const int* __restrict__ bpack_s,
@@ -349,7 +350,10 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     __shared__ __align__(16) T s_w[CW][6][32];
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
     const int X = KX * TB, E = X + P - 1, E2 = E * E, EZ = TB + P - 1;
-    const int CS = EZ * E2 + 4;  // component stride; 4 zero pads absorb the x-unroll overrun
+    // LDS layout: row stride ES >= E and plane stride PS >= E ES, padded so the
+    // lanes' rows fall in distinct banks; the padding is zero and absorbs the
+    // x-unroll overrun, as do 4 zero elements after each component
+    const int CS = EZ * PS + 4;
     const int64_t M3 = (int64_t)Mt * Mt * Mt;
     const int ncx = (nb + KX - 1) / KX;
     const int cx = blockIdx.x % ncx, cy = blockIdx.x / ncx;
@@ -365,13 +369,15 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     const int bm1 = MODE == 0 ? blockIdx.z + 1 : batch;
     const int bx0 = cx * KX, bx1 = min(nb, bx0 + KX) - 1;
     const int by0 = cy * KX, by1 = min(nb, by0 + KX) - 1;
-    // value of plane z, in-plane index t, component c of the current field
-    auto load = [&](const T* fb, int c, int z, int t) -> T {
+    // stage node (x, y) of plane z, component c of the current field into its ring slot
+    auto stage = [&](const T* fb, int c, int z, int t) {
         const int y = small_div(t, E), x = t - y * E;
         const int gx = lox + x, gy = loy + y;
-        if (gx < Mt && gy < Mt && z < Mt) return fb[(int64_t)c * M3 + ((int64_t)z * Mt + gy) * Mt + gx];
-        return (T)0;
+        T v = (T)0;
+        if (gx < Mt && gy < Mt && z < Mt) v = fb[(int64_t)c * M3 + ((int64_t)z * Mt + gy) * Mt + gx];
+        sm[c * CS + (z % EZ) * PS + y * ES + x] = v;
     };
+    for (int q = tid; q < NCS * CS; q += 64 * CW) sm[q] = (T)0;
     for (int bm = bm0; bm < bm1; ++bm) {
         for (int cs = 0; cs < 3; cs += NCS) {
             const T* fb = field + ((int64_t)bm * 3 + cs) * M3;
@@ -383,10 +389,8 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                     const int c = NCS == 1 ? 0 : small_div(q, EZ * E2);
                     const int r = q - c * EZ * E2;
                     const int pz = small_div(r, E2), t = r - pz * E2;
-                    const int z = tz0 * TB + pz;
-                    sm[c * CS + (z % EZ) * E2 + t] = load(fb, c, z, t);
+                    stage(fb, c, tz0 * TB + pz, t);
                 }
-                if (tid < NCS * 4) sm[(tid >> 2) * CS + EZ * E2 + (tid & 3)] = (T)0;
             }
             __syncthreads();
             for (int tz = tz0; tz < tz1; ++tz) {
@@ -399,8 +403,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                         const int c = NCS == 1 ? 0 : small_div(q, TB * E2);
                         const int r = q - c * TB * E2;
                         const int pz = small_div(r, E2), t = r - pz * E2;
-                        const int z = z0 - TB + EZ + pz;
-                        sm[c * CS + (z % EZ) * E2 + t] = load(fb, c, z, t);
+                        stage(fb, c, z0 - TB + EZ + pz, t);
                     }
                     __syncthreads();
                 }
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                             const int iz = small_div(r, P), iy = r - iz * P;
                             const int zz = bz + iz;
                             const int slot = zz - small_div(zz, EZ) * EZ;
-                            const T* row = sm + (slot * E + lby + iy) * E + lbx;
+                            const T* row = sm + slot * PS + (lby + iy) * ES + lbx;
                             T S[NCS], D[NCS];
 #pragma unroll
                             for (int c = 0; c < NCS; ++c) S[c] = D[c] = (T)0;
@@ -711,20 +714,54 @@ void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int 
 // Sweeping-quadrature configuration: components per pass, tile side in bins,
 // z-bins per workgroup and dynamic LDS bytes; ncs = 0 when it does not fit.
 struct ColCfg {
-    int ncs, kx, segb, nseg, ncol;
+    int ncs, kx, segb, nseg, ncol, es, ps;
     size_t lds;
 };
 
+// Worst LDS bank multiplicity of one quadrature read (64 lanes on window rows
+// r = l + 64 k, iy = r mod P, iz = r / P) for row stride es and plane stride ps
+// (elements of elem_bytes), summed over the passes, for 32 and 64 banks.
+static int bank_cost(int P, int es, int ps, int elem_bytes) {
+    const int wpe = elem_bytes / 4;
+    int tot = 0;
+    for (int nbk : {32, 64})
+        for (int base = 0; base < P * P; base += 64) {
+            int cnt[64] = {0};
+            int worst = 0;
+            for (int r = base; r < base + 64 && r < P * P; ++r) {
+                const int a = ((r / P) * ps + (r % P) * es) * wpe;
+                for (int w = 0; w < wpe; ++w) worst = std::max(worst, ++cnt[(a + w) % nbk]);
+            }
+            tot += worst;
+        }
+    return tot;
+}
+
 template <typename T> ColCfg col_config(const GridGeo& g) {
-    ColCfg best{0, 0, 0, 0, 0, 0};
+    ColCfg best{0, 0, 0, 0, 0, 0, 0, 0};
     const size_t limit = 160 * 1024 - CW * 6 * 32 * sizeof(T);
     // all components per pass when they fit; one-bin tiles measured as fast as
     // two-bin ones (less LDS, two workgroups per CU)
     const int opts[3][2] = {{3, 1}, {1, 2}, {1, 1}};
     for (auto& o : opts) {
         const int ncs = o[0], kx = o[1];
-        const size_t E = (size_t)kx * g.TS + g.P - 1, EZ = (size_t)g.TS + g.P - 1;
-        const size_t lds = ncs * (EZ * E * E + 4) * sizeof(T);
+        const int E = kx * g.TS + g.P - 1, EZ = g.TS + g.P - 1;
+        // padded strides with the fewest modelled bank conflicts that keep as
+        // many workgroups per CU as the unpadded layout
+        const size_t stat = CW * 6 * 32 * sizeof(T);
+        const size_t lds0 = ncs * ((size_t)EZ * E * E + 4) * sizeof(T);
+        if (lds0 > limit) continue;
+        const size_t per_cu0 = (160 * 1024) / (lds0 + stat);
+        const size_t budget = std::min(limit, (160 * 1024) / per_cu0 - stat);
+        int es = E, ps = E * E, cost = 1 << 30;
+        for (int e2 = E; e2 <= E + 3; ++e2)
+            for (int pad = 0; pad < 64; ++pad) {
+                const int p2 = e2 * E + pad;
+                if ((size_t)ncs * ((size_t)EZ * p2 + 4) * sizeof(T) > budget) break;
+                const int c = bank_cost(g.P, e2, p2, (int)sizeof(T)) * 256 + (e2 - E) * E + pad;
+                if (c < cost) { cost = c; es = e2; ps = p2; }
+            }
+        const size_t lds = ncs * ((size_t)EZ * ps + 4) * sizeof(T);
         if (lds > limit) continue;
         const int ncx = (g.nt + kx - 1) / kx;
         const int per_cu = (int)((160 * 1024) / (lds + CW * 6 * 32 * sizeof(T)));
@@ -732,7 +769,7 @@ template <typename T> ColCfg col_config(const GridGeo& g) {
         int nseg = (target + ncx * ncx - 1) / (ncx * ncx);
         nseg = nseg < 1 ? 1 : (nseg > g.nt ? g.nt : nseg);
         const int segb = (g.nt + nseg - 1) / nseg;
-        best = ColCfg{ncs, kx, segb, (g.nt + segb - 1) / segb, ncx * ncx, lds};
+        best = ColCfg{ncs, kx, segb, (g.nt + segb - 1) / segb, ncx * ncx, es, ps, lds};
         break;
     }
     return best;
@@ -746,7 +783,7 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
         const dim3 grd(cc.ncol, cc.nseg, batch);
 #define GCOL(NC)                                                                                               \
     allow_lds(k_gather_col<T, 0, NC>, cc.lds);                                                                 \
-    hipLaunchKernelGGL((k_gather_col<T, 0, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb,            \
+    hipLaunchKernelGGL((k_gather_col<T, 0, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
                        p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u,  \
                        (T*)nullptr)
         if (cc.ncs == 3) { GCOL(3); } else { GCOL(1); }
@@ -791,9 +828,9 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
 #define GCOLG(NC)                                                                                              \
     allow_lds(k_gather_col<T, 1, NC>, cc.lds);                                                                 \
     allow_lds(k_gather_col<T, 2, NC>, cc.lds);                                                                 \
-    hipLaunchKernelGGL((k_gather_col<T, 1, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb,            \
+    hipLaunchKernelGGL((k_gather_col<T, 1, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
                        p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);  \
-    hipLaunchKernelGGL((k_gather_col<T, 2, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb,            \
+    hipLaunchKernelGGL((k_gather_col<T, 2, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
                        p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n, batch, dsrc, dx)
         if (cc.ncs == 3) { GCOLG(3); } else { GCOLG(1); }
 #undef GCOLG
