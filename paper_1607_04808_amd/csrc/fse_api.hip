@@ -222,7 +222,8 @@ struct fse_plan {
     // points
     int *key_s, *rank_s, *key_r, *rank_r, *bpack, *perm_s, *bpack_s, *perm_r, *inv_r;
     void *coff, *coff_s, *x_r;
-    int *cnt_s, *start_s, *cnt_r, *start_r, *scan_tmp, *flag;
+    int *cnt_s, *start_s, *cnt_r, *start_r, *work_r, *scan_tmp, *flag;
+    int real_S = 256;
     int64_t ntiles3, ncells3;
     // sources
     void *src_s, *src_ra, *src_rb, *adj_s, *adj_r;
@@ -265,6 +266,8 @@ template <typename T> PointsDev<T> points(const fse_plan* p) {
     d.x_r = (const T*)p->x_r;
     d.cell_start = p->start_r;
     d.inv_r = p->inv_r;
+    d.work_start = p->work_r;
+    d.real_S = p->real_S;
     return d;
 }
 
@@ -297,6 +300,7 @@ template <typename T> fse_status_t allocate(fse_plan* p) {
     TRY(p->alloc(&p->start_s, p->ntiles3 + 1));
     TRY(p->alloc(&p->cnt_r, p->ncells3 + 1));
     TRY(p->alloc(&p->start_r, p->ncells3 + 1));
+    TRY(p->alloc(&p->work_r, p->ncells3 + 1));
     const size_t st = scan_tmp_ints(p->ntiles3 + 1) > scan_tmp_ints(p->ncells3 + 1)
                           ? scan_tmp_ints(p->ntiles3 + 1) : scan_tmp_ints(p->ncells3 + 1);
     TRY(p->alloc(&p->scan_tmp, st));
@@ -419,6 +423,10 @@ template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T*
                       p->bpack, (T*)p->coff, p->flag, st);
         launch_scan_exclusive(p->cnt_s, p->start_s, p->ntiles3 + 1, p->scan_tmp, st);
         launch_scan_exclusive(p->cnt_r, p->start_r, p->ncells3 + 1, p->scan_tmp, st);
+        // real-space work items: slices of up to real_S targets of one cell
+        p->real_S = (int)real_threads(n, p->ncells3);
+        launch_cell_slices(p->cnt_r, p->ncells3, p->real_S, st);
+        launch_scan_exclusive(p->cnt_r, p->work_r, p->ncells3 + 1, p->scan_tmp, st);
         launch_scatter<T>(x, n, p->key_s, p->rank_s, p->start_s, p->key_r, p->rank_r, p->start_r, p->bpack,
                           (const T*)p->coff, p->perm_s, p->bpack_s, (T*)p->coff_s, p->perm_r, (T*)p->x_r,
                           p->inv_r, st);

@@ -145,6 +145,13 @@ __global__ void k_permute3(const T* __restrict__ a, int64_t n, const int* __rest
     o[2] = ai[2];
 }
 
+// per-cell work items of the real-space pass: ceil(count / S); the extra entry is 0
+__global__ void k_cell_slices(int* cnt, int64_t ncells, int S) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells) cnt[c] = (cnt[c] + S - 1) / S;
+    else if (c == ncells) cnt[c] = 0;
+}
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -152,6 +159,10 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+void launch_cell_slices(int* cnt, int64_t ncells, int S, hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_slices, dim3(nblk(ncells + 1, 256)), dim3(256), 0, st, cnt, ncells, S);
 }
 
 size_t scan_tmp_ints(int64_t n) {

@@ -102,6 +102,9 @@ template <typename T> struct PointsDev {
     const T* x_r;             // positions (n,3), real-space order
     const int* cell_start;    // (ncell^3 + 1) offsets into real-space order
     const int* inv_r;         // user index -> real-space order
+    const int* work_start;    // (ncell^3 + 1) real-space work items: cell c owns items
+                              // [work_start[c], work_start[c+1]), each of up to real_S targets
+    int real_S;               // targets per real-space work item (= threads per workgroup)
 };
 
 // ---------------------------------------------------------------------------
@@ -109,6 +112,10 @@ template <typename T> struct PointsDev {
 // ---------------------------------------------------------------------------
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
 void launch_scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t st);
+// cnt[c] <- ceil(cnt[c] / S) for c < ncells, cnt[ncells] <- 0
+void launch_cell_slices(int* cnt, int64_t ncells, int S, hipStream_t st);
+// threads (= targets) per real-space work item for n points in ncells cells
+unsigned real_threads(int64_t n, int64_t ncells);
 size_t scan_tmp_ints(int64_t n);
 
 template <typename T>

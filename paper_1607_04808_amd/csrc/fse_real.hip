@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                                              const T* __restrict__ b_r, const T* __restrict__ w_r,
                                              int64_t n, int batch, T xi, T self_coef,
                                              const int* __restrict__ perm_r, T* out, int accumulate,
-                                             T* out2) {
+                                             T* out2, const int* __restrict__ work_start) {
     constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
     // sources per LDS chunk: 512, or 256 when the staged values are wide
     constexpr int CH = (NB * NS * sizeof(T) <= 24) ? 512 : 256;
@@ -130,10 +130,21 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     __shared__ unsigned short qd[QCAP][256];
     const int tid = threadIdx.x;
     const int nc = cg.ncell;
-    const int cell = blockIdx.x;
+    const int nthr = blockDim.x;
+    // work item -> (cell, slice): the last cell c with work_start[c] <= item
+    const int ncells = nc * nc * nc;
+    const int item = blockIdx.x;
+    if (item >= work_start[ncells]) return;
+    int lo = 0, hi = ncells;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (work_start[mid] <= item) lo = mid; else hi = mid;
+    }
+    const int cell = lo;
     const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
     const int b0 = blockIdx.y * NB;
-    const int t0 = cell_start[cell], t1 = cell_start[cell + 1];
+    const int t0 = cell_start[cell] + (item - work_start[cell]) * nthr;
+    const int t1 = min(cell_start[cell + 1], t0 + nthr);
     const T rc2 = (T)cg.rc2;
     // the candidate test uses |xl|^2 + |xs_l|^2 - 2 xl . xs_l in coordinates about
     // the cell corner, slightly widened (its rounding is ~1e-7 of rc^2 in FP32);
@@ -144,7 +155,6 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     const T c2x = (T)(2.0 * INV_SQRTPI) * xi;       // 2 xi / sqrt(pi)
     const T c4x3 = (T)(4.0 * INV_SQRTPI) * xi * xi2;  // 4 xi^3 / sqrt(pi)
     const T sgn = (KERNEL == FSE_STOKESLET) ? (T)1 : (T)-1;
-    const int nthr = blockDim.x;
     for (int tb = t0; tb < t1; tb += nthr) {
         const int j = tb + tid;
         const bool act = j < t1;
@@ -391,15 +401,16 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     }
 }
 
-// Threads per cell workgroup: whole waves covering a typical cell (mean plus
-// two standard deviations of a Poisson count), at most 256; fuller cells loop.
-unsigned real_threads(int64_t n, unsigned ncells) {
-    const double mean = (double)n / ncells;
+}  // namespace
+
+// Threads per work item (= targets per slice of a cell): whole waves covering a
+// typical cell (mean plus two standard deviations of a Poisson count), at most
+// 256; fuller cells are cut into several work items.
+unsigned real_threads(int64_t n, int64_t ncells) {
+    const double mean = (double)n / (double)ncells;
     const int waves = (int)std::ceil((mean + 2.0 * std::sqrt(mean)) / 64.0);
     return 64u * (unsigned)std::min(4, std::max(1, waves));
 }
-
-}  // namespace
 
 template <typename T>
 void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* src_a_r,
@@ -407,12 +418,14 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
                  hipStream_t st) {
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const int NBc = batch == 1 ? 1 : 4;
-    dim3 grd(ncells, (batch + NBc - 1) / NBc);
-    const unsigned thr = real_threads(p.n, ncells);
+    const unsigned thr = (unsigned)p.real_S;
+    // at most ceil(n / S) + ncells work items; the surplus workgroups return at once
+    const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
+    dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
     hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), 0, st, c, p.cell_start, p.x_r, src_a_r, \
                        src_b_r, (const T*)nullptr, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate,  \
-                       (T*)nullptr)
+                       (T*)nullptr, p.work_start)
     if (kernel == FSE_STOKESLET) {
         if (NBc == 1) LAUNCH(FSE_STOKESLET, 1); else LAUNCH(FSE_STOKESLET, 4);
     } else if (kernel == FSE_ROTLET) {
@@ -427,7 +440,8 @@ template <typename T>
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
                       int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st) {
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
-    const unsigned thr = real_threads(p.n, ncells);
+    const unsigned thr = (unsigned)p.real_S;
+    const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
     // batch members in groups of 4 per pass; each pass adds to dx (and dsrc)
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
@@ -435,8 +449,9 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
         const T* w = w_r + (int64_t)b0 * p.n * 3;
         T* ds = dsrc ? dsrc + (int64_t)b0 * p.n * 3 : nullptr;
 #define LAUNCHG(K, NB, WV)                                                                                \
-        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(ncells), dim3(thr), 0, st, c, p.cell_start, \
-                           p.x_r, f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)self_coef, p.perm_r, dx, 1, ds)
+        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(items), dim3(thr), 0, st, c, p.cell_start,  \
+                           p.x_r, f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)self_coef, p.perm_r, dx, 1, ds,   \
+                           p.work_start)
 #define LAUNCHK(K)                                                                                        \
         if (ds) { if (nb == 1) LAUNCHG(K, 1, true); else LAUNCHG(K, 4, true); }                           \
         else { if (nb == 1) LAUNCHG(K, 1, false); else LAUNCHG(K, 4, false); }
