@@ -226,7 +226,10 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                         const T q0 = ss[b][0][kk], q1 = ss[b][1][kk], q2 = ss[b][2][kk];
                         const T n0 = ss[b][3][kk], n1 = ss[b][4][kk], n2 = ss[b][5][kk];
                         const T hq = h0 * q0 + h1 * q1 + h2 * q2;
-                        const T hn = h0 * n0 + h1 * n1 + h2 * n2;
+                        // r . n in FP64: for sources on a smooth surface with n its normal,
+                        // r . n ~ r^2 / 2 cancels in the sum, so FP32 products would lose
+                        // it for close pairs (the FP32 products are exact in FP64)
+                        const T hn = (T)((double)r0 * n0 + (double)r1 * n1 + (double)r2v * n2) * ir;
                         const T nq = n0 * q0 + n1 * q1 + n2 * q2;
                         const T s1c = A1 * hn * hq + A2 * nq;
                         acc[b][0] += s1c * h0 + A2 * (n0 * hq + q0 * hn);
