@@ -41,6 +41,14 @@ template <int DIR, typename V> __device__ __forceinline__ V cmuli(V a) {
 // ---------------------------------------------------------------------------
 // cross-lane helpers
 // ---------------------------------------------------------------------------
+
+// floor(a / b) for 0 <= a < 2^21 and b >= 1 via a float reciprocal: (a + 0.5) / b
+// lies at least 1/(2b) from the integers on both sides, and the relative error
+// of (a + 0.5) * rcp(b) (about 1.5 ulp) keeps it within (a + 0.5) 2^-22.4 / b < 1/(2b).
+__device__ __forceinline__ int small_div(int a, int b) {
+    return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
+}
+
 __device__ __forceinline__ float readlane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }

@@ -182,9 +182,9 @@ __device__ void fft_lines(V* buf, int nl, int ld, const FftGeo& fg, const V* tw)
         const int nbf = n / r;
         const int tot = nl * nbf;
         for (int q = tid; q < tot; q += nthr) {
-            const int l = q / nbf;
+            const int l = small_div(q, nbf);
             const int b = q - l * nbf;
-            const int blk = b / m;
+            const int blk = small_div(b, m);
             const int n1 = b - blk * m;
             bf<V, INV>(r, buf + l * ld + blk * Ls + n1, m, n1 * ts, tw);
         }
@@ -316,7 +316,7 @@ __device__ __forceinline__ void kpoly(const T k[3], const C2<T>* g, C2<T>* w) {
 }
 
 template <typename T, int KERNEL, int CIN>
-__global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, C2<T>* __restrict__ B,
+__global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, int zc, C2<T>* __restrict__ B,
                                               const T* __restrict__ sig, double kscale,
                                               const C2<T>* __restrict__ twg,
                                               const int* __restrict__ revg) {
@@ -327,50 +327,55 @@ __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, C2<T>* __restr
     V* buf = tw + n;
     int* rev = (int*)(buf + CIN * n);
     load_tables(tw, rev, twg, revg, n);
-    const int ky = blockIdx.x, kx = blockIdx.y, bm = blockIdx.z;
+    const int kx = blockIdx.y, bm = blockIdx.z;
     const int64_t lstride = (int64_t)(Mt + 1) * n * Mt;  // between components
-    V* col = B + (int64_t)bm * CIN * lstride + ((int64_t)kx * n + ky) * Mt;
-#pragma unroll
-    for (int c = 0; c < CIN; ++c)
-        for (int z = threadIdx.x; z < n; z += blockDim.x)
-            buf[c * n + z] = (z < Mt) ? col[c * lstride + z] : cmk<V>((T)0, (T)0);
-    __syncthreads();
-    fft_lines<V, false>(buf, CIN, n, fg, tw);
-    // multiplier
-    const int kys = (ky < Mt) ? ky : ky - n;
-    const bool nyx = (kx == Mt), nyy = (ky == Mt);
+    const bool nyx = (kx == Mt);
     const T ks = (T)kscale;
     const int Mp = Mt + 1;
-    const T* sigrow = sig + ((int64_t)kx * Mp + (kys < 0 ? -kys : kys)) * Mp;
-    for (int p = threadIdx.x; p < n; p += blockDim.x) {
-        const int kzi = rev[p];
-        const int kzs = (kzi < Mt) ? kzi : kzi - n;
-        const bool nyz = (kzi == Mt);
-        V g[CIN];
+    // zc consecutive ky columns per workgroup: the tables above are loaded once
+    for (int ky = blockIdx.x * zc; ky < min(n, (int)(blockIdx.x + 1) * zc); ++ky) {
+        V* col = B + (int64_t)bm * CIN * lstride + ((int64_t)kx * n + ky) * Mt;
 #pragma unroll
-        for (int c = 0; c < CIN; ++c) g[c] = buf[c * n + p];
-        const T s = sigrow[kzs < 0 ? -kzs : kzs];
-        // wavenumbers in [-Mt, Mt): the Nyquist index carries -Mt in every direction
-        T k[3] = {ks * (T)(nyx ? -Mt : kx), ks * (T)kys, ks * (T)kzs};
-        V w[3];
-        kpoly<T, KERNEL>(k, g, w);
-        if (nyx || nyy || nyz) {
-            // Nyquist planes: use the Hermitian part of the multiplier, the mean
-            // of its values at k and at k with the Nyquist components negated.
-            T kr[3] = {nyx ? -k[0] : k[0], nyy ? -k[1] : k[1], nyz ? -k[2] : k[2]};
-            V wr[3];
-            kpoly<T, KERNEL>(kr, g, wr);
+        for (int c = 0; c < CIN; ++c)
+            for (int z = threadIdx.x; z < n; z += blockDim.x)
+                buf[c * n + z] = (z < Mt) ? col[c * lstride + z] : cmk<V>((T)0, (T)0);
+        __syncthreads();
+        fft_lines<V, false>(buf, CIN, n, fg, tw);
+        // multiplier
+        const int kys = (ky < Mt) ? ky : ky - n;
+        const bool nyy = (ky == Mt);
+        const T* sigrow = sig + ((int64_t)kx * Mp + (kys < 0 ? -kys : kys)) * Mp;
+        for (int p = threadIdx.x; p < n; p += blockDim.x) {
+            const int kzi = rev[p];
+            const int kzs = (kzi < Mt) ? kzi : kzi - n;
+            const bool nyz = (kzi == Mt);
+            V g[CIN];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) w[j] = cscale(cadd(w[j], wr[j]), (T)0.5);
+            for (int c = 0; c < CIN; ++c) g[c] = buf[c * n + p];
+            const T s = sigrow[kzs < 0 ? -kzs : kzs];
+            // wavenumbers in [-Mt, Mt): the Nyquist index carries -Mt in every direction
+            T k[3] = {ks * (T)(nyx ? -Mt : kx), ks * (T)kys, ks * (T)kzs};
+            V w[3];
+            kpoly<T, KERNEL>(k, g, w);
+            if (nyx || nyy || nyz) {
+                // Nyquist planes: use the Hermitian part of the multiplier, the mean
+                // of its values at k and at k with the Nyquist components negated.
+                T kr[3] = {nyx ? -k[0] : k[0], nyy ? -k[1] : k[1], nyz ? -k[2] : k[2]};
+                V wr[3];
+                kpoly<T, KERNEL>(kr, g, wr);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) w[j] = cscale(cadd(w[j], wr[j]), (T)0.5);
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) buf[j * n + p] = cscale(w[j], s);
         }
+        __syncthreads();
+        fft_lines<V, true>(buf, 3, n, fg, tw);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) buf[j * n + p] = cscale(w[j], s);
+        for (int c = 0; c < 3; ++c)
+            for (int z = threadIdx.x; z < Mt; z += blockDim.x) col[c * lstride + z] = buf[c * n + z];
+        __syncthreads();
     }
-    __syncthreads();
-    fft_lines<V, true>(buf, 3, n, fg, tw);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        for (int z = threadIdx.x; z < Mt; z += blockDim.x) col[c * lstride + z] = buf[c * n + z];
 }
 
 // ---------------------------------------------------------------------------
@@ -504,19 +509,20 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
     (void)revinv;
     const int Mt = g.Mt, n = fg.n;
     V* B = (V*)Bv;
-    dim3 grd(n, Mt + 1, batch);
+    constexpr int ZC = 4;  // ky columns per workgroup
+    dim3 grd((n + ZC - 1) / ZC, Mt + 1, batch);
     size_t sh = sizeof(V) * (size_t)n * (1 + c_in) + sizeof(int) * n;
     if (kernel == FSE_STOKESLET) {
         set_lds(k_fft_z<T, FSE_STOKESLET, 3>, sh);
-        hipLaunchKernelGGL((k_fft_z<T, FSE_STOKESLET, 3>), grd, dim3(128), sh, st, fg, Mt, B, sig,
+        hipLaunchKernelGGL((k_fft_z<T, FSE_STOKESLET, 3>), grd, dim3(128), sh, st, fg, Mt, ZC, B, sig,
                            kscale, (const V*)tw, rev);
     } else if (kernel == FSE_ROTLET) {
         set_lds(k_fft_z<T, FSE_ROTLET, 3>, sh);
-        hipLaunchKernelGGL((k_fft_z<T, FSE_ROTLET, 3>), grd, dim3(128), sh, st, fg, Mt, B, sig, kscale,
+        hipLaunchKernelGGL((k_fft_z<T, FSE_ROTLET, 3>), grd, dim3(128), sh, st, fg, Mt, ZC, B, sig, kscale,
                            (const V*)tw, rev);
     } else {
         set_lds(k_fft_z<T, FSE_STRESSLET, 6>, sh);
-        hipLaunchKernelGGL((k_fft_z<T, FSE_STRESSLET, 6>), grd, dim3(128), sh, st, fg, Mt, B, sig,
+        hipLaunchKernelGGL((k_fft_z<T, FSE_STRESSLET, 6>), grd, dim3(128), sh, st, fg, Mt, ZC, B, sig,
                            kscale, (const V*)tw, rev);
     }
 }

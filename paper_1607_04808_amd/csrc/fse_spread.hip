@@ -30,12 +30,6 @@ template <typename T> __device__ __forceinline__ T dexp(T x);
 template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 
-// floor(a / b) for 0 <= a < 2^21 and b >= 1 via a float reciprocal: (a + 0.5) / b
-// lies at least 1/(2b) from the integers on both sides, and the relative error
-// of (a + 0.5) * rcp(b) (about 1.5 ulp) keeps it within (a + 0.5) 2^-22.4 / b < 1/(2b).
-__device__ __forceinline__ int small_div(int a, int b) {
-    return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
-}
 
 // Output-stationary spreading.  The workgroup (256 threads) owns a 16 x 16 x TZ
 // core of grid nodes; each wave covers an 8 x 8 tile of its columns and each
