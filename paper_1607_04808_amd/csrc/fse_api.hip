@@ -610,6 +610,16 @@ fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
         L /= geo.radices[s];
         fg.ns = s + 1;
     }
+    // fuse adjacent stages greedily where the pair is supported
+    for (int s = 0; s < MAX_RADICES; ++s) fg.pair[s] = 0;
+    for (int s = 0; s + 1 < fg.ns;) {
+        if (fft_pair_ok(fg.rad[s], fg.rad[s + 1], dtype == FSE_F32 ? 4 : 8)) {
+            fg.pair[s] = 1;
+            s += 2;
+        } else {
+            s += 1;
+        }
+    }
     fse_status_t rc = dtype == FSE_F32 ? plan_init<float>(p) : plan_init<double>(p);
     if (rc != FSE_OK) {
         delete p;

@@ -97,7 +97,17 @@ struct FftGeo {
     int ns;                   // number of radix stages
     int rad[MAX_RADICES];     // radix per stage (DIF order)
     int Ls[MAX_RADICES];      // block length at each stage
+    int pair[MAX_RADICES];    // 1: stages s and s+1 run as one register-resident pass
 };
+
+// Stage pairs that run fused (both radices' butterflies of one element group
+// in registers): the product bounds the registers a thread holds.
+__host__ __device__ constexpr bool fft_pair_ok(int r1, int r2, int elem_bytes) {
+    return r1 * r2 <= (elem_bytes == 4 ? 32 : 16) &&
+           ((r1 == 8 && (r2 == 2 || r2 == 3 || r2 == 4)) || (r1 == 7 && (r2 == 2 || r2 == 3 || r2 == 4)) ||
+            (r1 == 5 && (r2 == 2 || r2 == 3 || r2 == 4 || r2 == 5)) || (r1 == 4 && r2 == 3) ||
+            (r1 == 2 && r2 == 3) || (r1 == 3 && r2 == 3));
+}
 
 // Points binned for one evaluation (device pointers)
 template <typename T> struct PointsDev {

@@ -170,23 +170,138 @@ __device__ __forceinline__ void bf(int r, V* p, int m, int tstep, const V* tw) {
     }
 }
 
-// All stages over `nl` lines of length n stored at buf + l*ld.  Barrier after
-// every stage (and none needed before the first: callers sync after loading).
+// Two DIF stages s, s+1 (radices R1, R2) on one element group in registers:
+// x[sub][i] = p[sub m + i mp] (m = Ls/R1, mp = m/R2); stage s transforms over
+// sub for each i (position n1 = n1p + i mp), stage s+1 over i for each sub.
+template <typename V, int R1, int R2>
+__device__ __forceinline__ void bf2_dif(V* p, int m, int mp, int n1p, int ts1, int ts2, const V* tw) {
+    V x[R1][R2];
+#pragma unroll
+    for (int a = 0; a < R1; ++a)
+#pragma unroll
+        for (int i = 0; i < R2; ++i) x[a][i] = p[a * m + i * mp];
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        V y[R1];
+#pragma unroll
+        for (int a = 0; a < R1; ++a) y[a] = x[a][i];
+        dft<V, R1, -1>(y);
+        const int n1 = n1p + i * mp;
+#pragma unroll
+        for (int k = 1; k < R1; ++k) y[k] = cmul(y[k], tw[ts1 * n1 * k]);
+#pragma unroll
+        for (int a = 0; a < R1; ++a) x[a][i] = y[a];
+    }
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+        dft<V, R2, -1>(x[a]);
+#pragma unroll
+        for (int k = 1; k < R2; ++k) x[a][k] = cmul(x[a][k], tw[ts2 * n1p * k]);
+    }
+#pragma unroll
+    for (int a = 0; a < R1; ++a)
+#pragma unroll
+        for (int i = 0; i < R2; ++i) p[a * m + i * mp] = x[a][i];
+}
+// The matching inverse of stages s+1 then s (DIT, conjugate twiddles first):
+// E[a][i] = p[a Ls1 + i m1] with Ls1 = Ls[s+1], m1 = Ls1/R2; stage s+1 over i
+// for each a (position n1), then stage s over a for each i (position n1 + i m1).
+template <typename V, int R1, int R2>
+__device__ __forceinline__ void bf2_dit_inv(V* p, int Ls1, int m1, int n1, int ts1, int ts2, const V* tw) {
+    V x[R1][R2];
+#pragma unroll
+    for (int a = 0; a < R1; ++a)
+#pragma unroll
+        for (int i = 0; i < R2; ++i) x[a][i] = p[a * Ls1 + i * m1];
+#pragma unroll
+    for (int a = 0; a < R1; ++a) {
+#pragma unroll
+        for (int k = 1; k < R2; ++k) x[a][k] = cmulc(x[a][k], tw[ts2 * n1 * k]);
+        dft<V, R2, 1>(x[a]);
+    }
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        V y[R1];
+        y[0] = x[0][i];
+        const int n1s = n1 + i * m1;
+#pragma unroll
+        for (int k = 1; k < R1; ++k) y[k] = cmulc(x[k][i], tw[ts1 * n1s * k]);
+        dft<V, R1, 1>(y);
+#pragma unroll
+        for (int a = 0; a < R1; ++a) x[a][i] = y[a];
+    }
+#pragma unroll
+    for (int a = 0; a < R1; ++a)
+#pragma unroll
+        for (int i = 0; i < R2; ++i) p[a * Ls1 + i * m1] = x[a][i];
+}
+
+#define FSE_FFT_PAIRS(X) \
+    X(8, 2) X(8, 3) X(8, 4) X(7, 2) X(7, 3) X(7, 4) X(5, 2) X(5, 3) X(5, 4) X(5, 5) X(4, 3) X(2, 3) X(3, 3)
+
+template <typename V, bool INV>
+__device__ __forceinline__ void bf2(int r1, int r2, V* p, int a, int b, int n1, int ts1, int ts2, const V* tw) {
+    switch (r1 * 16 + r2) {
+#define FSE_CASE(R1, R2)                                                          \
+    case R1 * 16 + R2:                                                            \
+        if constexpr (fft_pair_ok(R1, R2, (int)sizeof(V) / 2)) {                  \
+            if (INV) bf2_dit_inv<V, R1, R2>(p, a, b, n1, ts1, ts2, tw);           \
+            else bf2_dif<V, R1, R2>(p, a, b, n1, ts1, ts2, tw);                   \
+        }                                                                         \
+        break;
+        FSE_FFT_PAIRS(FSE_CASE)
+#undef FSE_CASE
+        default: break;
+    }
+}
+
+// All stages over `nl` lines of length n stored at buf + l*ld, single stages
+// or fused pairs (FftGeo::pair).  Barrier after every pass (and none needed
+// before the first: callers sync after loading).
 template <typename V, bool INV>
 __device__ void fft_lines(V* buf, int nl, int ld, const FftGeo& fg, const V* tw) {
     const int n = fg.n;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int si = 0; si < fg.ns; ++si) {
+    int si = 0;
+    while (si < fg.ns) {
+        // stage s in DIF numbering; the inverse runs the stages backwards
         const int s = INV ? fg.ns - 1 - si : si;
-        const int r = fg.rad[s], Ls = fg.Ls[s], m = Ls / r, ts = n / Ls;
-        const int nbf = n / r;
-        const int tot = nl * nbf;
-        for (int q = tid; q < tot; q += nthr) {
-            const int l = small_div(q, nbf);
-            const int b = q - l * nbf;
-            const int blk = small_div(b, m);
-            const int n1 = b - blk * m;
-            bf<V, INV>(r, buf + l * ld + blk * Ls + n1, m, n1 * ts, tw);
+        const bool fused = INV ? (s >= 1 && fg.pair[s - 1]) : (fg.pair[s] != 0);
+        if (fused) {
+            const int s0 = INV ? s - 1 : s;  // the pair is (s0, s0 + 1)
+            const int r1 = fg.rad[s0], r2 = fg.rad[s0 + 1];
+            const int Ls = fg.Ls[s0], m = Ls / r1, mp = m / r2;
+            const int ts1 = n / Ls, ts2 = n / m;
+            const int ngrp = n / (r1 * r2);
+            const int tot = nl * ngrp;
+            for (int q = tid; q < tot; q += nthr) {
+                const int l = small_div(q, ngrp);
+                const int g = q - l * ngrp;
+                if (!INV) {
+                    // groups: block of stage s0, position n1p < mp
+                    const int blk = small_div(g, mp);
+                    const int n1p = g - blk * mp;
+                    bf2<V, false>(r1, r2, buf + l * ld + blk * Ls + n1p, m, mp, n1p, ts1, ts2, tw);
+                } else {
+                    // groups: block of stage s0, position n1 < mp within a block of stage s0 + 1
+                    const int blk = small_div(g, mp);
+                    const int n1 = g - blk * mp;
+                    bf2<V, true>(r1, r2, buf + l * ld + blk * Ls + n1, m, mp, n1, ts1, ts2, tw);
+                }
+            }
+            si += 2;
+        } else {
+            const int r = fg.rad[s], Ls = fg.Ls[s], m = Ls / r, ts = n / Ls;
+            const int nbf = n / r;
+            const int tot = nl * nbf;
+            for (int q = tid; q < tot; q += nthr) {
+                const int l = small_div(q, nbf);
+                const int b = q - l * nbf;
+                const int blk = small_div(b, m);
+                const int n1 = b - blk * m;
+                bf<V, INV>(r, buf + l * ld + blk * Ls + n1, m, n1 * ts, tw);
+            }
+            si += 1;
         }
         __syncthreads();
     }
