@@ -13,6 +13,8 @@ which also gives the sampled relative error) are extra fields.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import math
 import os
@@ -75,6 +77,90 @@ def stage_work(stage, geo, n, P, dtype, pairs, c_in=3, batch=1):
     return None, None
 
 
+# Kernels behind each timed stage (FP32 / FP64 template names as rocprofv3 lists them)
+# and the sources that define them, for the counter-based HBM traffic.
+STAGE_KERNELS = {
+    "real": (["k_real<{T}, 0, 1, false, false>"], "fse_real.hip"),
+    "real_grad": (["k_real<{T}, 0, 1, true, true>"], "fse_real.hip"),
+    "spread": (["k_spread<{T}, 3,"], "fse_spread.hip"),
+    "gather": (["k_gather_col<{T}, 0, "], "fse_spread.hip"),
+    "gather_grad": (["k_gather_col<{T}, 1, ", "k_gather_col<{T}, 2, "], "fse_spread.hip"),
+    "fft_x": (["k_fft_x<{T},"], "fse_fft.hip"),
+    "fft_y": (["k_fft_y<{T},"], "fse_fft.hip"),
+    "fft_z_scale": (["k_fft_z<{T}, 0, 3>"], "fse_fft.hip"),
+    "fft_yinv": (["k_fft_yinv<{T},"], "fse_fft.hip"),
+    "fft_xinv": (["k_fft_xinv<{T},"], "fse_fft.hip"),
+}
+CSRC = os.path.join(ROOT, "paper_1607_04808_amd", "csrc")
+
+
+def source_hash(name):
+    """sha256 of a kernel source and the shared header, to tell stale counters."""
+    h = hashlib.sha256()
+    for f in (name, "fse_common.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(form):
+    return os.path.join(ROOT, "profiles", "traffic_stokeslet_n1m_%s.json" % form)
+
+
+def traffic_from_counters(fetch_csv, write_csv, form, copy_bytes):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of each stage's kernels from two
+    rocprofv3 --pmc runs, with the plain copy kernel's readings for scaling."""
+    def load(path, counter):
+        per = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"].replace("fse::(anonymous namespace)::", "").replace("void ", "")
+                per.setdefault(name, {}).setdefault(r["Dispatch_Id"], 0.0)
+                per[name][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return {k: list(v.values()) for k, v in per.items()}
+    fetch_d, write_d = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    # the probe is the largest plain copy; kernels of a stage: mean per dispatch
+    copy = "__amd_rocclr_copyBuffer"
+    out = {"form": form, "copy_probe": {"bytes": copy_bytes, "fetch_kib": max(fetch_d[copy]),
+                                         "write_kib": max(write_d[copy])},
+           "stages": {}}
+    fetch = {k: sum(v) / len(v) for k, v in fetch_d.items()}
+    write = {k: sum(v) / len(v) for k, v in write_d.items()}
+    T = "float" if form == "f32" else "double"
+    for stage, (pats, src) in STAGE_KERNELS.items():
+        f = w = 0.0
+        found = False
+        for pat in pats:
+            pat = pat.format(T=T)
+            names = [k for k in fetch if k.startswith(pat)]
+            if names:
+                found = True
+                f += sum(fetch[k] for k in names)
+                w += sum(write.get(k, 0.0) for k in names)
+        if found:
+            out["stages"][stage] = {"fetch_kib": f, "write_kib": w, "source": src, "sha": source_hash(src)}
+    return out
+
+
+def stage_traffic(form, stage):
+    """HBM bytes per launch group of `stage` from the committed counter readings,
+    scaled by the copy kernel's; None when absent or the kernel source changed."""
+    try:
+        with open(traffic_path(form)) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    st = t.get("stages", {}).get(stage)
+    if not st or st["sha"] != source_hash(st["source"]):
+        return None
+    cp = t["copy_probe"]
+    sf = cp["bytes"] / (cp["fetch_kib"] * 1024.0)
+    sw = cp["bytes"] / (cp["write_kib"] * 1024.0)
+    return st["fetch_kib"] * 1024.0 * sf + st["write_kib"] * 1024.0 * sw
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,7 +173,19 @@ def main():
     ap.add_argument("--forms", default="f32,f64")
     ap.add_argument("--set", action="append", default=[], metavar="FORM.KEY=VALUE",
                     help="override a parameter of a form, e.g. f32.xi=90 (repeatable)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter scaling)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-stage HBM traffic file from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        form = args.forms.split(",")[0]
+        t = traffic_from_counters(args.traffic_from[0], args.traffic_from[1], form,
+                                  args.copy_probe_mb * 2 ** 20)
+        with open(traffic_path(form), "w") as fh:
+            json.dump(t, fh, indent=1, sort_keys=True)
+        print("wrote", traffic_path(form))
+        return
     for item in args.set:
         key, val = item.split("=", 1)
         form, name = key.split(".", 1)
@@ -103,6 +201,12 @@ def main():
     import paper_1607_04808_amd as F
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb * 2 ** 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = args.n
     cfg_id = 0
     x64 = W.uniform_cube(n, 1000 + cfg_id)
@@ -184,12 +288,14 @@ def main():
     # dominant kernel and its roofline
     dom_name, dom = max(head["stages"].items(), key=lambda kv: kv[1]["ms_per_step"])
     peak_alu = PEAK["f32_TFLOPs"] if head_form == "f32" else PEAK["f64_TFLOPs"]
+    tr = stage_traffic(head_form, dom_name)
+    tr = round(tr) if tr is not None else None
     if dom["GBs"] is not None and dom["TFLOPs"] is None:
         roof = dict(kernel=dom_name, bound="hbm", achieved=round(dom["GBs"], 1), peak=PEAK["hbm_GBs"],
-                    unit="GB/s", frac=round(dom["GBs"] / PEAK["hbm_GBs"], 4), traffic=None)
+                    unit="GB/s", frac=round(dom["GBs"] / PEAK["hbm_GBs"], 4), traffic=tr)
     else:
         roof = dict(kernel=dom_name, bound="alu", achieved=round(dom["TFLOPs"], 2), peak=peak_alu,
-                    unit="TFLOP/s", frac=round(dom["TFLOPs"] / peak_alu, 4), traffic=None)
+                    unit="TFLOP/s", frac=round(dom["TFLOPs"] / peak_alu, 4), traffic=tr)
 
     line = {
         "metric": "stokeslet targets/s at 1e-6 rel err, N=1M; fwd+adjoint; FP32 vs FP64 form",
