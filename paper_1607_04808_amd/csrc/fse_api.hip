@@ -311,8 +311,8 @@ template <typename T> fse_status_t allocate(fse_plan* p) {
     TRY(p->alloc((T**)&p->adj_s, B * nm * 3));
     TRY(p->alloc((T**)&p->adj_r, B * nm * 3));
     TRY(p->alloc((T**)&p->grid, B * p->c_in * M3));
-    TRY(p->alloc((V**)&p->A, B * p->c_in * Mp * Mt * Mt));
-    TRY(p->alloc((V**)&p->B, B * p->c_in * Mp * n * Mt));
+    TRY(p->alloc((V**)&p->A, B * p->c_in * Mp * Mt * (size_t)p->fg.sy));
+    TRY(p->alloc((V**)&p->B, B * p->c_in * Mp * n * (size_t)p->fg.sz));
     TRY(p->alloc((T**)&p->phi, B * 3 * M3));
     TRY(p->alloc((T**)&p->phi_w, p->kernel == FSE_STRESSLET ? 1 : B * 3 * M3));
     TRY(p->alloc(&p->sig64, Mp * Mp * Mp));
@@ -609,6 +609,12 @@ fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
         fg.Ls[s] = L;
         L /= geo.radices[s];
         fg.ns = s + 1;
+    }
+    // y- and z-line strides of the intermediate spectra padded to 128 bytes, so the
+    // 16 (FP32) or 8 (FP64) lines a pass moves together start on a cache line
+    {
+        const int aln = 128 / (dtype == FSE_F32 ? 8 : 16);
+        fg.sy = fg.sz = (geo.Mt + aln - 1) / aln * aln;
     }
     // fuse adjacent stages greedily where the pair is supported
     for (int s = 0; s < MAX_RADICES; ++s) fg.pair[s] = 0;

@@ -98,6 +98,8 @@ struct FftGeo {
     int rad[MAX_RADICES];     // radix per stage (DIF order)
     int Ls[MAX_RADICES];      // block length at each stage
     int pair[MAX_RADICES];    // 1: stages s and s+1 run as one register-resident pass
+    int sy, sz;               // padded line strides (elements) of the y- and z-lines of the
+                              // intermediate spectra, multiples of 128 bytes
 };
 
 // Stage pairs that run fused (both radices' butterflies of one element group

@@ -345,7 +345,8 @@ __global__ __launch_bounds__(256) void k_fft_x(FftGeo fg, int Mt, const T* __res
     }
     __syncthreads();
     fft_lines<V, false>(buf, ROWS / 2, n, fg, tw);
-    V* dst = A + (int64_t)bc * (Mt + 1) * M2 + (int64_t)z * Mt + y0;
+    const int64_t MA = (int64_t)Mt * fg.sy;  // one kx slab of A
+    V* dst = A + (int64_t)bc * (Mt + 1) * MA + (int64_t)z * fg.sy + y0;
     for (int q = threadIdx.x; q < (Mt + 1) * ROWS; q += blockDim.x) {
         const int kx = q / ROWS, r = q % ROWS;
         if (y0 + r >= Mt) continue;
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(256) void k_fft_x(FftGeo fg, int Mt, const T* __res
         V X;
         if (r & 1) X = cmk<V>((T)0.5 * (zk.y + zn.y), (T)0.5 * (zn.x - zk.x));
         else X = cmk<V>((T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y));
-        dst[(int64_t)kx * M2 + r] = X;
+        dst[(int64_t)kx * MA + r] = X;
     }
 }
 
@@ -374,19 +375,19 @@ __global__ __launch_bounds__(256) void k_fft_y(FftGeo fg, int Mt, const C2<T>* _
     int* revinv = (int*)(buf + LZ * n);
     load_tables(tw, revinv, twg, revinvg, n);
     const int z0 = blockIdx.x * LZ, kx = blockIdx.y, bc = blockIdx.z;
-    const int64_t M2 = (int64_t)Mt * Mt;
-    const V* src = A + ((int64_t)bc * (Mt + 1) + kx) * M2;
+    const int SY = fg.sy, SZ = fg.sz;
+    const V* src = A + ((int64_t)bc * (Mt + 1) + kx) * Mt * SY;
     for (int l = 0; l < LZ; ++l) {
         const int z = z0 + l;
         for (int y = threadIdx.x; y < n; y += blockDim.x)
-            buf[l * n + y] = (y < Mt && z < Mt) ? src[(int64_t)z * Mt + y] : cmk<V>((T)0, (T)0);
+            buf[l * n + y] = (y < Mt && z < Mt) ? src[(int64_t)z * SY + y] : cmk<V>((T)0, (T)0);
     }
     __syncthreads();
     fft_lines<V, false>(buf, LZ, n, fg, tw);
-    V* dst = B + ((int64_t)bc * (Mt + 1) + kx) * n * Mt;
+    V* dst = B + ((int64_t)bc * (Mt + 1) + kx) * n * SZ;
     for (int q = threadIdx.x; q < n * LZ; q += blockDim.x) {
         const int ky = q / LZ, r = q % LZ;
-        if (z0 + r < Mt) dst[(int64_t)ky * Mt + z0 + r] = buf[r * n + revinv[ky]];
+        if (z0 + r < Mt) dst[(int64_t)ky * SZ + z0 + r] = buf[r * n + revinv[ky]];
     }
 }
 
@@ -443,13 +444,13 @@ __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, int zc, C2<T>*
     int* rev = (int*)(buf + CIN * n);
     load_tables(tw, rev, twg, revg, n);
     const int kx = blockIdx.y, bm = blockIdx.z;
-    const int64_t lstride = (int64_t)(Mt + 1) * n * Mt;  // between components
+    const int64_t lstride = (int64_t)(Mt + 1) * n * fg.sz;  // between components
     const bool nyx = (kx == Mt);
     const T ks = (T)kscale;
     const int Mp = Mt + 1;
     // zc consecutive ky columns per workgroup: the tables above are loaded once
     for (int ky = blockIdx.x * zc; ky < min(n, (int)(blockIdx.x + 1) * zc); ++ky) {
-        V* col = B + (int64_t)bm * CIN * lstride + ((int64_t)kx * n + ky) * Mt;
+        V* col = B + (int64_t)bm * CIN * lstride + ((int64_t)kx * n + ky) * fg.sz;
 #pragma unroll
         for (int c = 0; c < CIN; ++c)
             for (int z = threadIdx.x; z < n; z += blockDim.x)
@@ -511,19 +512,19 @@ __global__ __launch_bounds__(256) void k_fft_yinv(FftGeo fg, int Mt, int c_in,
     const int z0 = blockIdx.x * LZ, kx = blockIdx.y;
     const int bm = blockIdx.z / 3, c = blockIdx.z % 3;
     const int64_t bc = (int64_t)bm * c_in + c;
-    const int64_t M2 = (int64_t)Mt * Mt;
-    const V* src = B + (bc * (Mt + 1) + kx) * n * Mt;
+    const int SY = fg.sy, SZ = fg.sz;
+    const V* src = B + (bc * (Mt + 1) + kx) * n * SZ;
     for (int q = threadIdx.x; q < n * LZ; q += blockDim.x) {
         const int ky = q / LZ, r = q % LZ;
-        buf[r * n + revinv[ky]] = (z0 + r < Mt) ? src[(int64_t)ky * Mt + z0 + r] : cmk<V>((T)0, (T)0);
+        buf[r * n + revinv[ky]] = (z0 + r < Mt) ? src[(int64_t)ky * SZ + z0 + r] : cmk<V>((T)0, (T)0);
     }
     __syncthreads();
     fft_lines<V, true>(buf, LZ, n, fg, tw);
-    V* dst = A + (bc * (Mt + 1) + kx) * M2;
+    V* dst = A + (bc * (Mt + 1) + kx) * Mt * SY;
     for (int l = 0; l < LZ; ++l) {
         const int z = z0 + l;
         if (z >= Mt) break;
-        for (int y = threadIdx.x; y < Mt; y += blockDim.x) dst[(int64_t)z * Mt + y] = buf[l * n + y];
+        for (int y = threadIdx.x; y < Mt; y += blockDim.x) dst[(int64_t)z * SY + y] = buf[l * n + y];
     }
 }
 
@@ -548,10 +549,11 @@ __global__ __launch_bounds__(256) void k_fft_xinv(FftGeo fg, int Mt, int c_in,
     const int bm = blockIdx.z / 3, c = blockIdx.z % 3;
     const int64_t bc = (int64_t)bm * c_in + c, fc = (int64_t)bm * 3 + c;
     const int64_t M2 = (int64_t)Mt * Mt;
-    const V* src = A + bc * Mp * M2 + (int64_t)z * Mt + y0;
+    const int64_t MA = (int64_t)Mt * fg.sy;  // one kx slab of A
+    const V* src = A + bc * Mp * MA + (int64_t)z * fg.sy + y0;
     for (int q = threadIdx.x; q < Mp * ROWS; q += blockDim.x) {
         const int kx = q / ROWS, r = q % ROWS;
-        H[r * Mp + kx] = (y0 + r < Mt) ? src[(int64_t)kx * M2 + r] : cmk<V>((T)0, (T)0);
+        H[r * Mp + kx] = (y0 + r < Mt) ? src[(int64_t)kx * MA + r] : cmk<V>((T)0, (T)0);
     }
     __syncthreads();
     for (int l = 0; l < ROWS / 2; ++l) {

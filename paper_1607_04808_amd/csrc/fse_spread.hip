@@ -350,17 +350,22 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     const int CS = EZ * PS + 4;
     const int64_t M3 = (int64_t)Mt * Mt * Mt;
     const int ncx = (nb + KX - 1) / KX;
-    const int cx = blockIdx.x % ncx, cy = blockIdx.x / ncx;
+    // work item: column (x fastest) then z-segment; surplus items return
+    const int nwork = ncx * ncx * ((nb + segb - 1) / segb);
+    const int w = (int)blockIdx.x;
+    if (w >= nwork) return;
+    const int col = w % (ncx * ncx), seg = w / (ncx * ncx);
+    const int cx = col % ncx, cy = col / ncx;
     const int lox = cx * X, loy = cy * X;
-    const int tz0 = blockIdx.y * segb, tz1 = min(nb, tz0 + segb);
+    const int tz0 = seg * segb, tz1 = min(nb, tz0 + segb);
     if (tz0 >= tz1) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const T ahh = (T)g.ahh;
     const T dfac = (T)(-2.0 * g.ahh / g.h);
     const T half = (T)(0.5 * (P - 1));
     const int PP = P * P, P4 = (P + 3) & ~3;
-    const int bm0 = MODE == 0 ? blockIdx.z : 0;
-    const int bm1 = MODE == 0 ? blockIdx.z + 1 : batch;
+    const int bm0 = MODE == 0 ? blockIdx.y : 0;
+    const int bm1 = MODE == 0 ? blockIdx.y + 1 : batch;
     const int bx0 = cx * KX, bx1 = min(nb, bx0 + KX) - 1;
     const int by0 = cy * KX, by1 = min(nb, by0 + KX) - 1;
     // stage node (x, y) of plane z, component c of the current field into its ring slot
@@ -774,7 +779,7 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
                    hipStream_t st) {
     const ColCfg cc = col_config<T>(g);
     if (cc.ncs) {
-        const dim3 grd(cc.ncol, cc.nseg, batch);
+        const dim3 grd(cc.ncol * cc.nseg, batch);
 #define GCOL(NC)                                                                                               \
     allow_lds(k_gather_col<T, 0, NC>, cc.lds);                                                                 \
     hipLaunchKernelGGL((k_gather_col<T, 0, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
@@ -817,7 +822,7 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
     }
     const ColCfg cc = col_config<T>(g);
     if (cc.ncs) {
-        const dim3 grd(cc.ncol, cc.nseg, 1);
+        const dim3 grd(cc.ncol * cc.nseg, 1);
         // pass 1: forward field contracted with w; pass 2: phi_w value and contraction with f
 #define GCOLG(NC)                                                                                              \
     allow_lds(k_gather_col<T, 1, NC>, cc.lds);                                                                 \
