@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     __shared__ Pos4<T> xs[CH];  // source positions
     __shared__ Pos4<T> xq[CH];  // test form: -2 (x - o), |x - o|^2 about the cell corner o
     __shared__ T ss[NB][NS][CH];
-    __shared__ unsigned short qd[QCAP][256];
+    extern __shared__ unsigned short qd[];  // hit queues: QCAP rows of blockDim.x entries
     const int tid = threadIdx.x;
     const int nc = cg.ncell;
     const int nthr = blockDim.x;
@@ -183,8 +183,8 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             }
         T g0 = 0, g1 = 0, g2 = 0;
         // this thread's hit queue: column tid of qd, QROW entries per row
-        constexpr int QROW = 256;
-        unsigned short* const q0 = &qd[0][tid];
+        const int QROW = nthr;
+        unsigned short* const q0 = qd + tid;
         unsigned short* const qlim = q0 + (QCAP - 8) * QROW;
         unsigned short* qp = q0;
         const bool wave_active = __any(act);
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             }
         };
         auto flush = [&]() {
-            const int qn = (int)(qp - q0) / QROW;
+            const int qn = small_div((int)(qp - q0), QROW);
             for (int e = 0; __any(e < qn); ++e)
                 if (e < qn) eval((int)q0[e * QROW]);
             qp = q0;
@@ -406,12 +406,12 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
 
 }  // namespace
 
-// Threads per work item (= targets per slice of a cell): whole waves covering a
-// typical cell (mean plus two standard deviations of a Poisson count), at most
-// 256; fuller cells are cut into several work items.
+// Threads per work item (= targets per slice of a cell): the whole waves that
+// hold a cell of mean occupancy, at most 256; fuller cells are cut into several
+// work items, so no wave of a workgroup sits idle for the typical cell.
 unsigned real_threads(int64_t n, int64_t ncells) {
     const double mean = (double)n / (double)ncells;
-    const int waves = (int)std::ceil((mean + 2.0 * std::sqrt(mean)) / 64.0);
+    const int waves = (int)std::ceil(mean / 64.0);
     return 64u * (unsigned)std::min(4, std::max(1, waves));
 }
 
@@ -424,9 +424,10 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned thr = (unsigned)p.real_S;
     // at most ceil(n / S) + ncells work items; the surplus workgroups return at once
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
+    const size_t qbytes = (size_t)QCAP * thr * sizeof(unsigned short);
     dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
-    hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), 0, st, c, p.cell_start, p.x_r, src_a_r, \
+    hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p.cell_start, p.x_r, src_a_r, \
                        src_b_r, (const T*)nullptr, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate,  \
                        (T*)nullptr, p.work_start)
     if (kernel == FSE_STOKESLET) {
@@ -445,6 +446,7 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.real_S;
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
+    const size_t qbytes = (size_t)QCAP * thr * sizeof(unsigned short);
     // batch members in groups of 4 per pass; each pass adds to dx (and dsrc)
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
@@ -452,7 +454,7 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
         const T* w = w_r + (int64_t)b0 * p.n * 3;
         T* ds = dsrc ? dsrc + (int64_t)b0 * p.n * 3 : nullptr;
 #define LAUNCHG(K, NB, WV)                                                                                \
-        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(items), dim3(thr), 0, st, c, p.cell_start,  \
+        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(items), dim3(thr), qbytes, st, c, p.cell_start,  \
                            p.x_r, f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)self_coef, p.perm_r, dx, 1, ds,   \
                            p.work_start)
 #define LAUNCHK(K)                                                                                        \
