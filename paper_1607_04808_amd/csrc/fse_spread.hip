@@ -330,7 +330,7 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
 // ---------------------------------------------------------------------------
 constexpr int CW = 8;  // waves per sweeping workgroup
 
-template <typename T, int MODE, int NCS>
+template <typename T, int MODE, int NCS, int GP>
 __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int segb, int ES, int PS,
                                                        const int* __restrict__ tile_start,
                                                        const int* __restrict__ perm_s,
@@ -339,11 +339,14 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                                                        const T* __restrict__ field,
                                                        const T* __restrict__ vec_s, int64_t n, int batch,
                                                        T* out, T* dx) {
+    constexpr int GL = 64 / GP;  // lanes per point: a wave works on GP points at once
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* sm = (T*)smem_raw;
-    __shared__ __align__(16) T s_w[CW][6][32];
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
     const int X = KX * TB, E = X + P - 1, E2 = E * E, EZ = TB + P - 1;
+    const int P4 = (P + 3) & ~3;
+    // after the ring: per wave and point, the 1-D factors wx, wy, wz, dwx, dwy, dwz
+    // (P4 each, zero beyond P)
     // LDS layout: row stride ES >= E and plane stride PS >= E ES, padded so the
     // lanes' rows fall in distinct banks; the padding is zero and absorbs the
     // x-unroll overrun, as do 4 zero elements after each component
@@ -363,7 +366,11 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     const T ahh = (T)g.ahh;
     const T dfac = (T)(-2.0 * g.ahh / g.h);
     const T half = (T)(0.5 * (P - 1));
-    const int PP = P * P, P4 = (P + 3) & ~3;
+    const int PP = P * P;
+    const int grp = GP == 1 ? 0 : lane / GL, gl = GP == 1 ? lane : lane % GL;
+    // this group's factors, 16-byte aligned (the ring is rounded up to 4 elements
+    // and P4 is a multiple of 4) so the x-factors load as 128-bit broadcasts
+    T* const s_w = (T*)__builtin_assume_aligned(sm + ((NCS * CS + 3) & ~3) + (wid * GP + grp) * 6 * P4, 16);
     const int bm0 = MODE == 0 ? blockIdx.y : 0;
     const int bm1 = MODE == 0 ? blockIdx.y + 1 : batch;
     const int bx0 = cx * KX, bx1 = min(nb, bx0 + KX) - 1;
@@ -410,36 +417,38 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                 for (int by = by0; by <= by1; ++by) {
                     const int rowb = (tz * nb + by) * nb;
                     const int j0 = tile_start[rowb + bx0], j1 = tile_start[rowb + bx1 + 1];
-                    for (int j = j0 + wid; j < j1; j += CW) {
-                        const int bp = bpack_s[j];
+                    for (int jb = j0 + wid * GP; jb < j1; jb += CW * GP) {
+                        const int j = jb + grp;
+                        const bool valid = j < j1;
+                        const int bp = valid ? bpack_s[j] : 0;
                         const int lbx = (bp & 1023) - lox, lby = ((bp >> 10) & 1023) - loy, bz = bp >> 20;
-                        {
-                            // 1-D weights: lanes 0-31 x, lanes 32-63 y, then lanes 0-31 z
-                            const int d = lane >> 5, i = lane & 31;
-                            const T c0 = coff_s[3 * (int64_t)j + d];
+                        // 1-D factors of this group's point: entries q = d P4 + i, d = x, y, z
+                        T cxyz[3] = {(T)0, (T)0, (T)0};
+                        if (valid) {
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) cxyz[d] = coff_s[3 * (int64_t)j + d];
+                        }
+                        for (int q = gl; q < 3 * P4; q += GL) {
+                            const int d = small_div(q, P4), i = q - d * P4;
+                            const T c0 = d == 0 ? cxyz[0] : (d == 1 ? cxyz[1] : cxyz[2]);
                             const T e = c0 + half - (T)i;
-                            const T w = i < P ? dexp<T>(-ahh * e * e) : (T)0;
-                            s_w[wid][d][i] = w;
-                            s_w[wid][3 + d][i] = dfac * e * w;
-                            if (d == 0) {
-                                const T ez = coff_s[3 * (int64_t)j + 2] + half - (T)i;
-                                const T wz = i < P ? dexp<T>(-ahh * ez * ez) : (T)0;
-                                s_w[wid][2][i] = wz;
-                                s_w[wid][5][i] = dfac * ez * wz;
-                            }
+                            const T w = (valid && i < P) ? dexp<T>(-ahh * e * e) : (T)0;
+                            s_w[d * P4 + i] = w;
+                            s_w[(3 + d) * P4 + i] = dfac * e * w;
                         }
                         wave_lds_sync();
                         T pv[NCS];
 #pragma unroll
                         for (int c = 0; c < NCS; ++c)
-                            pv[c] = MODE != 0 ? vec_s[((int64_t)bm * n + j) * 3 + cs + c] : (T)0;
+                            pv[c] = (MODE != 0 && valid) ? vec_s[((int64_t)bm * n + j) * 3 + cs + c] : (T)0;
                         T v[NCS];
 #pragma unroll
                         for (int c = 0; c < NCS; ++c) v[c] = (T)0;
                         T g0 = 0, g1 = 0, g2 = 0;
-                        const T* wxr = s_w[wid][0];
-                        const T* dwxr = s_w[wid][3];
-                        for (int r = lane; r < PP; r += 64) {
+                        const T* wxr = s_w;
+                        const T* dwxr = s_w + 3 * P4;
+                        const int rows = valid ? PP : 0;
+                        for (int r = gl; r < rows; r += GL) {
                             const int iz = small_div(r, P), iy = r - iz * P;
                             const int zz = bz + iz;
                             const int slot = zz - small_div(zz, EZ) * EZ;
@@ -460,7 +469,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                                     }
                                 }
                             }
-                            const T wy = s_w[wid][1][iy], wz = s_w[wid][2][iz];
+                            const T wy = s_w[P4 + iy], wz = s_w[2 * P4 + iz];
                             if (MODE != 1) {
                                 const T wyz = wy * wz;
 #pragma unroll
@@ -473,27 +482,27 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                                     Sp += pv[c] * S[c];
                                     Dp += pv[c] * D[c];
                                 }
-                                const T dwy = s_w[wid][4][iy], dwz = s_w[wid][5][iz];
+                                const T dwy = s_w[4 * P4 + iy], dwz = s_w[5 * P4 + iz];
                                 g0 += wy * wz * Dp;
                                 g1 += dwy * wz * Sp;
                                 g2 += wy * dwz * Sp;
                             }
                         }
-                        const int64_t i = perm_s[j];
+                        const int64_t i = valid ? perm_s[j] : 0;
                         if (MODE != 1) {
 #pragma unroll
-                            for (int c = 0; c < NCS; ++c) v[c] = wave_sum(v[c]);
-                            if (lane == 0 && out) {
+                            for (int c = 0; c < NCS; ++c) v[c] = group_sum<GL>(v[c]);
+                            if (gl == 0 && valid && out) {
                                 T* o = out + ((int64_t)bm * n + i) * 3 + cs;
 #pragma unroll
                                 for (int c = 0; c < NCS; ++c) o[c] = v[c];
                             }
                         }
                         if (MODE != 0) {
-                            g0 = wave_sum(g0);
-                            g1 = wave_sum(g1);
-                            g2 = wave_sum(g2);
-                            if (lane == 0 && dx) {
+                            g0 = group_sum<GL>(g0);
+                            g1 = group_sum<GL>(g1);
+                            g2 = group_sum<GL>(g2);
+                            if (gl == 0 && valid && dx) {
                                 // the first contribution (forward field, first batch member,
                                 // first component pass) overwrites; the same lane adds the rest
                                 const bool first = (MODE == 1 && bm == 0 && cs == 0);
@@ -736,9 +745,14 @@ static int bank_cost(int P, int es, int ps, int elem_bytes) {
     return tot;
 }
 
+// points per wave of the sweeping quadrature: 4 in FP32 (16 lanes each), 1 in
+// FP64 (whose field ring leaves no LDS for four points' factors)
+template <typename T> constexpr int col_gp() { return sizeof(T) == 4 ? 4 : 1; }
+
 template <typename T> ColCfg col_config(const GridGeo& g) {
     ColCfg best{0, 0, 0, 0, 0, 0, 0, 0};
-    const size_t limit = 160 * 1024 - CW * 6 * 32 * sizeof(T);
+    const size_t wbytes = (size_t)CW * col_gp<T>() * 6 * ((g.P + 3) & ~3) * sizeof(T);
+    const size_t limit = 160 * 1024 - wbytes;
     // all components per pass when they fit; one-bin tiles measured as fast as
     // two-bin ones (less LDS, two workgroups per CU)
     const int opts[3][2] = {{3, 1}, {1, 2}, {1, 1}};
@@ -747,7 +761,7 @@ template <typename T> ColCfg col_config(const GridGeo& g) {
         const int E = kx * g.TS + g.P - 1, EZ = g.TS + g.P - 1;
         // padded strides with the fewest modelled bank conflicts that keep as
         // many workgroups per CU as the unpadded layout
-        const size_t stat = CW * 6 * 32 * sizeof(T);
+        const size_t stat = wbytes;
         const size_t lds0 = ncs * ((size_t)EZ * E * E + 4) * sizeof(T);
         if (lds0 > limit) continue;
         const size_t per_cu0 = (160 * 1024) / (lds0 + stat);
@@ -760,10 +774,11 @@ template <typename T> ColCfg col_config(const GridGeo& g) {
                 const int c = bank_cost(g.P, e2, p2, (int)sizeof(T)) * 256 + (e2 - E) * E + pad;
                 if (c < cost) { cost = c; es = e2; ps = p2; }
             }
-        const size_t lds = ncs * ((size_t)EZ * ps + 4) * sizeof(T);
-        if (lds > limit) continue;
+        const size_t ring = ((ncs * ((size_t)EZ * ps + 4) + 3) & ~(size_t)3) * sizeof(T);
+        if (ring > limit) continue;
+        const size_t lds = ring + wbytes;  // dynamic: the ring, then the factors
         const int ncx = (g.nt + kx - 1) / kx;
-        const int per_cu = (int)((160 * 1024) / (lds + CW * 6 * 32 * sizeof(T)));
+        const int per_cu = (int)((160 * 1024) / lds);
         const int target = 2 * 256 * (per_cu < 1 ? 1 : per_cu);
         int nseg = (target + ncx * ncx - 1) / (ncx * ncx);
         nseg = nseg < 1 ? 1 : (nseg > g.nt ? g.nt : nseg);
@@ -781,8 +796,8 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
     if (cc.ncs) {
         const dim3 grd(cc.ncol * cc.nseg, batch);
 #define GCOL(NC)                                                                                               \
-    allow_lds(k_gather_col<T, 0, NC>, cc.lds);                                                                 \
-    hipLaunchKernelGGL((k_gather_col<T, 0, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
+    allow_lds(k_gather_col<T, 0, NC, col_gp<T>()>, cc.lds);                                                                 \
+    hipLaunchKernelGGL((k_gather_col<T, 0, NC, col_gp<T>()>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
                        p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u,  \
                        (T*)nullptr)
         if (cc.ncs == 3) { GCOL(3); } else { GCOL(1); }
@@ -825,11 +840,11 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
         const dim3 grd(cc.ncol * cc.nseg, 1);
         // pass 1: forward field contracted with w; pass 2: phi_w value and contraction with f
 #define GCOLG(NC)                                                                                              \
-    allow_lds(k_gather_col<T, 1, NC>, cc.lds);                                                                 \
-    allow_lds(k_gather_col<T, 2, NC>, cc.lds);                                                                 \
-    hipLaunchKernelGGL((k_gather_col<T, 1, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
+    allow_lds(k_gather_col<T, 1, NC, col_gp<T>()>, cc.lds);                                                                 \
+    allow_lds(k_gather_col<T, 2, NC, col_gp<T>()>, cc.lds);                                                                 \
+    hipLaunchKernelGGL((k_gather_col<T, 1, NC, col_gp<T>()>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
                        p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);  \
-    hipLaunchKernelGGL((k_gather_col<T, 2, NC>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
+    hipLaunchKernelGGL((k_gather_col<T, 2, NC, col_gp<T>()>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
                        p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n, batch, dsrc, dx)
         if (cc.ncs == 3) { GCOLG(3); } else { GCOLG(1); }
 #undef GCOLG
