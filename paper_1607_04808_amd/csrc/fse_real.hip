@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                                              T* out2, const int* __restrict__ work_start) {
     constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
     // sources per LDS chunk: 512, or 256 when the staged values are wide
-    constexpr int CH = 128;
+    constexpr int CH = sizeof(T) == 4 ? 64 : 128;
     __shared__ Pos4<T> xs[CH];  // source positions
     __shared__ Pos4<T> xq[CH];  // test form: -2 (x - o), |x - o|^2 about the cell corner o
     __shared__ T ss[NB][NS][CH];
