@@ -33,7 +33,7 @@ PEAK = {"hbm_GBs": 8000.0, "f32_TFLOPs": 157.3, "f64_TFLOPs": 78.6}
 # Parameters per form (calibrated against the oracle):
 # FP32 form: 1e-6 relative max-norm; FP64 form: 1e-10.
 FORMS = {
-    "f32": dict(xi=75.0, rc=0.0504, M=236, P=12, tol=1e-6),
+    "f32": dict(xi=77.0, rc=0.04909, M=236, P=12, tol=1e-6),
     "f64": dict(xi=80.0, rc=0.06075, M=304, P=20, tol=1e-10),
 }
 N_DEFAULT = 1_000_000
