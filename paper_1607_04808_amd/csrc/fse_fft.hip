@@ -431,44 +431,101 @@ __device__ __forceinline__ void kpoly(const T k[3], const C2<T>* g, C2<T>* w) {
     }
 }
 
-template <typename T, int KERNEL, int CIN>
+template <typename T, int KERNEL, int CIN, int PF>
 __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, int zc, C2<T>* __restrict__ B,
                                               const T* __restrict__ sig, double kscale,
                                               const C2<T>* __restrict__ twg,
                                               const int* __restrict__ revg) {
+    // PF > 0: the next column (PF elements per thread, CIN * Mt <= 128 PF) and its
+    // row of sigma are fetched into registers while the current one is
+    // transformed, so the loads overlap the LDS work of the column before
     using V = C2<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n = fg.n;
+    const int Mp = Mt + 1;
     V* tw = (V*)smem;
     V* buf = tw + n;
     int* rev = (int*)(buf + CIN * n);
+    T* ssig = (T*)(((uintptr_t)(rev + n) + 15) & ~(uintptr_t)15);  // sigma row of the column
     load_tables(tw, rev, twg, revg, n);
     const int kx = blockIdx.y, bm = blockIdx.z;
     const int64_t lstride = (int64_t)(Mt + 1) * n * fg.sz;  // between components
     const bool nyx = (kx == Mt);
     const T ks = (T)kscale;
-    const int Mp = Mt + 1;
-    // zc consecutive ky columns per workgroup: the tables above are loaded once
-    for (int ky = blockIdx.x * zc; ky < min(n, (int)(blockIdx.x + 1) * zc); ++ky) {
-        V* col = B + (int64_t)bm * CIN * lstride + ((int64_t)kx * n + ky) * fg.sz;
+    const int tid = threadIdx.x;
+    const int ky0 = blockIdx.x * zc, ky1 = min(n, (int)(blockIdx.x + 1) * zc);
+    const V* colbase = B + (int64_t)bm * CIN * lstride + (int64_t)kx * n * fg.sz;
+    auto sigrow = [&](int ky) {
+        const int kys = (ky < Mt) ? ky : ky - n;
+        return sig + ((int64_t)kx * Mp + (kys < 0 ? -kys : kys)) * Mp;
+    };
+    constexpr int NP = PF > 0 ? PF : 1;
+    constexpr int NS = 4;  // sigma values per thread (Mp <= 512)
+    V pre[NP];
+    T pres[NS];
+    auto fetch = [&](int ky) {
+        const V* col = colbase + (int64_t)ky * fg.sz;
 #pragma unroll
-        for (int c = 0; c < CIN; ++c)
-            for (int z = threadIdx.x; z < n; z += blockDim.x)
-                buf[c * n + z] = (z < Mt) ? col[c * lstride + z] : cmk<V>((T)0, (T)0);
-        __syncthreads();
+        for (int k = 0; k < NP; ++k) {
+            const int e = tid + k * 128;
+            pre[k] = cmk<V>((T)0, (T)0);
+            if (e < CIN * Mt) {
+                const int c = small_div(e, Mt);
+                pre[k] = col[c * lstride + (e - c * Mt)];
+            }
+        }
+        const T* sr = sigrow(ky);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int e = tid + k * 128;
+            pres[k] = e < Mp ? sr[e] : (T)0;
+        }
+    };
+    if (PF > 0 && ky0 < ky1) fetch(ky0);
+    // zc consecutive ky columns per workgroup: the tables above are loaded once
+    for (int ky = ky0; ky < ky1; ++ky) {
+        V* col = B + (int64_t)bm * CIN * lstride + ((int64_t)kx * n + ky) * fg.sz;
+        if (PF > 0) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                const int e = tid + k * 128;
+                if (e < CIN * Mt) {
+                    const int c = small_div(e, Mt);
+                    buf[c * n + (e - c * Mt)] = pre[k];
+                }
+            }
+            for (int q = tid; q < CIN * (n - Mt); q += blockDim.x) {
+                const int c = small_div(q, n - Mt);
+                buf[c * n + Mt + (q - c * (n - Mt))] = cmk<V>((T)0, (T)0);
+            }
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int e = tid + k * 128;
+                if (e < Mp) ssig[e] = pres[k];
+            }
+            __syncthreads();
+            if (ky + 1 < ky1) fetch(ky + 1);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CIN; ++c)
+                for (int z = tid; z < n; z += blockDim.x)
+                    buf[c * n + z] = (z < Mt) ? col[c * lstride + z] : cmk<V>((T)0, (T)0);
+            const T* sr = sigrow(ky);
+            for (int e = tid; e < Mp; e += blockDim.x) ssig[e] = sr[e];
+            __syncthreads();
+        }
         fft_lines<V, false>(buf, CIN, n, fg, tw);
         // multiplier
         const int kys = (ky < Mt) ? ky : ky - n;
         const bool nyy = (ky == Mt);
-        const T* sigrow = sig + ((int64_t)kx * Mp + (kys < 0 ? -kys : kys)) * Mp;
-        for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        for (int p = tid; p < n; p += blockDim.x) {
             const int kzi = rev[p];
             const int kzs = (kzi < Mt) ? kzi : kzi - n;
             const bool nyz = (kzi == Mt);
             V g[CIN];
 #pragma unroll
             for (int c = 0; c < CIN; ++c) g[c] = buf[c * n + p];
-            const T s = sigrow[kzs < 0 ? -kzs : kzs];
+            const T s = ssig[kzs < 0 ? -kzs : kzs];
             // wavenumbers in [-Mt, Mt): the Nyquist index carries -Mt in every direction
             T k[3] = {ks * (T)(nyx ? -Mt : kx), ks * (T)kys, ks * (T)kzs};
             V w[3];
@@ -489,7 +546,7 @@ __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, int zc, C2<T>*
         fft_lines<V, true>(buf, 3, n, fg, tw);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            for (int z = threadIdx.x; z < Mt; z += blockDim.x) col[c * lstride + z] = buf[c * n + z];
+            for (int z = tid; z < Mt; z += blockDim.x) col[c * lstride + z] = buf[c * n + z];
         __syncthreads();
     }
 }
@@ -628,20 +685,35 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
     V* B = (V*)Bv;
     constexpr int ZC = 4;  // ky columns per workgroup
     dim3 grd((n + ZC - 1) / ZC, Mt + 1, batch);
-    size_t sh = sizeof(V) * (size_t)n * (1 + c_in) + sizeof(int) * n;
-    if (kernel == FSE_STOKESLET) {
-        set_lds(k_fft_z<T, FSE_STOKESLET, 3>, sh);
-        hipLaunchKernelGGL((k_fft_z<T, FSE_STOKESLET, 3>), grd, dim3(128), sh, st, fg, Mt, ZC, B, sig,
-                           kscale, (const V*)tw, rev);
-    } else if (kernel == FSE_ROTLET) {
-        set_lds(k_fft_z<T, FSE_ROTLET, 3>, sh);
-        hipLaunchKernelGGL((k_fft_z<T, FSE_ROTLET, 3>), grd, dim3(128), sh, st, fg, Mt, ZC, B, sig, kscale,
-                           (const V*)tw, rev);
-    } else {
-        set_lds(k_fft_z<T, FSE_STRESSLET, 6>, sh);
-        hipLaunchKernelGGL((k_fft_z<T, FSE_STRESSLET, 6>), grd, dim3(128), sh, st, fg, Mt, ZC, B, sig,
-                           kscale, (const V*)tw, rev);
-    }
+    // LDS: twiddles, CIN lines, index table, sigma row
+    size_t sh = sizeof(V) * (size_t)n * (1 + c_in) + sizeof(int) * n + 16 + sizeof(T) * (size_t)(Mt + 1);
+    const int need = (c_in * Mt + 127) / 128;  // column elements per thread
+    // the prefetch registers cost the FP32 kernel a third of its occupancy (the
+    // LDS allows eight blocks per CU there), a net loss; FP64 is LDS-limited to
+    // three blocks per CU, so the overlap is free
+    const bool sig_ok = Mt + 1 <= 4 * 128;
+#define ZLAUNCH(K, CI, PFV)                                                                                  \
+    do {                                                                                                     \
+        set_lds(k_fft_z<T, K, CI, PFV>, sh);                                                                 \
+        hipLaunchKernelGGL((k_fft_z<T, K, CI, PFV>), grd, dim3(128), sh, st, fg, Mt, ZC, B, sig, kscale,  \
+                           (const V*)tw, rev);                                                               \
+    } while (0)
+#define ZPICK(K, CI)                                                                                         \
+    do {                                                                                                     \
+        if constexpr (sizeof(T) == 8) {                                                                      \
+            if (sig_ok && need <= 6) ZLAUNCH(K, CI, 6);                                                      \
+            else if (sig_ok && need <= 8) ZLAUNCH(K, CI, 8);                                                 \
+            else if (sig_ok && need <= 12) ZLAUNCH(K, CI, 12);                                               \
+            else ZLAUNCH(K, CI, 0);                                                                          \
+        } else {                                                                                             \
+            ZLAUNCH(K, CI, 0);                                                                               \
+        }                                                                                                    \
+    } while (0)
+    if (kernel == FSE_STOKESLET) ZPICK(FSE_STOKESLET, 3);
+    else if (kernel == FSE_ROTLET) ZPICK(FSE_ROTLET, 3);
+    else ZPICK(FSE_STRESSLET, 6);
+#undef ZPICK
+#undef ZLAUNCH
 }
 
 template <typename T>
