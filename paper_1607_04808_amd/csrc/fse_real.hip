@@ -122,8 +122,8 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                                              const int* __restrict__ perm_r, T* out, int accumulate,
                                              T* out2, const int* __restrict__ work_start) {
     constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
-    // sources per LDS chunk: 512, or 256 when the staged values are wide
-    constexpr int CH = sizeof(T) == 4 ? 64 : 128;
+    // source slots per LDS chunk
+    constexpr int CH = 128;
     __shared__ Pos4<T> xs[CH];  // source positions
     __shared__ Pos4<T> xq[CH];  // test form: -2 (x - o), |x - o|^2 about the cell corner o
     __shared__ T ss[NB][NS][CH];
@@ -155,6 +155,26 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     const T c2x = (T)(2.0 * INV_SQRTPI) * xi;       // 2 xi / sqrt(pi)
     const T c4x3 = (T)(4.0 * INV_SQRTPI) * xi * xi2;  // 4 xi^3 / sqrt(pi)
     const T sgn = (KERNEL == FSE_STOKESLET) ? (T)1 : (T)-1;
+    // the 27 neighbour cells (empty beyond the box): lane k < 27 of every wave
+    // holds the start and count of cell k
+    __shared__ int ch_off[28], ch_base[27];
+    int nb_s = 0, nb_n = 0;
+    {
+        const int lane = tid & 63;
+        if (lane < 27) {
+            const int nx = cx + lane % 3 - 1, ny = cy + (lane / 3) % 3 - 1, nz = cz + lane / 9 - 1;
+            if (nx >= 0 && nx < nc && ny >= 0 && ny < nc && nz >= 0 && nz < nc) {
+                const int cc = (nz * nc + ny) * nc + nx;
+                nb_s = cell_start[cc];
+                nb_n = cell_start[cc + 1] - nb_s;
+            }
+        }
+    }
+    int tot = nb_n;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) tot += __shfl_xor(tot, d);
+    // chunks: at most CH - 27 sources on average, so that no chunk exceeds CH
+    const int nch = (tot + (CH - 28)) / (CH - 27);
     for (int tb = t0; tb < t1; tb += nthr) {
         const int j = tb + tid;
         const bool act = j < t1;
@@ -305,72 +325,97 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             qp = q0;
         };
 
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int nz = cz + dz;
-            if (nz < 0 || nz >= nc) continue;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int ny = cy + dy;
-                if (ny < 0 || ny >= nc) continue;
-                const int row = (nz * nc + ny) * nc;
-                // the three x-neighbour cells are contiguous in cell order
-                const int s0 = cell_start[row + max(cx - 1, 0)];
-                const int s1 = cell_start[row + min(cx + 1, nc - 1) + 1];
-                for (int sb = s0; sb < s1; sb += CH) {
-                    __syncthreads();
-                    for (int q = tid; q < CH; q += nthr) {
-                        const int k = sb + q;
-                        Pos4<T> ps, pq;
-                        ps.x = ps.y = ps.z = ps.pad = (T)0;
-                        pq.x = pq.y = pq.z = (T)0;
-                        pq.pad = (T)FAR;  // padding slot: never within the cutoff
-                        if (k < s1) {
-                            ps.x = x_r[3 * (int64_t)k];
-                            ps.y = x_r[3 * (int64_t)k + 1];
-                            ps.z = x_r[3 * (int64_t)k + 2];
-                            const T l0 = ps.x - ox, l1 = ps.y - oy, l2 = ps.z - oz;
-                            pq.x = (T)-2 * l0;
-                            pq.y = (T)-2 * l1;
-                            pq.z = (T)-2 * l2;
-                            pq.pad = l0 * l0 + l1 * l1 + l2 * l2;
-#pragma unroll
-                            for (int b = 0; b < NB; ++b) {
-                                if (b0 + b < batch) {
-                                    const T* ap = a_r + ((int64_t)(b0 + b) * n + k) * 3;
-#pragma unroll
-                                    for (int d = 0; d < 3; ++d) ss[b][d][q] = ap[d];
-                                    if (NS == 6) {
-                                        const T* bp = (GRAD ? w_r : b_r) + ((int64_t)(b0 + b) * n + k) * 3;
-#pragma unroll
-                                        for (int d = 0; d < 3; ++d) ss[b][3 + d][q] = bp[d];
-                                    }
-                                } else {
-#pragma unroll
-                                    for (int d = 0; d < NS; ++d) ss[b][d][q] = (T)0;
-                                }
-                            }
-                        }
-                        xs[q] = ps;
-                        xq[q] = pq;
-                    }
-                    __syncthreads();
-                    if (!wave_active) continue;
-                    // candidates in groups of 8 (padding slots are far away); the
-                    // self pair and coincident points (r^2 = 0) are queued and
-                    // skipped when evaluated
-                    const int cnt8 = (min(CH, s1 - sb) + 7) & ~7;
-                    for (int k8 = 0; k8 < cnt8; k8 += 8) {
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const Pos4<T> pq = xq[k8 + u];
-                            const T r2 = fma(xl0, pq.x, fma(xl1, pq.y, fma(xl2, pq.z, At + pq.pad)));
-                            *qp = (unsigned short)(k8 + u);
-                            qp += r2 <= rc2t ? QROW : 0;
-                        }
-                        if (__any(qp > qlim)) flush();
-                    }
-                    flush();
+        // Each chunk takes the same fraction of every neighbour cell: chunk c of NCH
+        // holds sources [lo(c), lo(c + 1)) of cell k, lo(c) = floor(c n_k / NCH).
+        // Every target then sees a sample of its whole neighbourhood in each chunk,
+        // so the hit counts of the lanes are alike and the flushes waste few lanes
+        // (cell-by-cell chunks give hit counts that depend on where the target
+        // sits in its cell).
+        // lo(c + 1) - lo(c) = nq + (1 if the running remainder wraps), nq = n_k / NCH
+        const int nq = nb_n / nch;
+        const int nr = nb_n - nq * nch;
+        int cur = nb_s, rem = 0;
+        for (int c = 0; c < nch; ++c) {
+            __syncthreads();
+            if (tid < 32) {
+                int cnt = 0, base = 0;
+                if (tid < 27) {
+                    rem += nr;
+                    const int wrap = rem >= nch ? 1 : 0;
+                    rem -= wrap * nch;
+                    cnt = nq + wrap;
+                    base = cur;
+                    cur += cnt;
                 }
+                int inc = cnt;
+#pragma unroll
+                for (int d = 1; d < 32; d <<= 1) {
+                    const int v = __shfl_up(inc, d, 32);
+                    if (tid >= d) inc += v;
+                }
+                if (tid < 27) {
+                    ch_off[tid + 1] = inc;
+                    ch_base[tid] = base - (inc - cnt);  // slot q of cell k holds source ch_base[k] + q
+                }
+                if (tid == 0) ch_off[0] = 0;
             }
+            __syncthreads();
+            const int cntc = ch_off[27];
+            for (int q = tid; q < CH; q += nthr) {
+                Pos4<T> ps, pq;
+                ps.x = ps.y = ps.z = ps.pad = (T)0;
+                pq.x = pq.y = pq.z = (T)0;
+                pq.pad = (T)FAR;  // padding slot: never within the cutoff
+                if (q < cntc) {
+                    int kc = 0;  // the last cell whose slots start at or before q
+#pragma unroll
+                    for (int st = 16; st > 0; st >>= 1)
+                        if (kc + st <= 26 && ch_off[kc + st] <= q) kc += st;
+                    const int k = ch_base[kc] + q;
+                    ps.x = x_r[3 * (int64_t)k];
+                    ps.y = x_r[3 * (int64_t)k + 1];
+                    ps.z = x_r[3 * (int64_t)k + 2];
+                    const T l0 = ps.x - ox, l1 = ps.y - oy, l2 = ps.z - oz;
+                    pq.x = (T)-2 * l0;
+                    pq.y = (T)-2 * l1;
+                    pq.z = (T)-2 * l2;
+                    pq.pad = l0 * l0 + l1 * l1 + l2 * l2;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        if (b0 + b < batch) {
+                            const T* ap = a_r + ((int64_t)(b0 + b) * n + k) * 3;
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) ss[b][d][q] = ap[d];
+                            if (NS == 6) {
+                                const T* bp = (GRAD ? w_r : b_r) + ((int64_t)(b0 + b) * n + k) * 3;
+#pragma unroll
+                                for (int d = 0; d < 3; ++d) ss[b][3 + d][q] = bp[d];
+                            }
+                        } else {
+#pragma unroll
+                            for (int d = 0; d < NS; ++d) ss[b][d][q] = (T)0;
+                        }
+                    }
+                }
+                xs[q] = ps;
+                xq[q] = pq;
+            }
+            __syncthreads();
+            if (!wave_active) continue;
+            // candidates in groups of 8 (padding slots are far away); the self pair
+            // and coincident points (r^2 = 0) are queued and skipped when evaluated
+            const int cnt8 = (cntc + 7) & ~7;
+            for (int k8 = 0; k8 < cnt8; k8 += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const Pos4<T> pq = xq[k8 + u];
+                    const T r2 = fma(xl0, pq.x, fma(xl1, pq.y, fma(xl2, pq.z, At + pq.pad)));
+                    *qp = (unsigned short)(k8 + u);
+                    qp += r2 <= rc2t ? QROW : 0;
+                }
+                if (__any(qp > qlim)) flush();
+            }
+            flush();
         }
         if (act) {
             const int64_t i = perm_r[j];
