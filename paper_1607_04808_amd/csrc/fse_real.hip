@@ -94,7 +94,21 @@ __device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, flo
     ec = e * t * q;
 }
 
-constexpr int QCAP = 32;  // queued hits per thread before the wave flushes
+#ifndef FSE_REAL_CH
+#define FSE_REAL_CH 128
+#endif
+// queued hits per thread before the wave flushes (deeper FP64 queues cost less
+// occupancy than the extra flushes)
+template <typename T>
+constexpr int qcap() { return sizeof(T) == 4 ? 32 : 48; }
+// 1 when the sign bit of v is set (v < 0 or v = -0), else 0
+__device__ __forceinline__ unsigned sign_bit(float v) { return __float_as_uint(v) >> 31; }
+__device__ __forceinline__ unsigned sign_bit(double v) {
+    return (unsigned)((unsigned long long)__double_as_longlong(v) >> 63);
+}
+// queue row stride: the workgroup size rounded up to a power of two, so that a
+// hit advances the queue pointer by a shift of the hit bit
+__host__ __device__ inline int queue_row(int nthr) { return nthr <= 64 ? 64 : nthr <= 128 ? 128 : 256; }
 // Far-away position for padding slots and idle lanes: every distance to it
 // exceeds rc (its square may overflow to +inf, which fails the test as well).
 constexpr double FAR = 1e18;
@@ -123,11 +137,11 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                                              T* out2, const int* __restrict__ work_start) {
     constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
     // source slots per LDS chunk
-    constexpr int CH = 128;
+    constexpr int CH = FSE_REAL_CH;
     __shared__ Pos4<T> xs[CH];  // source positions
     __shared__ Pos4<T> xq[CH];  // test form: -2 (x - o), |x - o|^2 about the cell corner o
     __shared__ T ss[NB][NS][CH];
-    extern __shared__ unsigned short qd[];  // hit queues: QCAP rows of blockDim.x entries
+    extern __shared__ unsigned short qd[];  // hit queues: qcap rows of blockDim.x entries
     const int tid = threadIdx.x;
     const int nc = cg.ncell;
     const int nthr = blockDim.x;
@@ -189,24 +203,30 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         const T At = act ? xl0 * xl0 + xl1 * xl1 + xl2 * xl2 : (T)FAR;
         // target-side values for the gradient: f_t, w_t per batch member
         T ft[NB][3], wt[NB][3];
-        T acc[NB][3];
+        // acc holds the pairs of one flush; sum the flush totals: the FP32 rounding of
+        // a target whose total is dominated by a close pair then grows with the
+        // number of flushes, not with the number of pairs
+        T acc[NB][3], sum[NB][3];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                acc[b][d] = (T)0;
+                acc[b][d] = sum[b][d] = (T)0;
                 ft[b][d] = wt[b][d] = (T)0;
                 if (GRAD && act && b0 + b < batch) {
                     ft[b][d] = a_r[((int64_t)(b0 + b) * n + j) * 3 + d];
                     wt[b][d] = w_r[((int64_t)(b0 + b) * n + j) * 3 + d];
                 }
             }
-        T g0 = 0, g1 = 0, g2 = 0;
+        T g0 = 0, g1 = 0, g2 = 0, gs0 = 0, gs1 = 0, gs2 = 0;
         // this thread's hit queue: column tid of qd, QROW entries per row
-        const int QROW = nthr;
+        const int QROW = queue_row(nthr);
+        const int qsh = QROW == 64 ? 7 : QROW == 128 ? 8 : 9;  // log2 of a row in bytes
         unsigned short* const q0 = qd + tid;
-        unsigned short* const qlim = q0 + (QCAP - 8) * QROW;
+        unsigned short* const qlim = q0 + (qcap<T>() - 8) * QROW;
         unsigned short* qp = q0;
+        // widened test threshold folded into the target term: a hit is a negative sign
+        const T Atc = At - rc2t;
         const bool wave_active = __any(act);
 
         auto eval = [&](int kk) {
@@ -319,10 +339,23 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             }
         };
         auto flush = [&]() {
-            const int qn = small_div((int)(qp - q0), QROW);
+            const int qn = (int)(qp - q0) >> (qsh - 1);
             for (int e = 0; __any(e < qn); ++e)
                 if (e < qn) eval((int)q0[e * QROW]);
             qp = q0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    sum[b][d] += acc[b][d];
+                    acc[b][d] = (T)0;
+                }
+            if constexpr (GRAD) {
+                gs0 += g0;
+                gs1 += g1;
+                gs2 += g2;
+                g0 = g1 = g2 = (T)0;
+            }
         };
 
         // Each chunk takes the same fraction of every neighbour cell: chunk c of NCH
@@ -405,14 +438,20 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             // candidates in groups of 8 (padding slots are far away); the self pair
             // and coincident points (r^2 = 0) are queued and skipped when evaluated
             const int cnt8 = (cntc + 7) & ~7;
+            // slot indices two to a register (low, high half), advanced by 8 per group
+            unsigned kp[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) kp[v] = (2u * v) | ((2u * v + 1u) << 16);
             for (int k8 = 0; k8 < cnt8; k8 += 8) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const Pos4<T> pq = xq[k8 + u];
-                    const T r2 = fma(xl0, pq.x, fma(xl1, pq.y, fma(xl2, pq.z, At + pq.pad)));
-                    *qp = (unsigned short)(k8 + u);
-                    qp += r2 <= rc2t ? QROW : 0;
+                    const T d = fma(xl0, pq.x, fma(xl1, pq.y, fma(xl2, pq.z, Atc + pq.pad)));
+                    *qp = (unsigned short)((u & 1) ? (kp[u >> 1] >> 16) : kp[u >> 1]);
+                    qp = (unsigned short*)((char*)qp + (sign_bit(d) << qsh));
                 }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) kp[v] += 0x00080008u;
                 if (__any(qp > qlim)) flush();
             }
             flush();
@@ -428,20 +467,20 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         const T prev = accumulate ? o[d] : (T)0;
-                        o[d] = prev + acc[b][d] + self_coef * a[d];
+                        o[d] = prev + sum[b][d] + self_coef * a[d];
                     }
                 }
             } else {
-                out[3 * i] += g0;
-                out[3 * i + 1] += g1;
-                out[3 * i + 2] += g2;
+                out[3 * i] += gs0;
+                out[3 * i + 1] += gs1;
+                out[3 * i + 2] += gs2;
                 if constexpr (WVAL) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         if (b0 + b >= batch) break;
                         T* o = out2 + ((int64_t)(b0 + b) * n + i) * 3;
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) o[d] += acc[b][d] + self_coef * wt[b][d];
+                        for (int d = 0; d < 3; ++d) o[d] += sum[b][d] + self_coef * wt[b][d];
                     }
                 }
             }
@@ -469,7 +508,7 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned thr = (unsigned)p.real_S;
     // at most ceil(n / S) + ncells work items; the surplus workgroups return at once
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)QCAP * thr * sizeof(unsigned short);
+    const size_t qbytes = (size_t)qcap<T>() * queue_row((int)thr) * sizeof(unsigned short);
     dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
     hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p.cell_start, p.x_r, src_a_r, \
@@ -491,7 +530,7 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.real_S;
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)QCAP * thr * sizeof(unsigned short);
+    const size_t qbytes = (size_t)qcap<T>() * queue_row((int)thr) * sizeof(unsigned short);
     // batch members in groups of 4 per pass; each pass adds to dx (and dsrc)
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
