@@ -636,8 +636,36 @@ __global__ __launch_bounds__(256) void k_fft_xinv(FftGeo fg, int Mt, int c_in,
     }
 }
 
-template <typename T> constexpr int xrows() { return sizeof(T) == 4 ? 16 : 8; }
-template <typename T> constexpr int ylines() { return sizeof(T) == 4 ? 16 : 8; }
+// Lines (rows) per workgroup of each pass.  Fewer lines mean less LDS per
+// workgroup and so more resident workgroups per CU, whose loads and stores
+// overlap the others' LDS transforms; more lines make wider HBM segments where
+// a pass writes across lines.  The values are the measured best per pass and
+// precision at the headline grids (Mt 250 FP32, 324 FP64).
+#ifndef FSE_XROWS32
+#define FSE_XROWS32 16
+#endif
+#ifndef FSE_XINVROWS32
+#define FSE_XINVROWS32 8
+#endif
+#ifndef FSE_YLINES32
+#define FSE_YLINES32 8
+#endif
+#ifndef FSE_XROWS64
+#define FSE_XROWS64 4
+#endif
+#ifndef FSE_XINVROWS64
+#define FSE_XINVROWS64 2
+#endif
+#ifndef FSE_YLINES64
+#define FSE_YLINES64 4
+#endif
+#ifndef FSE_YINVLINES64
+#define FSE_YINVLINES64 2
+#endif
+template <typename T> constexpr int xrows() { return sizeof(T) == 4 ? FSE_XROWS32 : FSE_XROWS64; }
+template <typename T> constexpr int xinvrows() { return sizeof(T) == 4 ? FSE_XINVROWS32 : FSE_XINVROWS64; }
+template <typename T> constexpr int ylines() { return sizeof(T) == 4 ? FSE_YLINES32 : FSE_YLINES64; }
+template <typename T> constexpr int yinvlines() { return sizeof(T) == 4 ? FSE_YLINES32 : FSE_YINVLINES64; }
 
 // Raise a pass's dynamic-LDS limit to `bytes`; remembered per kernel.
 template <typename K> void set_lds(K kern, size_t bytes) {
@@ -723,7 +751,7 @@ void launch_fft_inverse(const FftGeo& fg, const GridGeo& g, void* Bv, void* Av, 
     using V = C2<T>;
     (void)rev;
     const int Mt = g.Mt, n = fg.n;
-    constexpr int R = xrows<T>(), LZ = ylines<T>();
+    constexpr int R = xinvrows<T>(), LZ = yinvlines<T>();
     V* A = (V*)Av;
     V* B = (V*)Bv;
     if (passes & 1) {
