@@ -330,7 +330,7 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
 // ---------------------------------------------------------------------------
 constexpr int CW = 8;  // waves per sweeping workgroup
 
-template <typename T, int MODE, int NCS, int GP>
+template <typename T, int MODE, int NCS, int GP, int PT>
 __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int segb, int ES, int PS,
                                                        const int* __restrict__ tile_start,
                                                        const int* __restrict__ perm_s,
@@ -344,7 +344,9 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     T* sm = (T*)smem_raw;
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
     const int X = KX * TB, E = X + P - 1, E2 = E * E, EZ = TB + P - 1;
-    const int P4 = (P + 3) & ~3;
+    // PT > 0: the padded window width P4 as a compile-time constant (the x sums
+    // unrolled with immediate LDS offsets); PT = 0: any P
+    const int P4 = PT > 0 ? PT : (P + 3) & ~3;
     // after the ring: per wave and point, the 1-D factors wx, wy, wz, dwx, dwy, dwz
     // (P4 each, zero beyond P)
     // LDS layout: row stride ES >= E and plane stride PS >= E ES, padded so the
@@ -368,6 +370,9 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     const T half = (T)(0.5 * (P - 1));
     const int PP = P * P;
     const int grp = GP == 1 ? 0 : lane / GL, gl = GP == 1 ? lane : lane % GL;
+    // row advance by GL: (dq, dr) = divmod(GL, P), and the matching ring offsets
+    const int dq = GL / P, dr = GL - dq * P;
+    const int step_r = dq * PS + dr * ES, step_c = PS - P * ES;
     // this group's factors, 16-byte aligned (the ring is rounded up to 4 elements
     // and P4 is a multiple of 4) so the x-factors load as 128-bit broadcasts
     T* const s_w = (T*)__builtin_assume_aligned(sm + ((NCS * CS + 3) & ~3) + (wid * GP + grp) * 6 * P4, 16);
@@ -448,24 +453,41 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                         const T* wxr = s_w;
                         const T* dwxr = s_w + 3 * P4;
                         const int rows = valid ? PP : 0;
+                        // the lane's rows r = gl, gl + GL, ...: (iz, iy) = divmod(r, P) and
+                        // the ring offset advance incrementally, (iz, iy) by divmod(GL, P)
+                        int iz = small_div(gl, P), iy = gl - iz * P;
+                        int slot = bz + iz;
+                        slot -= small_div(slot, EZ) * EZ;
+                        int ro = slot * PS + (lby + iy) * ES + lbx;
                         for (int r = gl; r < rows; r += GL) {
-                            const int iz = small_div(r, P), iy = r - iz * P;
-                            const int zz = bz + iz;
-                            const int slot = zz - small_div(zz, EZ) * EZ;
-                            const T* row = sm + slot * PS + (lby + iy) * ES + lbx;
+                            const T* row = sm + ro;
                             T S[NCS], D[NCS];
 #pragma unroll
                             for (int c = 0; c < NCS; ++c) S[c] = D[c] = (T)0;
-                            for (int ix = 0; ix < P4; ix += 4) {
+                            if constexpr (PT > 0) {
 #pragma unroll
-                                for (int u = 0; u < 4; ++u) {
-                                    const T wxu = wxr[ix + u];
-                                    const T dwxu = MODE != 0 ? dwxr[ix + u] : (T)0;
+                                for (int ix = 0; ix < PT; ++ix) {
+                                    const T wxu = wxr[ix];
+                                    const T dwxu = MODE != 0 ? dwxr[ix] : (T)0;
 #pragma unroll
                                     for (int c = 0; c < NCS; ++c) {
-                                        const T a = row[c * CS + ix + u];
+                                        const T a = row[c * CS + ix];
                                         S[c] += wxu * a;
                                         if (MODE != 0) D[c] += dwxu * a;
+                                    }
+                                }
+                            } else {
+                                for (int ix = 0; ix < P4; ix += 4) {
+#pragma unroll
+                                    for (int u = 0; u < 4; ++u) {
+                                        const T wxu = wxr[ix + u];
+                                        const T dwxu = MODE != 0 ? dwxr[ix + u] : (T)0;
+#pragma unroll
+                                        for (int c = 0; c < NCS; ++c) {
+                                            const T a = row[c * CS + ix + u];
+                                            S[c] += wxu * a;
+                                            if (MODE != 0) D[c] += dwxu * a;
+                                        }
                                     }
                                 }
                             }
@@ -486,6 +508,20 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                                 g0 += wy * wz * Dp;
                                 g1 += dwy * wz * Sp;
                                 g2 += wy * dwz * Sp;
+                            }
+                            iy += dr;
+                            iz += dq;
+                            slot += dq;
+                            ro += step_r;
+                            if (iy >= P) {
+                                iy -= P;
+                                ++iz;
+                                ++slot;
+                                ro += step_c;
+                            }
+                            while (slot >= EZ) {
+                                slot -= EZ;
+                                ro -= EZ * PS;
                             }
                         }
                         const int64_t i = valid ? perm_s[j] : 0;
@@ -795,12 +831,20 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
     const ColCfg cc = col_config<T>(g);
     if (cc.ncs) {
         const dim3 grd(cc.ncol * cc.nseg, batch);
-#define GCOL(NC)                                                                                               \
-    allow_lds(k_gather_col<T, 0, NC, col_gp<T>()>, cc.lds);                                                                 \
-    hipLaunchKernelGGL((k_gather_col<T, 0, NC, col_gp<T>()>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
-                       p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field, (const T*)nullptr, p.n, batch, u,  \
-                       (T*)nullptr)
-        if (cc.ncs == 3) { GCOL(3); } else { GCOL(1); }
+#define GCOL(NC, PT)                                                                                           \
+    allow_lds(k_gather_col<T, 0, NC, col_gp<T>(), PT>, cc.lds);                                                \
+    hipLaunchKernelGGL((k_gather_col<T, 0, NC, col_gp<T>(), PT>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx,    \
+                       cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field,              \
+                       (const T*)nullptr, p.n, batch, u, (T*)nullptr)
+#define GCOLP(NC)                                                                                              \
+    switch ((g.P + 3) & ~3) {                                                                                  \
+        case 12: GCOL(NC, 12); break;                                                                          \
+        case 16: GCOL(NC, 16); break;                                                                          \
+        case 20: GCOL(NC, 20); break;                                                                          \
+        default: GCOL(NC, 0); break;                                                                           \
+    }
+        if (cc.ncs == 3) { GCOLP(3); } else { GCOLP(1); }
+#undef GCOLP
 #undef GCOL
         return;
     }
@@ -839,14 +883,24 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
     if (cc.ncs) {
         const dim3 grd(cc.ncol * cc.nseg, 1);
         // pass 1: forward field contracted with w; pass 2: phi_w value and contraction with f
-#define GCOLG(NC)                                                                                              \
-    allow_lds(k_gather_col<T, 1, NC, col_gp<T>()>, cc.lds);                                                                 \
-    allow_lds(k_gather_col<T, 2, NC, col_gp<T>()>, cc.lds);                                                                 \
-    hipLaunchKernelGGL((k_gather_col<T, 1, NC, col_gp<T>()>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
-                       p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_f, w_s, p.n, batch, (T*)nullptr, dx);  \
-    hipLaunchKernelGGL((k_gather_col<T, 2, NC, col_gp<T>()>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx, cc.segb, cc.es, cc.ps,            \
-                       p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n, batch, dsrc, dx)
-        if (cc.ncs == 3) { GCOLG(3); } else { GCOLG(1); }
+#define GCOLG(NC, PT)                                                                                          \
+    allow_lds(k_gather_col<T, 1, NC, col_gp<T>(), PT>, cc.lds);                                                \
+    allow_lds(k_gather_col<T, 2, NC, col_gp<T>(), PT>, cc.lds);                                                \
+    hipLaunchKernelGGL((k_gather_col<T, 1, NC, col_gp<T>(), PT>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx,    \
+                       cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_f, w_s, p.n,    \
+                       batch, (T*)nullptr, dx);                                                                \
+    hipLaunchKernelGGL((k_gather_col<T, 2, NC, col_gp<T>(), PT>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx,    \
+                       cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n,    \
+                       batch, dsrc, dx)
+#define GCOLGP(NC)                                                                                             \
+    switch ((g.P + 3) & ~3) {                                                                                  \
+        case 12: GCOLG(NC, 12); break;                                                                         \
+        case 16: GCOLG(NC, 16); break;                                                                         \
+        case 20: GCOLG(NC, 20); break;                                                                         \
+        default: GCOLG(NC, 0); break;                                                                          \
+    }
+        if (cc.ncs == 3) { GCOLGP(3); } else { GCOLGP(1); }
+#undef GCOLGP
 #undef GCOLG
         return;
     }
