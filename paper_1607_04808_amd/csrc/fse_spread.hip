@@ -54,6 +54,8 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     __shared__ T s_v[CH][NC];
     __shared__ int s_bp[CH];
     __shared__ int s_cnt;
+    __shared__ unsigned char s_list[4][CH];  // per wave: the staged points whose window meets its tile
+    static_assert(CH <= 256, "point indices of a chunk are bytes");
 
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
     const int ncxy = (Mt + 15) / 16;
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     const int cx = t % ncxy, cy = (t / ncxy) % ncxy, cz = t / (ncxy * ncxy);
     const int bm = blockIdx.y;
     const int lox = cx * 16, loy = cy * 16, loz = cz * TZ;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wx0 = (wid & 1) * 8, wy0 = (wid >> 1) * 8;  // the wave's 8 x 8 tile in the core
     const int tx = wx0 + (lane & 7), ty = wy0 + (lane >> 3);
     const int gx = lox + tx, gy = loy + ty;
@@ -121,13 +123,26 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                     }
                     s_w[k][r] = w;
                 }
+                // this wave's list: the staged points whose window reaches its 8 x 8 tile
+                int nl = 0;
+                for (int k0 = 0; k0 < cnt; k0 += 64) {
+                    const int k = k0 + lane;
+                    bool hit = false;
+                    if (k < cnt) {
+                        const int bp = s_bp[k];
+                        const int bx = bp & 1023, by = (bp >> 10) & 1023;
+                        hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
+                                by + P <= loy + wy0);
+                    }
+                    const unsigned long long m = __ballot(hit);
+                    if (hit) s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)k;
+                    nl += __popcll(m);
+                }
                 __syncthreads();
-                for (int k = 0; k < cnt; ++k) {
+                for (int li = 0; li < nl; ++li) {
+                    const int k = __builtin_amdgcn_readfirstlane((int)s_list[wid][li]);
                     const int bp = __builtin_amdgcn_readfirstlane(s_bp[k]);
-                    const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-                    // does the window reach this wave's 8 x 8 tile?
-                    if (bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 || by + P <= loy + wy0)
-                        continue;
+                    const int bz = bp >> 20;
                     const T wxy = s_w[k][tx] * s_w[k][16 + ty];
                     T v[NC];
 #pragma unroll
