@@ -107,21 +107,24 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                 }
                 __syncthreads();
                 const int cnt = s_cnt;
-                // Gaussian factors at the core's node offsets, zero outside the window
-                for (int q = threadIdx.x; q < cnt * NW; q += 256) {
-                    const int k = small_div(q, NW), r = q - k * NW;
-                    const int d = r < 16 ? 0 : (r < 32 ? 1 : 2);
-                    const int o = r - 16 * d;
+                // Gaussian factors at the core's node offsets, zero outside the window;
+                // one work item per point and direction
+                for (int q = threadIdx.x; q < cnt * 3; q += 256) {
+                    const int k = small_div(q, 3), d = q - 3 * k;
                     const int bp = s_bp[k];
                     const int b = d == 0 ? (bp & 1023) : (d == 1 ? ((bp >> 10) & 1023) : (bp >> 20));
                     const int lo = d == 0 ? lox : (d == 1 ? loy : loz);
-                    const int i = lo + o - b;  // index inside the window
-                    T w = (T)0;
-                    if (i >= 0 && i < P) {
-                        const T e = s_c[k][d] + half - (T)i;
-                        w = dexp<T>(-ahh * e * e);
+                    const int i0 = lo - b;                      // window index of core offset 0
+                    const T e0 = s_c[k][d] + half - (T)i0;      // window coordinate there
+                    T* dst = &s_w[k][16 * d];
+#pragma unroll
+                    for (int o = 0; o < 16; ++o) {
+                        if (o >= TZ && d == 2) break;
+                        const T e = e0 - (T)o;
+                        const T w = dexp<T>(-ahh * e * e);
+                        const int i = i0 + o;
+                        dst[o] = (i >= 0 && i < P) ? w : (T)0;
                     }
-                    s_w[k][r] = w;
                 }
                 // this wave's list: the staged points whose window reaches its 8 x 8 tile
                 int nl = 0;
