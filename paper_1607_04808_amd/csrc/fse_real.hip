@@ -78,8 +78,9 @@ __device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, flo
     constexpr float LOG2E = 1.44269504f;
     ir = __builtin_amdgcn_rsqf(r2);
     r = r2 * ir;
-    e = __builtin_amdgcn_exp2f(-(xi2 * r2) * LOG2E);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.4f, xi * r, 1.0f));
+    // the factors xi^2 log2(e) and 0.4 xi are loop invariants
+    e = __builtin_amdgcn_exp2f((xi2 * -LOG2E) * r2);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.4f * xi, r, 1.0f));
     float q = -0.0292195667f;
     q = fmaf(q, t, 0.140469076f);
     q = fmaf(q, t, -0.235575206f);
@@ -229,13 +230,20 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         const T Atc = At - rc2t;
         const bool wave_active = __any(act);
 
-        auto eval = [&](int kk) {
+        // One queued pair, without branches: a pair that is off (a lane past its
+        // queue, the self pair, coincident points, or beyond the cutoff) is evaluated
+        // at r = r_c with its radial factors zeroed, so it adds exactly zero.
+        auto eval = [&](int kk, bool on) {
             const Pos4<T> ps = xs[kk];
             const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
-            const T r2 = r0 * r0 + r1 * r1 + r2v * r2v;
-            if (r2 == (T)0 || r2 > rc2) return;
+            const T r2q = r0 * r0 + r1 * r1 + r2v * r2v;
+            const bool use = on && r2q != (T)0 && r2q <= rc2;
+            const T r2 = use ? r2q : rc2;  // a harmless argument for the radial factors
             T r, ir, e, ec;
             radial<T>(xi, xi2, r2, r, ir, e, ec);
+            ir = use ? ir : (T)0;
+            e = use ? e : (T)0;
+            ec = use ? ec : (T)0;
             if constexpr (!GRAD) {
                 if constexpr (KERNEL == FSE_STOKESLET) {
                     const T cd = ec * ir - c2x * e;
@@ -340,8 +348,15 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         };
         auto flush = [&]() {
             const int qn = (int)(qp - q0) >> (qsh - 1);
-            for (int e = 0; __any(e < qn); ++e)
-                if (e < qn) eval((int)q0[e * QROW]);
+            int qmax = qn;
+#pragma unroll
+            for (int d = 32; d > 0; d >>= 1) qmax = max(qmax, __shfl_xor(qmax, d));
+            qmax = __builtin_amdgcn_readfirstlane(qmax);
+            for (int e = 0; e < qmax; ++e) {
+                const bool on = e < qn;
+                const int kk = q0[e * QROW];
+                eval(on ? kk : 0, on);
+            }
             qp = q0;
 #pragma unroll
             for (int b = 0; b < NB; ++b)

@@ -115,12 +115,15 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                     const int b = d == 0 ? (bp & 1023) : (d == 1 ? ((bp >> 10) & 1023) : (bp >> 20));
                     const int lo = d == 0 ? lox : (d == 1 ? loy : loz);
                     const int i0 = lo - b;                      // window index of core offset 0
-                    const T e0 = s_c[k][d] + half - (T)i0;      // window coordinate there
+                    // window coordinate there: the offset plus an exact half-integer, so
+                    // the coordinate e carries one rounding (adding half first would round
+                    // at the magnitude of P / 2 for every node)
+                    const T sc = s_c[k][d], k0 = half - (T)i0;
                     T* dst = &s_w[k][16 * d];
 #pragma unroll
                     for (int o = 0; o < 16; ++o) {
                         if (o >= TZ && d == 2) break;
-                        const T e = e0 - (T)o;
+                        const T e = sc + (k0 - (T)o);
                         const T w = dexp<T>(-ahh * e * e);
                         const int i = i0 + o;
                         dst[o] = (i >= 0 && i < P) ? w : (T)0;
@@ -249,12 +252,12 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
                     // 1-D weights: lanes 0-31 x, lanes 32-63 y, then lanes 0-31 z
                     const int d = lane >> 5, i = lane & 31;
                     const T c0 = coff_s[3 * (int64_t)j + d];
-                    const T e = c0 + half - (T)i;
+                    const T e = c0 + (half - (T)i);
                     const T w = i < P ? dexp<T>(-ahh * e * e) : (T)0;
                     s_w[wid][d][i] = w;
                     s_w[wid][3 + d][i] = dfac * e * w;
                     if (d == 0) {
-                        const T ez = coff_s[3 * (int64_t)j + 2] + half - (T)i;
+                        const T ez = coff_s[3 * (int64_t)j + 2] + (half - (T)i);
                         const T wz = i < P ? dexp<T>(-ahh * ez * ez) : (T)0;
                         s_w[wid][2][i] = wz;
                         s_w[wid][5][i] = dfac * ez * wz;
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                         for (int q = gl; q < 3 * P4; q += GL) {
                             const int d = small_div(q, P4), i = q - d * P4;
                             const T c0 = d == 0 ? cxyz[0] : (d == 1 ? cxyz[1] : cxyz[2]);
-                            const T e = c0 + half - (T)i;
+                            const T e = c0 + (half - (T)i);
                             const T w = (valid && i < P) ? dexp<T>(-ahh * e * e) : (T)0;
                             s_w[d * P4 + i] = w;
                             s_w[(3 + d) * P4 + i] = dfac * e * w;
@@ -596,10 +599,10 @@ __global__ __launch_bounds__(256) void k_gather(GridGeo g, const int* __restrict
         const int bp = bpack_s[j];
         const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
         const T cx = coff_s[3 * (int64_t)j], cy = coff_s[3 * (int64_t)j + 1], cz = coff_s[3 * (int64_t)j + 2];
-        const T ex = cx + half - (T)gx;
+        const T ex = cx + (half - (T)gx);
         const T wx = (gx < P) ? dexp<T>(-ahh * ex * ex) : (T)0;
         if (lane < P) {
-            const T ey = cy + half - (T)lane, ez = cz + half - (T)lane;
+            const T ey = cy + (half - (T)lane), ez = cz + (half - (T)lane);
             wsh[wid][0][lane] = dexp<T>(-ahh * ey * ey);
             wsh[wid][1][lane] = dexp<T>(-ahh * ez * ez);
         }
@@ -664,11 +667,11 @@ __global__ __launch_bounds__(256) void k_gather_grad(GridGeo g, const int* __res
         const int bp = bpack_s[j];
         const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
         const T cx = coff_s[3 * (int64_t)j], cy = coff_s[3 * (int64_t)j + 1], cz = coff_s[3 * (int64_t)j + 2];
-        const T ex = cx + half - (T)gx;
+        const T ex = cx + (half - (T)gx);
         const T wx = (gx < P) ? dexp<T>(-ahh * ex * ex) : (T)0;
         const T dwx = dfac * ex * wx;
         if (lane < P) {
-            const T ey = cy + half - (T)lane, ez = cz + half - (T)lane;
+            const T ey = cy + (half - (T)lane), ez = cz + (half - (T)lane);
             const T wy = dexp<T>(-ahh * ey * ey), wz = dexp<T>(-ahh * ez * ez);
             wsh[wid][0][lane] = wy;
             wsh[wid][1][lane] = wz;
