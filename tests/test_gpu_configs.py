@@ -155,7 +155,7 @@ def test_headline_1m_forward_adjoint(form):
     f = W.normal_strengths(n, 2000)
     w = W.normal_strengths(n, 3000)
     plan = F.Plan("stokeslet", form, F.make_params(prm["xi"], prm["rc"], prm["M"], prm["P"], (0.0, 0.0, 0.0),
-                                                   bench.L_BOX), batch=1, nmax=n)
+                                                   bench.L_BOX, Mt=prm["Mt"]), batch=1, nmax=n)
     try:
         plan.set_points(_tt(x, form))
         ft, wt = _tt(f, form), _tt(w, form)

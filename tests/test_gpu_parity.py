@@ -127,6 +127,7 @@ CASES = [
     (1500, 10.0, 0.32, 24, 10, 0, 1.0, (0.0, 0.0, 0.0)),    # eta 0.58, radices 7,5,2
     (777, 6.0, 0.6, 20, 13, 42, 1.3, (-0.5, 0.25, 2.0)),    # eta 0.66, odd P, ragged n, radices 7,4,3
     (2048, 10.0, 0.3, 30, 16, 60, 1.0, (0.0, 0.0, 0.0)),    # eta 0.59, padded grid, radices 8,5,3
+    (1200, 10.0, 0.32, 24, 10, 64, 1.0, (0.0, 0.0, 0.0)),   # eta 0.58, n = 128: radices 8,8,2 (8,2 fused)
 ]
 
 
