@@ -49,6 +49,28 @@ __device__ __forceinline__ int small_div(int a, int b) {
     return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
 }
 
+// Copy `total` elements into LDS (or any per-element destination) with B
+// independent loads per thread in flight: ld(q) reads element q, st(q, v) stores
+// it.  A plain strided loop of load-then-store waits out one memory latency per
+// element, since each LDS store needs its load to have returned.
+template <int B, typename LD, typename ST>
+__device__ __forceinline__ void staged_copy(int total, LD&& ld, ST&& st) {
+    const int nthr = blockDim.x;
+    for (int q0 = threadIdx.x; q0 < total; q0 += B * nthr) {
+        decltype(ld(0)) v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int q = q0 + b * nthr;
+            if (q < total) v[b] = ld(q);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int q = q0 + b * nthr;
+            if (q < total) st(q, v[b]);
+        }
+    }
+}
+
 __device__ __forceinline__ float readlane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }

@@ -311,10 +311,8 @@ __device__ void fft_lines(V* buf, int nl, int ld, const FftGeo& fg, const V* tw)
 // to every thread before any use.
 template <typename V>
 __device__ __forceinline__ void load_tables(V* tw, int* idx, const V* twg, const int* idxg, int n) {
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        tw[q] = twg[q];
-        idx[q] = idxg[q];
-    }
+    staged_copy<4>(n, [&](int q) { return twg[q]; }, [&](int q, V v) { tw[q] = v; });
+    staged_copy<4>(n, [&](int q) { return idxg[q]; }, [&](int q, int v) { idx[q] = v; });
     __syncthreads();
 }
 
@@ -335,14 +333,16 @@ __global__ __launch_bounds__(256) void k_fft_x(FftGeo fg, int Mt, const T* __res
     const int y0 = blockIdx.x * ROWS, z = blockIdx.y, bc = blockIdx.z;
     const int64_t M2 = (int64_t)Mt * Mt;
     const T* src = grid + ((int64_t)bc * Mt + z) * M2;
-    for (int l = 0; l < ROWS / 2; ++l) {
-        const int ya = y0 + 2 * l, yb = ya + 1;
-        for (int x = threadIdx.x; x < n; x += blockDim.x) {
+    staged_copy<8>(
+        (ROWS / 2) * n,
+        [&](int q) {
+            const int l = small_div(q, n), x = q - l * n;
+            const int ya = y0 + 2 * l, yb = ya + 1;
             const T re = (x < Mt && ya < Mt) ? src[(int64_t)ya * Mt + x] : (T)0;
             const T im = (x < Mt && yb < Mt) ? src[(int64_t)yb * Mt + x] : (T)0;
-            buf[l * n + x] = cmk<V>(re, im);
-        }
-    }
+            return cmk<V>(re, im);
+        },
+        [&](int q, V v) { buf[q] = v; });
     __syncthreads();
     fft_lines<V, false>(buf, ROWS / 2, n, fg, tw);
     const int64_t MA = (int64_t)Mt * fg.sy;  // one kx slab of A
@@ -377,11 +377,14 @@ __global__ __launch_bounds__(256) void k_fft_y(FftGeo fg, int Mt, const C2<T>* _
     const int z0 = blockIdx.x * LZ, kx = blockIdx.y, bc = blockIdx.z;
     const int SY = fg.sy, SZ = fg.sz;
     const V* src = A + ((int64_t)bc * (Mt + 1) + kx) * Mt * SY;
-    for (int l = 0; l < LZ; ++l) {
-        const int z = z0 + l;
-        for (int y = threadIdx.x; y < n; y += blockDim.x)
-            buf[l * n + y] = (y < Mt && z < Mt) ? src[(int64_t)z * SY + y] : cmk<V>((T)0, (T)0);
-    }
+    staged_copy<8>(
+        LZ * n,
+        [&](int q) {
+            const int l = small_div(q, n), y = q - l * n;
+            const int z = z0 + l;
+            return (y < Mt && z < Mt) ? src[(int64_t)z * SY + y] : cmk<V>((T)0, (T)0);
+        },
+        [&](int q, V v) { buf[q] = v; });
     __syncthreads();
     fft_lines<V, false>(buf, LZ, n, fg, tw);
     V* dst = B + ((int64_t)bc * (Mt + 1) + kx) * n * SZ;
@@ -506,12 +509,15 @@ __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, int zc, C2<T>*
             __syncthreads();
             if (ky + 1 < ky1) fetch(ky + 1);
         } else {
-#pragma unroll
-            for (int c = 0; c < CIN; ++c)
-                for (int z = tid; z < n; z += blockDim.x)
-                    buf[c * n + z] = (z < Mt) ? col[c * lstride + z] : cmk<V>((T)0, (T)0);
+            staged_copy<8>(
+                CIN * n,
+                [&](int q) {
+                    const int c = small_div(q, n), z = q - c * n;
+                    return (z < Mt) ? col[c * lstride + z] : cmk<V>((T)0, (T)0);
+                },
+                [&](int q, V v) { buf[q] = v; });
             const T* sr = sigrow(ky);
-            for (int e = tid; e < Mp; e += blockDim.x) ssig[e] = sr[e];
+            staged_copy<4>(Mp, [&](int e) { return sr[e]; }, [&](int e, T v) { ssig[e] = v; });
             __syncthreads();
         }
         fft_lines<V, false>(buf, CIN, n, fg, tw);
@@ -571,10 +577,16 @@ __global__ __launch_bounds__(256) void k_fft_yinv(FftGeo fg, int Mt, int c_in,
     const int64_t bc = (int64_t)bm * c_in + c;
     const int SY = fg.sy, SZ = fg.sz;
     const V* src = B + (bc * (Mt + 1) + kx) * n * SZ;
-    for (int q = threadIdx.x; q < n * LZ; q += blockDim.x) {
-        const int ky = q / LZ, r = q % LZ;
-        buf[r * n + revinv[ky]] = (z0 + r < Mt) ? src[(int64_t)ky * SZ + z0 + r] : cmk<V>((T)0, (T)0);
-    }
+    staged_copy<8>(
+        n * LZ,
+        [&](int q) {
+            const int ky = q / LZ, r = q % LZ;
+            return (z0 + r < Mt) ? src[(int64_t)ky * SZ + z0 + r] : cmk<V>((T)0, (T)0);
+        },
+        [&](int q, V v) {
+            const int ky = q / LZ, r = q % LZ;
+            buf[r * n + revinv[ky]] = v;
+        });
     __syncthreads();
     fft_lines<V, true>(buf, LZ, n, fg, tw);
     V* dst = A + (bc * (Mt + 1) + kx) * Mt * SY;
@@ -608,10 +620,16 @@ __global__ __launch_bounds__(256) void k_fft_xinv(FftGeo fg, int Mt, int c_in,
     const int64_t M2 = (int64_t)Mt * Mt;
     const int64_t MA = (int64_t)Mt * fg.sy;  // one kx slab of A
     const V* src = A + bc * Mp * MA + (int64_t)z * fg.sy + y0;
-    for (int q = threadIdx.x; q < Mp * ROWS; q += blockDim.x) {
-        const int kx = q / ROWS, r = q % ROWS;
-        H[r * Mp + kx] = (y0 + r < Mt) ? src[(int64_t)kx * MA + r] : cmk<V>((T)0, (T)0);
-    }
+    staged_copy<8>(
+        Mp * ROWS,
+        [&](int q) {
+            const int kx = q / ROWS, r = q % ROWS;
+            return (y0 + r < Mt) ? src[(int64_t)kx * MA + r] : cmk<V>((T)0, (T)0);
+        },
+        [&](int q, V v) {
+            const int kx = q / ROWS, r = q % ROWS;
+            H[r * Mp + kx] = v;
+        });
     __syncthreads();
     for (int l = 0; l < ROWS / 2; ++l) {
         const V* Ha = H + (2 * l) * Mp;

@@ -401,13 +401,36 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     const int bm1 = MODE == 0 ? blockIdx.y + 1 : batch;
     const int bx0 = cx * KX, bx1 = min(nb, bx0 + KX) - 1;
     const int by0 = cy * KX, by1 = min(nb, by0 + KX) - 1;
-    // stage node (x, y) of plane z, component c of the current field into its ring slot
-    auto stage = [&](const T* fb, int c, int z, int t) {
-        const int y = small_div(t, E), x = t - y * E;
-        const int gx = lox + x, gy = loy + y;
-        T v = (T)0;
-        if (gx < Mt && gy < Mt && z < Mt) v = fb[(int64_t)c * M3 + ((int64_t)z * Mt + gy) * Mt + gx];
-        sm[c * CS + (z % EZ) * PS + y * ES + x] = v;
+    // element q of a run of npl planes from plane z1: component c, plane z, node (x, y)
+    struct RingNode {
+        int c, z, y, x;
+    };
+    auto ring_node = [&](int q, int z1, int npl) {
+        RingNode r;
+        r.c = NCS == 1 ? 0 : small_div(q, npl * E2);
+        const int rem = q - r.c * npl * E2;
+        const int pz = small_div(rem, E2), t = rem - pz * E2;
+        r.y = small_div(t, E);
+        r.x = t - r.y * E;
+        r.z = z1 + pz;
+        return r;
+    };
+    // stage planes [z1, z1 + npl) of the current field into their ring slots
+    auto stage_planes = [&](const T* fb, int z1, int npl) {
+        staged_copy<8>(
+            NCS * npl * E2,
+            [&](int q) {
+                const RingNode r = ring_node(q, z1, npl);
+                const int gx = lox + r.x, gy = loy + r.y;
+                return (gx < Mt && gy < Mt && r.z < Mt)
+                           ? fb[(int64_t)r.c * M3 + ((int64_t)r.z * Mt + gy) * Mt + gx]
+                           : (T)0;
+            },
+            [&](int q, T v) {
+                const RingNode r = ring_node(q, z1, npl);
+                const int slot = r.z - small_div(r.z, EZ) * EZ;
+                sm[r.c * CS + slot * PS + r.y * ES + r.x] = v;
+            });
     };
     for (int q = tid; q < NCS * CS; q += 64 * CW) sm[q] = (T)0;
     for (int bm = bm0; bm < bm1; ++bm) {
@@ -415,28 +438,14 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
             const T* fb = field + ((int64_t)bm * 3 + cs) * M3;
             // initial ring: planes [tz0 TB, tz0 TB + EZ)
             __syncthreads();
-            {
-                const int tot = NCS * EZ * E2;
-                for (int q = tid; q < tot; q += 64 * CW) {
-                    const int c = NCS == 1 ? 0 : small_div(q, EZ * E2);
-                    const int r = q - c * EZ * E2;
-                    const int pz = small_div(r, E2), t = r - pz * E2;
-                    stage(fb, c, tz0 * TB + pz, t);
-                }
-            }
+            stage_planes(fb, tz0 * TB, EZ);
             __syncthreads();
             for (int tz = tz0; tz < tz1; ++tz) {
                 const int z0 = tz * TB;
                 if (tz > tz0) {
                     // planes [z0 - TB + EZ, z0 + EZ) replace [z0 - TB, z0) in the ring
                     __syncthreads();
-                    const int ptot = NCS * TB * E2;
-                    for (int q = tid; q < ptot; q += 64 * CW) {
-                        const int c = NCS == 1 ? 0 : small_div(q, TB * E2);
-                        const int r = q - c * TB * E2;
-                        const int pz = small_div(r, E2), t = r - pz * E2;
-                        stage(fb, c, z0 - TB + EZ + pz, t);
-                    }
+                    stage_planes(fb, z0 - TB + EZ, TB);
                     __syncthreads();
                 }
                 // the points of the z-bin tz in this tile (one contiguous range per bin row)
