@@ -90,18 +90,23 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                 if ((int)threadIdx.x < CH) {
                     const int j = base + (int)threadIdx.x;
                     if (j < j1) {
+                        // all of the point's loads first (one memory latency), then the test
                         const int bp = bpack_s[j];
+                        T cc[3], vv[NC];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) cc[d] = coff_s[3 * (int64_t)j + d];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) vv[c] = src_s[((int64_t)bm * n + j) * NC + c];
                         const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
                         const bool ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy &&
                                         bz <= loz + TZ - 1 && bz + P > loz;
                         if (ov) {
                             const int k = atomicAdd(&s_cnt, 1);
                             s_bp[k] = bp;
-                            s_c[k][0] = coff_s[3 * (int64_t)j];
-                            s_c[k][1] = coff_s[3 * (int64_t)j + 1];
-                            s_c[k][2] = coff_s[3 * (int64_t)j + 2];
 #pragma unroll
-                            for (int c = 0; c < NC; ++c) s_v[k][c] = src_s[((int64_t)bm * n + j) * NC + c];
+                            for (int d = 0; d < 3; ++d) s_c[k][d] = cc[d];
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) s_v[k][c] = vv[c];
                         }
                     }
                 }
