@@ -499,7 +499,19 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                             T S[NCS], D[NCS];
 #pragma unroll
                             for (int c = 0; c < NCS; ++c) S[c] = D[c] = (T)0;
-                            if constexpr (PT > 0) {
+                            // mode 1 needs only p . F: contract the components first, then
+                            // one x-sum each for the value and the x-derivative
+                            T Sp1 = (T)0, Dp1 = (T)0;
+                            if constexpr (PT > 0 && MODE == 1) {
+#pragma unroll
+                                for (int ix = 0; ix < PT; ++ix) {
+                                    T ap = pv[0] * row[ix];
+#pragma unroll
+                                    for (int c = 1; c < NCS; ++c) ap += pv[c] * row[c * CS + ix];
+                                    Sp1 += wxr[ix] * ap;
+                                    Dp1 += dwxr[ix] * ap;
+                                }
+                            } else if constexpr (PT > 0) {
 #pragma unroll
                                 for (int ix = 0; ix < PT; ++ix) {
                                     const T wxu = wxr[ix];
@@ -533,11 +545,13 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                                 for (int c = 0; c < NCS; ++c) v[c] += wyz * S[c];
                             }
                             if (MODE != 0) {
-                                T Sp = 0, Dp = 0;
+                                T Sp = Sp1, Dp = Dp1;
+                                if (!(PT > 0 && MODE == 1)) {
 #pragma unroll
-                                for (int c = 0; c < NCS; ++c) {
-                                    Sp += pv[c] * S[c];
-                                    Dp += pv[c] * D[c];
+                                    for (int c = 0; c < NCS; ++c) {
+                                        Sp += pv[c] * S[c];
+                                        Dp += pv[c] * D[c];
+                                    }
                                 }
                                 const T dwy = s_w[4 * P4 + iy], dwz = s_w[5 * P4 + iz];
                                 g0 += wy * wz * Dp;
