@@ -87,7 +87,7 @@ STAGE_KERNELS = {
     "gather_grad": (["k_gather_col<{T}, 1, ", "k_gather_col<{T}, 2, "], "fse_spread.hip"),
     "fft_x": (["k_fft_x<{T},"], "fse_fft.hip"),
     "fft_y": (["k_fft_y<{T},"], "fse_fft.hip"),
-    "fft_z_scale": (["k_fft_z<{T}, 0, 3,"], "fse_fft.hip"),
+    "fft_z_scale": (["k_fft_z<{T}, 0, 3,", "k_fft_zb<{T}, 0,"], "fse_fft.hip"),
     "fft_yinv": (["k_fft_yinv<{T},"], "fse_fft.hip"),
     "fft_xinv": (["k_fft_xinv<{T},"], "fse_fft.hip"),
 }
