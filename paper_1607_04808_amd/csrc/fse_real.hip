@@ -231,19 +231,25 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         const bool wave_active = __any(act);
 
         // One queued pair, without branches: a pair that is off (a lane past its
-        // queue, the self pair, coincident points, or beyond the cutoff) is evaluated
-        // at r = r_c with its radial factors zeroed, so it adds exactly zero.
+        // queue, the self pair, coincident points, or beyond the cutoff) adds exactly
+        // zero (see the two precisions below).
         auto eval = [&](int kk, bool on) {
             const Pos4<T> ps = xs[kk];
             const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
             const T r2q = r0 * r0 + r1 * r1 + r2v * r2v;
             const bool use = on && r2q != (T)0 && r2q <= rc2;
-            const T r2 = use ? r2q : rc2;  // a harmless argument for the radial factors
+            // FP32: r^2 = 1e30 makes e (and with it ec) exactly zero, and every kernel
+            // term carries one of them, so the pair adds zero with no selects.  FP64:
+            // exp of a huge argument takes the library's slow path, so evaluate at
+            // r = r_c and zero the factors.
+            const T r2 = use ? r2q : (sizeof(T) == 4 ? (T)1e30f : rc2);
             T r, ir, e, ec;
             radial<T>(xi, xi2, r2, r, ir, e, ec);
-            ir = use ? ir : (T)0;
-            e = use ? e : (T)0;
-            ec = use ? ec : (T)0;
+            if constexpr (sizeof(T) == 8) {
+                ir = use ? ir : (T)0;
+                e = use ? e : (T)0;
+                ec = use ? ec : (T)0;
+            }
             if constexpr (!GRAD) {
                 if constexpr (KERNEL == FSE_STOKESLET) {
                     const T cd = ec * ir - c2x * e;
