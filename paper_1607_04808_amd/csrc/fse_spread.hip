@@ -54,8 +54,9 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     __shared__ T s_v[CH][NC];
     __shared__ int s_bp[CH];
     __shared__ int s_cnt;
-    __shared__ unsigned char s_list[4][CH];  // per wave: the staged points whose window meets its tile
-    static_assert(CH <= 256, "point indices of a chunk are bytes");
+    // per wave: the staged points whose window meets its tile, as k | (z-group mask << 8)
+    __shared__ unsigned short s_list[4][CH];
+    static_assert(CH <= 256 && TZ <= 32, "list entries: point index byte and z-group mask");
 
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
     const int ncxy = (Mt + 15) / 16;
@@ -139,21 +140,27 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                 for (int k0 = 0; k0 < cnt; k0 += 64) {
                     const int k = k0 + lane;
                     bool hit = false;
+                    unsigned zm = 0;  // groups of 4 core z-nodes the window meets
                     if (k < cnt) {
                         const int bp = s_bp[k];
-                        const int bx = bp & 1023, by = (bp >> 10) & 1023;
+                        const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
                         hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
                                 by + P <= loy + wy0);
+                        const int zlo = max(bz, loz) - loz, zhi = min(bz + P, loz + TZ) - loz;
+#pragma unroll
+                        for (int z4 = 0; z4 < TZ; z4 += 4)
+                            if (z4 < zhi && z4 + 4 > zlo) zm |= 1u << (z4 / 4);
                     }
                     const unsigned long long m = __ballot(hit);
-                    if (hit) s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)k;
+                    if (hit)
+                        s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)(k | (zm << 8));
                     nl += __popcll(m);
                 }
                 __syncthreads();
                 for (int li = 0; li < nl; ++li) {
-                    const int k = __builtin_amdgcn_readfirstlane((int)s_list[wid][li]);
-                    const int bp = __builtin_amdgcn_readfirstlane(s_bp[k]);
-                    const int bz = bp >> 20;
+                    const int ent = __builtin_amdgcn_readfirstlane((int)s_list[wid][li]);
+                    const int k = ent & 255;
+                    const unsigned zm = (unsigned)ent >> 8;
                     const T wxy = s_w[k][tx] * s_w[k][16 + ty];
                     T v[NC];
 #pragma unroll
@@ -162,10 +169,9 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
 #pragma unroll
                     for (int z = 0; z < TZ; ++z) wz[z] = s_w[k][32 + z];
                     // z in groups of 4 that meet the window (the factors are zero outside it)
-                    const int zlo = max(bz, loz) - loz, zhi = min(bz + P, loz + TZ) - loz;
 #pragma unroll
                     for (int z4 = 0; z4 < TZ; z4 += 4) {
-                        if (z4 < zhi && z4 + 4 > zlo) {
+                        if (zm & (1u << (z4 / 4))) {
 #pragma unroll
                             for (int z = z4; z < z4 + 4; ++z) {
                                 const T w = wxy * wz[z];
