@@ -157,8 +157,13 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                     nl += __popcll(m);
                 }
                 __syncthreads();
-                for (int li = 0; li < nl; ++li) {
-                    const int ent = __builtin_amdgcn_readfirstlane((int)s_list[wid][li]);
+                // list entries come 64 at a time, one per lane, and are read from the
+                // lanes as the wave visits them (no LDS round trip per visit)
+                for (int l0 = 0; l0 < nl; l0 += 64) {
+                  const int mine = l0 + lane < nl ? (int)s_list[wid][l0 + lane] : 0;
+                  const int cl = min(64, nl - l0);
+                  for (int li = 0; li < cl; ++li) {
+                    const int ent = __builtin_amdgcn_readlane(mine, li);
                     const int k = ent & 255;
                     const unsigned zm = (unsigned)ent >> 8;
                     const T wxy = s_w[k][tx] * s_w[k][16 + ty];
@@ -180,6 +185,7 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                             }
                         }
                     }
+                  }
                 }
                 __syncthreads();
             }
