@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--n", type=int, default=N_DEFAULT)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-targets", type=int, default=2048, help="oracle target sample size")
+    ap.add_argument("--cpu-targets", type=int, default=6144, help="oracle target sample size")
     ap.add_argument("--forms", default="f32,f64")
     ap.add_argument("--set", action="append", default=[], metavar="FORM.KEY=VALUE",
                     help="override a parameter of a form, e.g. f32.xi=90 (repeatable)")
