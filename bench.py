@@ -18,6 +18,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -94,12 +95,19 @@ STAGE_KERNELS = {
 CSRC = os.path.join(ROOT, "paper_1607_04808_amd", "csrc")
 
 
+def code_text(text):
+    """Source text without // comments, trailing blanks and empty lines: what the
+    compiler sees, so that editing a comment keeps the counters valid."""
+    lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+    return "\n".join(ln for ln in lines if ln)
+
+
 def source_hash(name):
-    """sha256 of a kernel source and the shared header, to tell stale counters."""
+    """sha256 of a kernel source and the shared header (code only), to tell stale counters."""
     h = hashlib.sha256()
     for f in (name, "fse_common.h"):
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(CSRC, f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

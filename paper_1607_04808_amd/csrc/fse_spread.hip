@@ -9,8 +9,10 @@
 // window start, x-fastest bin order, so a row of bins is one contiguous range.
 //
 // Spreading: output-stationary (see k_spread); every node is written exactly
-// once, coalesced, by the thread that owns it: no atomics, no clearing of the
-// grid, and a deterministic summation order.
+// once, coalesced, by the thread that owns it: no floating-point atomics and no
+// clearing of the grid.  The order in which a node's terms are summed follows
+// the staging order of its points, which an LDS counter sets, so repeated runs
+// agree to rounding, not bit for bit.
 //
 // Quadrature: one workgroup per bin stages the (TB+P-1)^3 block of the field
 // that the bin's windows cover in LDS (when it fits) and each wave reduces one
@@ -39,10 +41,11 @@ template <> __device__ __forceinline__ double dexp<double>(double x) { return ex
 // starts can reach the core, are staged in LDS in chunks of CH, compacted to
 // the ones whose window overlaps the core, and their Gaussian factors at the
 // core's 16 + 16 + TZ node offsets (zero outside the window) are computed
-// cooperatively into LDS.  Every thread then walks the chunk's points in
-// order (a fixed order, so the result is deterministic): a wave whose tile
-// misses a point's window skips it, the point's z-factors come in as one
-// broadcast, and its z-range inside the core is a wave-uniform bound.
+// cooperatively into LDS.  Each wave then lists the staged points whose window
+// meets its 8 x 8 tile, each entry tagged with the groups of 4 core z-nodes the
+// window covers, and walks its list: the entries are read 64 at a time into
+// lanes and taken from there one per visit, the point's factors and values come
+// in as LDS broadcasts, and only the tagged z-groups are accumulated.
 template <typename T, int NC, int TZ, int CH>
 __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict__ tile_start,
                                                const int* __restrict__ bpack_s,
