@@ -421,36 +421,41 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     const int bm1 = MODE == 0 ? blockIdx.y + 1 : batch;
     const int bx0 = cx * KX, bx1 = min(nb, bx0 + KX) - 1;
     const int by0 = cy * KX, by1 = min(nb, by0 + KX) - 1;
-    // element q of a run of npl planes from plane z1: component c, plane z, node (x, y)
-    struct RingNode {
-        int c, z, y, x;
-    };
-    auto ring_node = [&](int q, int z1, int npl) {
-        RingNode r;
-        r.c = NCS == 1 ? 0 : small_div(q, npl * E2);
-        const int rem = q - r.c * npl * E2;
-        const int pz = small_div(rem, E2), t = rem - pz * E2;
-        r.y = small_div(t, E);
-        r.x = t - r.y * E;
-        r.z = z1 + pz;
-        return r;
-    };
-    // stage planes [z1, z1 + npl) of the current field into their ring slots
+    // stage planes [z1, z1 + npl) of the current field into their ring slots: a
+    // thread owns (component, y, x) columns of the footprint, located once, and
+    // walks the planes with a pointer that advances one plane per load, eight
+    // loads in flight; planes beyond the grid (from nv on) and nodes outside it
+    // stage zeros (the node's address is clamped into the field, its value dropped)
     auto stage_planes = [&](const T* fb, int z1, int npl) {
-        staged_copy<8>(
-            NCS * npl * E2,
-            [&](int q) {
-                const RingNode r = ring_node(q, z1, npl);
-                const int gx = lox + r.x, gy = loy + r.y;
-                return (gx < Mt && gy < Mt && r.z < Mt)
-                           ? fb[(int64_t)r.c * M3 + ((int64_t)r.z * Mt + gy) * Mt + gx]
-                           : (T)0;
-            },
-            [&](int q, T v) {
-                const RingNode r = ring_node(q, z1, npl);
-                const int slot = r.z - small_div(r.z, EZ) * EZ;
-                sm[r.c * CS + slot * PS + r.y * ES + r.x] = v;
-            });
+        const int s1 = z1 % EZ;
+        const int nv = min(npl, Mt - z1);
+        const int64_t MM = (int64_t)Mt * Mt;
+        for (int q = tid; q < NCS * E2; q += 64 * CW) {
+            const int c = NCS == 1 ? 0 : small_div(q, E2);
+            const int t = q - c * E2;
+            const int y = small_div(t, E), x = t - y * E;
+            const int gx = lox + x, gy = loy + y;
+            const bool in = gx < Mt && gy < Mt;
+            const T* src = fb + (int64_t)c * M3 + (int64_t)min(gy, Mt - 1) * Mt + min(gx, Mt - 1);
+            T* dst = sm + c * CS + y * ES + x;
+            for (int k0 = 0; k0 < npl; k0 += 8) {
+                T v[8];
+                const T* pz = src + (int64_t)(z1 + k0) * MM;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    v[b] = k0 + b < nv ? *pz : (T)0;
+                    pz += MM;
+                }
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    if (k0 + b < npl) {
+                        // ring slot of plane z1 + k0 + b: s1 < EZ and k0 + b < npl <= EZ
+                        const int sl = s1 + k0 + b;
+                        dst[(sl >= EZ ? sl - EZ : sl) * PS] = in ? v[b] : (T)0;
+                    }
+                }
+            }
+        }
     };
     for (int q = tid; q < NCS * CS; q += 64 * CW) sm[q] = (T)0;
     for (int bm = bm0; bm < bm1; ++bm) {
