@@ -997,16 +997,25 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
                            p.bpack_s, p.coff_s, phi_f, phi_w, f_s, w_s, p.n, batch, dsrc, dx);
 }
 
-// Bin side for the point binning: the largest side <= 7 (FP32) or <= 6 (FP64)
-// whose quadrature block still fits in LDS for one component, at least 2.
+// Bin side for the point binning: the largest side <= 7 whose quadrature block
+// still fits in LDS for one component, at least 2.  At the 1e-6 (FP32, P = 12)
+// and 1e-10 (FP64, P = 20) settings, sides 4 to 8 (FP32) and 4 to 7 (FP64)
+// measured fastest at 7: larger bins stage fewer ring planes per point, and at
+// 8 the FP32 ring leaves room for one workgroup per CU instead of two.
+#ifndef FSE_TBMAX32
+#define FSE_TBMAX32 7
+#endif
+#ifndef FSE_TBMAX64
+#define FSE_TBMAX64 7
+#endif
 int bin_side(int elem_bytes, int P) {
-    const int tb_max = elem_bytes == 4 ? 7 : 6;
+    const int tb_max = elem_bytes == 4 ? FSE_TBMAX32 : FSE_TBMAX64;
     const size_t limit = 160 * 1024 - GW * 6 * 32 * (size_t)elem_bytes;
     for (int tb = tb_max; tb >= 2; --tb) {
         const size_t E = (size_t)tb + P - 1;
         if ((E * E * E + 4) * elem_bytes <= limit) return tb;
     }
-    return elem_bytes == 4 ? 7 : 6;  // too large for LDS: the quadrature reads global memory
+    return tb_max;  // too large for LDS: the quadrature reads global memory
 }
 
 #define INST(T)                                                                                      \
