@@ -33,6 +33,73 @@ template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 
 
+// Stage the points j in [base, min(j1, base + CH)) whose window overlaps the
+// core (lox, loy, loz) + [0,16) x [0,16) x [0,TZ) into LDS, compacted (their
+// order follows an LDS counter), and compute their Gaussian factors at the
+// core's 16 + 16 + TZ node offsets, zero outside the window: one work item per
+// point and direction.  Returns the number staged, the same in every thread.
+// The caller synchronises before reading the factors.
+template <typename T, int NC, int TZ, int CH>
+__device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, int loz, int base, int j1,
+                                           int bm, int64_t n, const int* __restrict__ bpack_s,
+                                           const T* __restrict__ coff_s, const T* __restrict__ src_s,
+                                           T (*s_w)[32 + TZ], T (*s_c)[3], T (*s_v)[NC], int* s_bp,
+                                           int& s_cnt) {
+    const int P = g.P;
+    const T ahh = (T)g.ahh;
+    const T half = (T)(0.5 * (P - 1));
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    if ((int)threadIdx.x < CH) {
+        const int j = base + (int)threadIdx.x;
+        if (j < j1) {
+            // all of the point's loads first (one memory latency), then the test
+            const int bp = bpack_s[j];
+            T cc[3], vv[NC];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cc[d] = coff_s[3 * (int64_t)j + d];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) vv[c] = src_s[((int64_t)bm * n + j) * NC + c];
+            const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
+            const bool ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy &&
+                            bz <= loz + TZ - 1 && bz + P > loz;
+            if (ov) {
+                const int k = atomicAdd(&s_cnt, 1);
+                s_bp[k] = bp;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s_c[k][d] = cc[d];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) s_v[k][c] = vv[c];
+            }
+        }
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    // Gaussian factors at the core's node offsets, zero outside the window;
+    // one work item per point and direction
+    for (int q = threadIdx.x; q < cnt * 3; q += 256) {
+        const int k = small_div(q, 3), d = q - 3 * k;
+        const int bp = s_bp[k];
+        const int b = d == 0 ? (bp & 1023) : (d == 1 ? ((bp >> 10) & 1023) : (bp >> 20));
+        const int lo = d == 0 ? lox : (d == 1 ? loy : loz);
+        const int i0 = lo - b;                      // window index of core offset 0
+        // window coordinate there: the offset plus an exact half-integer, so
+        // the coordinate e carries one rounding (adding half first would round
+        // at the magnitude of P / 2 for every node)
+        const T sc = s_c[k][d], k0 = half - (T)i0;
+        T* dst = &s_w[k][16 * d];
+#pragma unroll
+        for (int o = 0; o < 16; ++o) {
+            if (o >= TZ && d == 2) break;
+            const T e = sc + (k0 - (T)o);
+            const T w = dexp<T>(-ahh * e * e);
+            const int i = i0 + o;
+            dst[o] = (i >= 0 && i < P) ? w : (T)0;
+        }
+    }
+    return cnt;
+}
+
 // Output-stationary spreading.  The workgroup (256 threads) owns a 16 x 16 x TZ
 // core of grid nodes; each wave covers an 8 x 8 tile of its columns and each
 // thread keeps the z-column (x, y, 0..TZ-1) of the core in registers for every
@@ -71,8 +138,6 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     const int wx0 = (wid & 1) * 8, wy0 = (wid >> 1) * 8;  // the wave's 8 x 8 tile in the core
     const int tx = wx0 + (lane & 7), ty = wy0 + (lane >> 3);
     const int gx = lox + tx, gy = loy + ty;
-    const T ahh = (T)g.ahh;
-    const T half = (T)(0.5 * (P - 1));
 
     T acc[TZ][NC];
 #pragma unroll
@@ -89,55 +154,8 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
             const int row = (sz * nb + sy) * nb;
             const int j0 = tile_start[row + bx0], j1 = tile_start[row + bx1 + 1];
             for (int base = j0; base < j1; base += CH) {
-                if (threadIdx.x == 0) s_cnt = 0;
-                __syncthreads();
-                if ((int)threadIdx.x < CH) {
-                    const int j = base + (int)threadIdx.x;
-                    if (j < j1) {
-                        // all of the point's loads first (one memory latency), then the test
-                        const int bp = bpack_s[j];
-                        T cc[3], vv[NC];
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) cc[d] = coff_s[3 * (int64_t)j + d];
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) vv[c] = src_s[((int64_t)bm * n + j) * NC + c];
-                        const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-                        const bool ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy &&
-                                        bz <= loz + TZ - 1 && bz + P > loz;
-                        if (ov) {
-                            const int k = atomicAdd(&s_cnt, 1);
-                            s_bp[k] = bp;
-#pragma unroll
-                            for (int d = 0; d < 3; ++d) s_c[k][d] = cc[d];
-#pragma unroll
-                            for (int c = 0; c < NC; ++c) s_v[k][c] = vv[c];
-                        }
-                    }
-                }
-                __syncthreads();
-                const int cnt = s_cnt;
-                // Gaussian factors at the core's node offsets, zero outside the window;
-                // one work item per point and direction
-                for (int q = threadIdx.x; q < cnt * 3; q += 256) {
-                    const int k = small_div(q, 3), d = q - 3 * k;
-                    const int bp = s_bp[k];
-                    const int b = d == 0 ? (bp & 1023) : (d == 1 ? ((bp >> 10) & 1023) : (bp >> 20));
-                    const int lo = d == 0 ? lox : (d == 1 ? loy : loz);
-                    const int i0 = lo - b;                      // window index of core offset 0
-                    // window coordinate there: the offset plus an exact half-integer, so
-                    // the coordinate e carries one rounding (adding half first would round
-                    // at the magnitude of P / 2 for every node)
-                    const T sc = s_c[k][d], k0 = half - (T)i0;
-                    T* dst = &s_w[k][16 * d];
-#pragma unroll
-                    for (int o = 0; o < 16; ++o) {
-                        if (o >= TZ && d == 2) break;
-                        const T e = sc + (k0 - (T)o);
-                        const T w = dexp<T>(-ahh * e * e);
-                        const int i = i0 + o;
-                        dst[o] = (i >= 0 && i < P) ? w : (T)0;
-                    }
-                }
+                const int cnt = stage_chunk<T, NC, TZ, CH>(g, lox, loy, loz, base, j1, bm, n, bpack_s, coff_s,
+                                                           src_s, s_w, s_c, s_v, s_bp, s_cnt);
                 // this wave's list: the staged points whose window reaches its 8 x 8 tile
                 int nl = 0;
                 for (int k0 = 0; k0 < cnt; k0 += 64) {
@@ -202,6 +220,112 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
                 const int64_t o = ((int64_t)gz * Mt + gy) * Mt + gx;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[z][c];
+            }
+        }
+    }
+}
+
+// FP32 spreading on the matrix cores.  Same cores, chunks and per-wave point
+// lists as k_spread (TZ = 16), but a wave's contribution from four listed points
+// k is one product per component c and 16-node xy block:
+//   acc_c[z][xy] += sum_k (wz_k(z) v_k[c]) (wx_k(x) wy_k(y)),
+// a 16 x 4 by 4 x 16 matrix product (v_mfma_f32_16x16x4f32; z rows, points
+// along k, xy nodes as columns).  Lane l supplies A[z = l mod 16][k = l / 16]
+// and B[k = l / 16][xy = l mod 16] and holds D[z = 4 (l / 16) + j][xy = l mod 16],
+// j = 0..3; the four xy blocks of the wave's 8 x 8 tile are its row pairs.
+// Every listed point costs the full 16 z-rows (no z-group skipping) at twice
+// the non-packed FP32 FMA rate of the vector units.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int NC, int CH>
+__global__ __launch_bounds__(256) void k_spread_mfma(GridGeo g, const int* __restrict__ tile_start,
+                                                    const int* __restrict__ bpack_s,
+                                                    const float* __restrict__ coff_s,
+                                                    const float* __restrict__ src_s, int64_t n,
+                                                    float* grid) {
+    constexpr int TZ = 16;
+    __shared__ __align__(16) float s_w[CH][32 + TZ];
+    __shared__ float s_c[CH][3];
+    __shared__ float s_v[CH][NC];
+    __shared__ int s_bp[CH];
+    __shared__ int s_cnt;
+    __shared__ unsigned char s_list[4][CH];  // per wave: the staged points that meet its tile
+    static_assert(CH <= 256, "list entries are point index bytes");
+    const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
+    const int ncxy = (Mt + 15) / 16;
+    const int t = blockIdx.x;
+    const int cx = t % ncxy, cy = (t / ncxy) % ncxy, cz = t / (ncxy * ncxy);
+    const int bm = blockIdx.y;
+    const int lox = cx * 16, loy = cy * 16, loz = cz * TZ;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wx0 = (wid & 1) * 8, wy0 = (wid >> 1) * 8;  // the wave's 8 x 8 tile in the core
+    const int kl = lane >> 4, cl = lane & 15;              // operand slot: point kl, row / column cl
+    const int xo = wx0 + (cl & 7), yo = wy0 + (cl >> 3);   // xy node of column cl in block 0
+
+    f32x4 acc[NC][4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[c][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int bx0 = max(0, lox - P + 1) / TB, bx1 = min(Mt - P, lox + 15) / TB;
+    const int by0 = max(0, loy - P + 1) / TB, by1 = min(Mt - P, loy + 15) / TB;
+    const int bz0 = max(0, loz - P + 1) / TB, bz1 = min(Mt - P, loz + TZ - 1) / TB;
+    for (int sz = bz0; sz <= bz1; ++sz)
+        for (int sy = by0; sy <= by1; ++sy) {
+            const int row = (sz * nb + sy) * nb;
+            const int j0 = tile_start[row + bx0], j1 = tile_start[row + bx1 + 1];
+            for (int base = j0; base < j1; base += CH) {
+                const int cnt = stage_chunk<float, NC, TZ, CH>(g, lox, loy, loz, base, j1, bm, n, bpack_s,
+                                                               coff_s, src_s, s_w, s_c, s_v, s_bp, s_cnt);
+                int nl = 0;
+                for (int k0 = 0; k0 < cnt; k0 += 64) {
+                    const int k = k0 + lane;
+                    bool hit = false;
+                    if (k < cnt) {
+                        const int bp = s_bp[k];
+                        const int bx = bp & 1023, by = (bp >> 10) & 1023;
+                        hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
+                                by + P <= loy + wy0);
+                    }
+                    const unsigned long long m = __ballot(hit);
+                    if (hit) s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)k;
+                    nl += __popcll(m);
+                }
+                __syncthreads();
+                // four listed points per step; slots past the list get zero A operands
+                // (their B operands read point 0's factors, which are finite)
+                for (int l0 = 0; l0 < nl; l0 += 4) {
+                    const bool ok = l0 + kl < nl;
+                    const int k = ok ? (int)s_list[wid][l0 + kl] : 0;
+                    const float wz = ok ? s_w[k][32 + cl] : 0.f;
+                    const float wx = s_w[k][xo];
+                    float a[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) a[c] = wz * s_v[k][c];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const float bb = wx * s_w[k][16 + yo + 2 * b];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], bb, acc[c][b], 0, 0, 0);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    const int64_t M3 = (int64_t)Mt * Mt * Mt;
+    const int gx = lox + xo;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int gy = loy + yo + 2 * b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gz = loz + 4 * kl + j;
+            if (gx < Mt && gy < Mt && gz < Mt) {
+                const int64_t o = ((int64_t)gz * Mt + gy) * Mt + gx;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[c][b][j];
             }
         }
     }
@@ -820,7 +944,15 @@ void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int 
 #define SPREAD(NC, CHK)                                                                                      \
     hipLaunchKernelGGL((k_spread<T, NC, TZ, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,     \
                        p.coff_s, src_s, p.n, grid)
-    if (c_in == 3) SPREAD(3, 128); else SPREAD(6, 128);
+#define SPREAD_MFMA(NC, CHK)                                                                                 \
+    hipLaunchKernelGGL((k_spread_mfma<NC, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s, p.coff_s, \
+                       src_s, p.n, grid)
+    if constexpr (sizeof(T) == 4) {
+        if (c_in == 3) SPREAD_MFMA(3, 128); else SPREAD_MFMA(6, 128);
+    } else {
+        if (c_in == 3) SPREAD(3, 128); else SPREAD(6, 128);
+    }
+#undef SPREAD_MFMA
 #undef SPREAD
 }
 
