@@ -32,6 +32,17 @@ template <typename T> __device__ __forceinline__ T dexp(T x);
 template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
 template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
 
+// Gaussian factor exp(-alpha h^2 e^2) as gauss(gauss_coef(alpha h^2) e^2): in FP32
+// the hardware base-2 exponential with log2(e) folded into the coefficient (the
+// rounding of the argument then dominates, as it does for expf of a rounded
+// -alpha h^2 e^2), in FP64 exp.
+template <typename T> __host__ __device__ inline T gauss_coef(double ahh) {
+    return sizeof(T) == 4 ? (T)(-ahh * 1.4426950408889634) : (T)(-ahh);
+}
+template <typename T> __device__ __forceinline__ T gauss(T y);
+template <> __device__ __forceinline__ float gauss<float>(float y) { return __builtin_amdgcn_exp2f(y); }
+template <> __device__ __forceinline__ double gauss<double>(double y) { return exp(y); }
+
 
 // Stage the points j in [base, min(j1, base + CH)) whose window overlaps the
 // core (lox, loy, loz) + [0,16) x [0,16) x [0,TZ) into LDS, compacted (their
@@ -46,7 +57,7 @@ __device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, i
                                            T (*s_w)[32 + TZ], T (*s_c)[3], T (*s_v)[NC], int* s_bp,
                                            int& s_cnt) {
     const int P = g.P;
-    const T ahh = (T)g.ahh;
+    const T gk = gauss_coef<T>(g.ahh);
     const T half = (T)(0.5 * (P - 1));
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
@@ -92,9 +103,8 @@ __device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, i
         for (int o = 0; o < 16; ++o) {
             if (o >= TZ && d == 2) break;
             const T e = sc + (k0 - (T)o);
-            const T w = dexp<T>(-ahh * e * e);
-            const int i = i0 + o;
-            dst[o] = (i >= 0 && i < P) ? w : (T)0;
+            const T w = gauss<T>(gk * e * e);
+            dst[o] = (unsigned)(i0 + o) < (unsigned)P ? w : (T)0;  // 0 <= i0 + o < P
         }
     }
     return cnt;
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int NC, int CH>
-__global__ __launch_bounds__(256) void k_spread_mfma(GridGeo g, const int* __restrict__ tile_start,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_spread_mfma(GridGeo g, const int* __restrict__ tile_start,
                                                     const int* __restrict__ bpack_s,
                                                     const float* __restrict__ coff_s,
                                                     const float* __restrict__ src_s, int64_t n,
