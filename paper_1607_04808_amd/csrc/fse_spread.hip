@@ -28,10 +28,6 @@ namespace fse {
 
 namespace {
 
-template <typename T> __device__ __forceinline__ T dexp(T x);
-template <> __device__ __forceinline__ float dexp<float>(float x) { return expf(x); }
-template <> __device__ __forceinline__ double dexp<double>(double x) { return exp(x); }
-
 // Gaussian factor exp(-alpha h^2 e^2) as gauss(gauss_coef(alpha h^2) e^2): in FP32
 // the hardware base-2 exponential with log2(e) folded into the coefficient (the
 // rounding of the argument then dominates, as it does for expf of a rounded
@@ -376,7 +372,7 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
     const int tbx = s % nb, tby = (s / nb) % nb, tbz = s / (nb * nb);
     const int lox = tbx * TB, loy = tby * TB, loz = tbz * TB;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const T ahh = (T)g.ahh;
+    const T gk = gauss_coef<T>(g.ahh);
     const T dfac = (T)(-2.0 * g.ahh / g.h);
     const T half = (T)(0.5 * (P - 1));
     const int PP = P * P, P4 = (P + 3) & ~3;
@@ -407,12 +403,12 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
                     const int d = lane >> 5, i = lane & 31;
                     const T c0 = coff_s[3 * (int64_t)j + d];
                     const T e = c0 + (half - (T)i);
-                    const T w = i < P ? dexp<T>(-ahh * e * e) : (T)0;
+                    const T w = i < P ? gauss<T>(gk * e * e) : (T)0;
                     s_w[wid][d][i] = w;
                     s_w[wid][3 + d][i] = dfac * e * w;
                     if (d == 0) {
                         const T ez = coff_s[3 * (int64_t)j + 2] + (half - (T)i);
-                        const T wz = i < P ? dexp<T>(-ahh * ez * ez) : (T)0;
+                        const T wz = i < P ? gauss<T>(gk * ez * ez) : (T)0;
                         s_w[wid][2][i] = wz;
                         s_w[wid][5][i] = dfac * ez * wz;
                     }
@@ -540,7 +536,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
     const int tz0 = seg * segb, tz1 = min(nb, tz0 + segb);
     if (tz0 >= tz1) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const T ahh = (T)g.ahh;
+    const T gk = gauss_coef<T>(g.ahh);
     const T dfac = (T)(-2.0 * g.ahh / g.h);
     const T half = (T)(0.5 * (P - 1));
     const int PP = P * P;
@@ -626,7 +622,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                             const int d = small_div(q, P4), i = q - d * P4;
                             const T c0 = d == 0 ? cxyz[0] : (d == 1 ? cxyz[1] : cxyz[2]);
                             const T e = c0 + (half - (T)i);
-                            const T w = (valid && i < P) ? dexp<T>(-ahh * e * e) : (T)0;
+                            const T w = (valid && i < P) ? gauss<T>(gk * e * e) : (T)0;
                             s_w[d * P4 + i] = w;
                             s_w[(3 + d) * P4 + i] = dfac * e * w;
                         }
@@ -774,7 +770,7 @@ __global__ __launch_bounds__(256) void k_gather(GridGeo g, const int* __restrict
     const int j0 = tile_start[s], j1 = tile_start[s + 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int gx = lane % LPR, grp = lane / LPR;
-    const T ahh = (T)g.ahh;
+    const T gk = gauss_coef<T>(g.ahh);
     const T half = (T)(0.5 * (P - 1));
     const T* fb0 = field + (int64_t)bm * 3 * M3;
     for (int j = j0 + wid; j < j1; j += 4) {
@@ -782,11 +778,11 @@ __global__ __launch_bounds__(256) void k_gather(GridGeo g, const int* __restrict
         const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
         const T cx = coff_s[3 * (int64_t)j], cy = coff_s[3 * (int64_t)j + 1], cz = coff_s[3 * (int64_t)j + 2];
         const T ex = cx + (half - (T)gx);
-        const T wx = (gx < P) ? dexp<T>(-ahh * ex * ex) : (T)0;
+        const T wx = (gx < P) ? gauss<T>(gk * ex * ex) : (T)0;
         if (lane < P) {
             const T ey = cy + (half - (T)lane), ez = cz + (half - (T)lane);
-            wsh[wid][0][lane] = dexp<T>(-ahh * ey * ey);
-            wsh[wid][1][lane] = dexp<T>(-ahh * ez * ez);
+            wsh[wid][0][lane] = gauss<T>(gk * ey * ey);
+            wsh[wid][1][lane] = gauss<T>(gk * ez * ez);
         }
         wave_lds_sync();
         T a0 = 0, a1 = 0, a2 = 0;
@@ -842,7 +838,7 @@ __global__ __launch_bounds__(256) void k_gather_grad(GridGeo g, const int* __res
     const int j0 = tile_start[s], j1 = tile_start[s + 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int gx = lane % LPR, grp = lane / LPR;
-    const T ahh = (T)g.ahh;
+    const T gk = gauss_coef<T>(g.ahh);
     const T dfac = (T)(-2.0 * g.ahh / g.h);
     const T half = (T)(0.5 * (P - 1));
     for (int j = j0 + wid; j < j1; j += 4) {
@@ -850,11 +846,11 @@ __global__ __launch_bounds__(256) void k_gather_grad(GridGeo g, const int* __res
         const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
         const T cx = coff_s[3 * (int64_t)j], cy = coff_s[3 * (int64_t)j + 1], cz = coff_s[3 * (int64_t)j + 2];
         const T ex = cx + (half - (T)gx);
-        const T wx = (gx < P) ? dexp<T>(-ahh * ex * ex) : (T)0;
+        const T wx = (gx < P) ? gauss<T>(gk * ex * ex) : (T)0;
         const T dwx = dfac * ex * wx;
         if (lane < P) {
             const T ey = cy + (half - (T)lane), ez = cz + (half - (T)lane);
-            const T wy = dexp<T>(-ahh * ey * ey), wz = dexp<T>(-ahh * ez * ez);
+            const T wy = gauss<T>(gk * ey * ey), wz = gauss<T>(gk * ez * ez);
             wsh[wid][0][lane] = wy;
             wsh[wid][1][lane] = wz;
             wsh[wid][2][lane] = dfac * ey * wy;
