@@ -173,6 +173,9 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     // the 27 neighbour cells (empty beyond the box): lane k < 27 of every wave
     // holds the start and count of cell k
     __shared__ int ch_off[28], ch_base[27];
+    __shared__ int s_kc[4];    // kept sources per wave in a staging round
+    __shared__ T s_bb[4][6];   // per wave: target bounding box (low x, y, z, high x, y, z)
+    __shared__ T s_box[6];     // the work item's target bounding box
     int nb_s = 0, nb_n = 0;
     {
         const int lane = tid & 63;
@@ -229,6 +232,28 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         // widened test threshold folded into the target term: a hit is a negative sign
         const T Atc = At - rc2t;
         const bool wave_active = __any(act);
+        // bounding box of the work item's targets about the cell corner
+        T bb_lo[3] = {act ? xl0 : (T)FAR, act ? xl1 : (T)FAR, act ? xl2 : (T)FAR};
+        T bb_hi[3] = {act ? xl0 : (T)-FAR, act ? xl1 : (T)-FAR, act ? xl2 : (T)-FAR};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                bb_lo[d] = min(bb_lo[d], __shfl_xor(bb_lo[d], o));
+                bb_hi[d] = max(bb_hi[d], __shfl_xor(bb_hi[d], o));
+            }
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                s_bb[tid >> 6][d] = bb_lo[d];
+                s_bb[tid >> 6][3 + d] = bb_hi[d];
+            }
+        __syncthreads();
+        if (tid < 6) {
+            T v = s_bb[0][tid];
+            for (int w = 1; w < (nthr >> 6); ++w) v = tid < 3 ? min(v, s_bb[w][tid]) : max(v, s_bb[w][tid]);
+            s_box[tid] = v;
+        }
 
         // One queued pair, without branches: a pair that is off (a lane past its
         // queue, the self pair, coincident points, or beyond the cutoff) adds exactly
@@ -415,11 +440,16 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
             }
             __syncthreads();
             const int cntc = ch_off[27];
-            for (int q = tid; q < CH; q += nthr) {
+            // stage the chunk's sources, dropping those farther than rc from the
+            // targets' bounding box (about a quarter of the 27 cells' volume): the
+            // kept ones are compacted in slot order (wave ballots), so the candidate
+            // loop below runs over fewer slots
+            int kept = 0;
+            for (int q0 = 0; q0 < cntc; q0 += nthr) {
+                const int q = q0 + tid;
                 Pos4<T> ps, pq;
-                ps.x = ps.y = ps.z = ps.pad = (T)0;
-                pq.x = pq.y = pq.z = (T)0;
-                pq.pad = (T)FAR;  // padding slot: never within the cutoff
+                bool keep = false;
+                int src = 0;
                 if (q < cntc) {
                     int kc = 0;  // the last cell whose slots start at or before q
 #pragma unroll
@@ -429,36 +459,63 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                     ps.x = x_r[3 * (int64_t)k];
                     ps.y = x_r[3 * (int64_t)k + 1];
                     ps.z = x_r[3 * (int64_t)k + 2];
+                    ps.pad = (T)0;
+                    src = k;
                     const T l0 = ps.x - ox, l1 = ps.y - oy, l2 = ps.z - oz;
                     pq.x = (T)-2 * l0;
                     pq.y = (T)-2 * l1;
                     pq.z = (T)-2 * l2;
                     pq.pad = l0 * l0 + l1 * l1 + l2 * l2;
+                    const T e0 = max(max(s_box[0] - l0, l0 - s_box[3]), (T)0);
+                    const T e1 = max(max(s_box[1] - l1, l1 - s_box[4]), (T)0);
+                    const T e2 = max(max(s_box[2] - l2, l2 - s_box[5]), (T)0);
+                    keep = e0 * e0 + e1 * e1 + e2 * e2 <= rc2t;
+                }
+                const unsigned long long m = __ballot(keep);
+                if ((tid & 63) == 0) s_kc[tid >> 6] = __popcll(m);
+                __syncthreads();
+                int off = kept, all = 0;
+                for (int w = 0; w < (nthr >> 6); ++w) {
+                    const int cw = s_kc[w];
+                    off += w < (tid >> 6) ? cw : 0;
+                    all += cw;
+                }
+                if (keep) {
+                    const int slot = off + __popcll(m & ((1ull << (tid & 63)) - 1ull));
+                    xs[slot] = ps;
+                    xq[slot] = pq;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         if (b0 + b < batch) {
-                            const T* ap = a_r + ((int64_t)(b0 + b) * n + k) * 3;
+                            const T* ap = a_r + ((int64_t)(b0 + b) * n + src) * 3;
 #pragma unroll
-                            for (int d = 0; d < 3; ++d) ss[b][d][q] = ap[d];
-                            if (NS == 6) {
-                                const T* bp = (GRAD ? w_r : b_r) + ((int64_t)(b0 + b) * n + k) * 3;
+                            for (int d = 0; d < 3; ++d) ss[b][d][slot] = ap[d];
+                            if constexpr (NS == 6) {
+                                const T* bp = (GRAD ? w_r : b_r) + ((int64_t)(b0 + b) * n + src) * 3;
 #pragma unroll
-                                for (int d = 0; d < 3; ++d) ss[b][3 + d][q] = bp[d];
+                                for (int d = 0; d < 3; ++d) ss[b][3 + d][slot] = bp[d];
                             }
                         } else {
 #pragma unroll
-                            for (int d = 0; d < NS; ++d) ss[b][d][q] = (T)0;
+                            for (int d = 0; d < NS; ++d) ss[b][d][slot] = (T)0;
                         }
                     }
                 }
-                xs[q] = ps;
-                xq[q] = pq;
+                kept += all;
+                __syncthreads();
+            }
+            // slots up to the next multiple of 8: never within the cutoff
+            if (tid < ((kept + 7) & ~7) - kept) {
+                Pos4<T> pf;
+                pf.x = pf.y = pf.z = (T)0;
+                pf.pad = (T)FAR;
+                xq[kept + tid] = pf;
             }
             __syncthreads();
             if (!wave_active) continue;
             // candidates in groups of 8 (padding slots are far away); the self pair
             // and coincident points (r^2 = 0) are queued and skipped when evaluated
-            const int cnt8 = (cntc + 7) & ~7;
+            const int cnt8 = (kept + 7) & ~7;
             // slot indices two to a register (low, high half), advanced by 8 per group
             unsigned kp[4];
 #pragma unroll
