@@ -40,50 +40,63 @@ template <> __device__ __forceinline__ float gauss<float>(float y) { return __bu
 template <> __device__ __forceinline__ double gauss<double>(double y) { return exp(y); }
 
 
-// Stage the points j in [base, min(j1, base + CH)) whose window overlaps the
-// core (lox, loy, loz) + [0,16) x [0,16) x [0,TZ) into LDS, compacted (their
-// order follows an LDS counter), and compute their Gaussian factors at the
-// core's 16 + 16 + TZ node offsets, zero outside the window: one work item per
-// point and direction.  Returns the number staged, the same in every thread.
-// The caller synchronises before reading the factors.
-template <typename T, int NC, int TZ, int CH>
-__device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, int loz, int base, int j1,
-                                           int bm, int64_t n, const int* __restrict__ bpack_s,
-                                           const T* __restrict__ coff_s, const T* __restrict__ src_s,
-                                           T (*s_w)[32 + TZ], T (*s_c)[3], T (*s_v)[NC], int* s_bp,
-                                           int& s_cnt) {
-    const int P = g.P;
-    const T gk = gauss_coef<T>(g.ahh);
-    const T half = (T)(0.5 * (P - 1));
+// One point of a chunk, held in registers between its load and its staging.
+template <typename T, int NC> struct ChunkPoint {
+    int bp;       // packed window start; -1: no point
+    T cc[3], vv[NC];
+};
+
+// Thread t < CH loads point base + t of the bin range ending at j1 (all of its
+// loads at once: one memory latency).
+template <typename T, int NC, int CH>
+__device__ __forceinline__ void load_point(ChunkPoint<T, NC>& pt, int base, int j1, int bm, int64_t n,
+                                           const int* __restrict__ bpack_s, const T* __restrict__ coff_s,
+                                           const T* __restrict__ src_s) {
+    pt.bp = -1;
+    const int j = base + (int)threadIdx.x;
+    if ((int)threadIdx.x < CH && j < j1) {
+        pt.bp = bpack_s[j];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pt.cc[d] = coff_s[3 * (int64_t)j + d];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pt.vv[c] = src_s[((int64_t)bm * n + j) * NC + c];
+    }
+}
+
+// Stage the loaded points whose window overlaps the core (lox, loy, loz) +
+// [0,16) x [0,16) x [0,TZ) into LDS, compacted (their order follows an LDS
+// counter).  Returns the number staged, the same in every thread.
+template <typename T, int NC, int TZ>
+__device__ __forceinline__ int stage_points(const ChunkPoint<T, NC>& pt, int P, int lox, int loy, int loz,
+                                            T (*s_c)[3], T (*s_v)[NC], int* s_bp, int& s_cnt) {
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    if ((int)threadIdx.x < CH) {
-        const int j = base + (int)threadIdx.x;
-        if (j < j1) {
-            // all of the point's loads first (one memory latency), then the test
-            const int bp = bpack_s[j];
-            T cc[3], vv[NC];
+    if (pt.bp >= 0) {
+        const int bx = pt.bp & 1023, by = (pt.bp >> 10) & 1023, bz = pt.bp >> 20;
+        const bool ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy &&
+                        bz <= loz + TZ - 1 && bz + P > loz;
+        if (ov) {
+            const int k = atomicAdd(&s_cnt, 1);
+            s_bp[k] = pt.bp;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) cc[d] = coff_s[3 * (int64_t)j + d];
+            for (int d = 0; d < 3; ++d) s_c[k][d] = pt.cc[d];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) vv[c] = src_s[((int64_t)bm * n + j) * NC + c];
-            const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-            const bool ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy &&
-                            bz <= loz + TZ - 1 && bz + P > loz;
-            if (ov) {
-                const int k = atomicAdd(&s_cnt, 1);
-                s_bp[k] = bp;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) s_c[k][d] = cc[d];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) s_v[k][c] = vv[c];
-            }
+            for (int c = 0; c < NC; ++c) s_v[k][c] = pt.vv[c];
         }
     }
     __syncthreads();
-    const int cnt = s_cnt;
-    // Gaussian factors at the core's node offsets, zero outside the window;
-    // one work item per point and direction
+    return s_cnt;
+}
+
+// Gaussian factors of the cnt staged points at the core's 16 + 16 + TZ node
+// offsets, zero outside the window: one work item per point and direction.
+// The caller synchronises before reading them.
+template <typename T, int TZ>
+__device__ __forceinline__ void chunk_factors(const GridGeo& g, int cnt, int lox, int loy, int loz,
+                                              T (*s_w)[32 + TZ], T (*s_c)[3], const int* s_bp) {
+    const int P = g.P;
+    const T gk = gauss_coef<T>(g.ahh);
+    const T half = (T)(0.5 * (P - 1));
     for (int q = threadIdx.x; q < cnt * 3; q += 256) {
         const int k = small_div(q, 3), d = q - 3 * k;
         const int bp = s_bp[k];
@@ -103,6 +116,19 @@ __device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, i
             dst[o] = (unsigned)(i0 + o) < (unsigned)P ? w : (T)0;  // 0 <= i0 + o < P
         }
     }
+}
+
+// Load, stage and factor the chunk of points [base, min(j1, base + CH)).
+template <typename T, int NC, int TZ, int CH>
+__device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, int loz, int base, int j1,
+                                           int bm, int64_t n, const int* __restrict__ bpack_s,
+                                           const T* __restrict__ coff_s, const T* __restrict__ src_s,
+                                           T (*s_w)[32 + TZ], T (*s_c)[3], T (*s_v)[NC], int* s_bp,
+                                           int& s_cnt) {
+    ChunkPoint<T, NC> pt;
+    load_point<T, NC, CH>(pt, base, j1, bm, n, bpack_s, coff_s, src_s);
+    const int cnt = stage_points<T, NC, TZ>(pt, g.P, lox, loy, loz, s_c, s_v, s_bp, s_cnt);
+    chunk_factors<T, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
     return cnt;
 }
 
@@ -244,7 +270,7 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int NC, int CH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_spread_mfma(GridGeo g, const int* __restrict__ tile_start,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4 : 3))) void k_spread_mfma(GridGeo g, const int* __restrict__ tile_start,
                                                     const int* __restrict__ bpack_s,
                                                     const float* __restrict__ coff_s,
                                                     const float* __restrict__ src_s, int64_t n,
@@ -277,49 +303,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int bx0 = max(0, lox - P + 1) / TB, bx1 = min(Mt - P, lox + 15) / TB;
     const int by0 = max(0, loy - P + 1) / TB, by1 = min(Mt - P, loy + 15) / TB;
     const int bz0 = max(0, loz - P + 1) / TB, bz1 = min(Mt - P, loz + TZ - 1) / TB;
-    for (int sz = bz0; sz <= bz1; ++sz)
-        for (int sy = by0; sy <= by1; ++sy) {
-            const int row = (sz * nb + sy) * nb;
-            const int j0 = tile_start[row + bx0], j1 = tile_start[row + bx1 + 1];
-            for (int base = j0; base < j1; base += CH) {
-                const int cnt = stage_chunk<float, NC, TZ, CH>(g, lox, loy, loz, base, j1, bm, n, bpack_s,
-                                                               coff_s, src_s, s_w, s_c, s_v, s_bp, s_cnt);
-                int nl = 0;
-                for (int k0 = 0; k0 < cnt; k0 += 64) {
-                    const int k = k0 + lane;
-                    bool hit = false;
-                    if (k < cnt) {
-                        const int bp = s_bp[k];
-                        const int bx = bp & 1023, by = (bp >> 10) & 1023;
-                        hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
-                                by + P <= loy + wy0);
-                    }
-                    const unsigned long long m = __ballot(hit);
-                    if (hit) s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)k;
-                    nl += __popcll(m);
-                }
-                __syncthreads();
-                // four listed points per step; slots past the list get zero A operands
-                // (their B operands read point 0's factors, which are finite)
-                for (int l0 = 0; l0 < nl; l0 += 4) {
-                    const bool ok = l0 + kl < nl;
-                    const int k = ok ? (int)s_list[wid][l0 + kl] : 0;
-                    const float wz = ok ? s_w[k][32 + cl] : 0.f;
-                    const float wx = s_w[k][xo];
-                    float a[NC];
+    // The chunks run as one sequence over the bin rows (sz, sy), row r = (sz - bz0)
+    // nry + sy - by0, each row's range cut into chunks of CH.  The next chunk's
+    // range and points are loaded while the current one is processed, so neither
+    // memory latency waits behind the chunk's barriers.
+    const int nry = by1 - by0 + 1, nrows = (nry > 0 && bz1 >= bz0) ? (bz1 - bz0 + 1) * nry : 0;
+    // first non-empty row from r on: its range in [jb, je), or r = nrows
+    auto find_row = [&](int r, int& jb, int& je) {
+        for (; r < nrows; ++r) {
+            const int rz = r / nry;
+            const int row = ((bz0 + rz) * nb + by0 + (r - rz * nry)) * nb;
+            jb = tile_start[row + bx0];
+            je = tile_start[row + bx1 + 1];
+            if (jb < je) break;
+        }
+        return r;
+    };
+    int r = 0, base = 0, end = 0;
+    r = find_row(0, base, end);
+    ChunkPoint<float, NC> pt;
+    if (r < nrows) load_point<float, NC, CH>(pt, base, end, bm, n, bpack_s, coff_s, src_s);
+    while (r < nrows) {
+        const int cnt = stage_points<float, NC, TZ>(pt, P, lox, loy, loz, s_c, s_v, s_bp, s_cnt);
+        // the next chunk: the rest of this row, else the next non-empty row
+        int nr = r, nbase = base + CH, nend = end;
+        if (nbase >= end) nr = find_row(r + 1, nbase, nend);
+        if (nr < nrows) load_point<float, NC, CH>(pt, nbase, nend, bm, n, bpack_s, coff_s, src_s);
+        chunk_factors<float, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
+        int nl = 0;
+        for (int k0 = 0; k0 < cnt; k0 += 64) {
+            const int k = k0 + lane;
+            bool hit = false;
+            if (k < cnt) {
+                const int bp = s_bp[k];
+                const int bx = bp & 1023, by = (bp >> 10) & 1023;
+                hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
+                        by + P <= loy + wy0);
+            }
+            const unsigned long long m = __ballot(hit);
+            if (hit) s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)k;
+            nl += __popcll(m);
+        }
+        __syncthreads();
+        // four listed points per step; slots past the list get zero A operands
+        // (their B operands read point 0's factors, which are finite)
+        for (int l0 = 0; l0 < nl; l0 += 4) {
+            const bool ok = l0 + kl < nl;
+            const int k = ok ? (int)s_list[wid][l0 + kl] : 0;
+            const float wz = ok ? s_w[k][32 + cl] : 0.f;
+            const float wx = s_w[k][xo];
+            float a[NC];
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) a[c] = wz * s_v[k][c];
+            for (int c = 0; c < NC; ++c) a[c] = wz * s_v[k][c];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const float bb = wx * s_w[k][16 + yo + 2 * b];
+            for (int b = 0; b < 4; ++b) {
+                const float bb = wx * s_w[k][16 + yo + 2 * b];
 #pragma unroll
-                        for (int c = 0; c < NC; ++c)
-                            acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], bb, acc[c][b], 0, 0, 0);
-                    }
-                }
-                __syncthreads();
+                for (int c = 0; c < NC; ++c)
+                    acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], bb, acc[c][b], 0, 0, 0);
             }
         }
+        __syncthreads();
+        r = nr;
+        base = nbase;
+        end = nend;
+    }
     const int64_t M3 = (int64_t)Mt * Mt * Mt;
     const int gx = lox + xo;
 #pragma unroll
