@@ -120,6 +120,32 @@ def test_stage_grids(kernel):
     plan.close()
 
 
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
+@pytest.mark.parametrize("M,P,Mt", [(24, 10, 35), (20, 12, 0), (8, 7, 0)])
+def test_spread_grid_f32(kernel, M, P, Mt):
+    """FP32 spreading (the matrix-core kernel) node by node against the oracle's grid
+    of the FP32-rounded inputs: cores cut by the grid edge (Mt not a multiple of 16),
+    the headline P, and a grid about one core wide with odd P."""
+    n = 900
+    params = F.make_params(10.0, 0.32, M, P, L=1.0, Mt=Mt)
+    x, a, b = _inputs(kernel, n, 90)
+    plan = _plan(kernel, "f32", params, n)
+    plan.set_points(_t(x, "f32"))
+    plan.eval_parts(_t(a, "f32"), None if b is None else _t(b, "f32"))
+    g = _oracle_geo(plan, params)
+    x64, a64, b64 = _as64(x, "f32"), _as64(a, "f32"), _as64(b, "f32")
+    grid_o = se.spread(x64, se.sources_grid(kernel, a64, b64), g)
+    if kernel == "stresslet":
+        sym = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+        grid_o = np.array([0.5 * (grid_o[3 * l + m] + grid_o[3 * m + l]) for l, m in sym])
+    norm = (g.alpha / math.pi) ** 1.5
+    G = plan.grid(0)[0].astype(np.float64)
+    e = relmax(np.transpose(G, (0, 3, 2, 1)) * norm, grid_o)
+    print(kernel, "Mt", g.Mt, "P", P, "FP32 spread err %.2e" % e)
+    assert e < 2e-6
+    plan.close()
+
+
 CASES = [
     # (n, xi, rc, M, P, Mt, L, lo); eta = xi^2 h^2 P / (C^2 pi) < 0.7 in every case, so
     # the middle factor exp(-(1-eta) k^2/4xi^2) of the Gaussian splitting is a
