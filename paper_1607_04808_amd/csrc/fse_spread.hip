@@ -548,9 +548,15 @@ __global__ __launch_bounds__(64 * GW) void k_gather_lds(GridGeo g, const int* __
 // over window rows).
 // ---------------------------------------------------------------------------
 constexpr int CW = 8;  // waves per sweeping workgroup
+// FP64 value quadrature with one component per pass: its ring leaves one workgroup
+// per CU and a bin step holds about ten points, so it runs 12 waves (one point each)
+#ifndef FSE_CW64V
+#define FSE_CW64V 12
+#endif
+constexpr int CW64V = FSE_CW64V;
 
-template <typename T, int MODE, int NCS, int GP, int PT>
-__global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int segb, int ES, int PS,
+template <typename T, int MODE, int NCS, int GP, int PT, int NW = CW>
+__global__ __launch_bounds__(64 * NW) void k_gather_col(GridGeo g, int KX, int segb, int ES, int PS,
                                                        const int* __restrict__ tile_start,
                                                        const int* __restrict__ perm_s,
                                                        const int* __restrict__ bpack_s,
@@ -608,7 +614,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
         const int s1 = z1 % EZ;
         const int nv = min(npl, Mt - z1);
         const int64_t MM = (int64_t)Mt * Mt;
-        for (int q = tid; q < NCS * E2; q += 64 * CW) {
+        for (int q = tid; q < NCS * E2; q += 64 * NW) {
             const int c = NCS == 1 ? 0 : small_div(q, E2);
             const int t = q - c * E2;
             const int y = small_div(t, E), x = t - y * E;
@@ -635,7 +641,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
             }
         }
     };
-    for (int q = tid; q < NCS * CS; q += 64 * CW) sm[q] = (T)0;
+    for (int q = tid; q < NCS * CS; q += 64 * NW) sm[q] = (T)0;
     for (int bm = bm0; bm < bm1; ++bm) {
         for (int cs = 0; cs < 3; cs += NCS) {
             const T* fb = field + ((int64_t)bm * 3 + cs) * M3;
@@ -655,7 +661,7 @@ __global__ __launch_bounds__(64 * CW) void k_gather_col(GridGeo g, int KX, int s
                 for (int by = by0; by <= by1; ++by) {
                     const int rowb = (tz * nb + by) * nb;
                     const int j0 = tile_start[rowb + bx0], j1 = tile_start[rowb + bx1 + 1];
-                    for (int jb = j0 + wid * GP; jb < j1; jb += CW * GP) {
+                    for (int jb = j0 + wid * GP; jb < j1; jb += NW * GP) {
                         const int j = jb + grp;
                         const bool valid = j < j1;
                         const int bp = valid ? bpack_s[j] : 0;
@@ -1040,9 +1046,9 @@ static int bank_cost(int P, int es, int ps, int elem_bytes) {
 // FP64 (whose field ring leaves no LDS for four points' factors)
 template <typename T> constexpr int col_gp() { return sizeof(T) == 4 ? 4 : 1; }
 
-template <typename T> ColCfg col_config(const GridGeo& g) {
+template <typename T> ColCfg col_config(const GridGeo& g, int waves = CW) {
     ColCfg best{0, 0, 0, 0, 0, 0, 0, 0};
-    const size_t wbytes = (size_t)CW * col_gp<T>() * 6 * ((g.P + 3) & ~3) * sizeof(T);
+    const size_t wbytes = (size_t)waves * col_gp<T>() * 6 * ((g.P + 3) & ~3) * sizeof(T);
     const size_t limit = 160 * 1024 - wbytes;
     // all components per pass when they fit; one-bin tiles measured as fast as
     // two-bin ones (less LDS, two workgroups per CU)
@@ -1083,22 +1089,33 @@ template <typename T> ColCfg col_config(const GridGeo& g) {
 template <typename T>
 void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int batch, T* u,
                    hipStream_t st) {
-    const ColCfg cc = col_config<T>(g);
+    ColCfg cc = col_config<T>(g);
+    bool wide = false;  // CW64V waves (FP64, one component per pass)
+    if (sizeof(T) == 8 && cc.ncs == 1) {
+        const ColCfg cw = col_config<T>(g, CW64V);
+        if (cw.ncs == 1) { cc = cw; wide = true; }
+    }
     if (cc.ncs) {
         const dim3 grd(cc.ncol * cc.nseg, batch);
-#define GCOL(NC, PT)                                                                                           \
-    allow_lds(k_gather_col<T, 0, NC, col_gp<T>(), PT>, cc.lds);                                                \
-    hipLaunchKernelGGL((k_gather_col<T, 0, NC, col_gp<T>(), PT>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx,    \
-                       cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field,              \
+#define GCOL(NC, PT, NWV)                                                                                      \
+    allow_lds(k_gather_col<T, 0, NC, col_gp<T>(), PT, NWV>, cc.lds);                                           \
+    hipLaunchKernelGGL((k_gather_col<T, 0, NC, col_gp<T>(), PT, NWV>), grd, dim3(64 * NWV), cc.lds, st, g,     \
+                       cc.kx, cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field,       \
                        (const T*)nullptr, p.n, batch, u, (T*)nullptr)
-#define GCOLP(NC)                                                                                              \
+#define GCOLP(NC, NWV)                                                                                         \
     switch ((g.P + 3) & ~3) {                                                                                  \
-        case 12: GCOL(NC, 12); break;                                                                          \
-        case 16: GCOL(NC, 16); break;                                                                          \
-        case 20: GCOL(NC, 20); break;                                                                          \
-        default: GCOL(NC, 0); break;                                                                           \
+        case 12: GCOL(NC, 12, NWV); break;                                                                     \
+        case 16: GCOL(NC, 16, NWV); break;                                                                     \
+        case 20: GCOL(NC, 20, NWV); break;                                                                     \
+        default: GCOL(NC, 0, NWV); break;                                                                      \
     }
-        if (cc.ncs == 3) { GCOLP(3); } else { GCOLP(1); }
+        if (cc.ncs == 3) {
+            GCOLP(3, CW);
+        } else if (wide) {
+            GCOLP(1, CW64V);
+        } else {
+            GCOLP(1, CW);
+        }
 #undef GCOLP
 #undef GCOL
         return;
