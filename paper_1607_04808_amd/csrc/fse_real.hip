@@ -104,9 +104,16 @@ __device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, flo
 #define FSE_REAL_CH64 160
 #endif
 // queued hits per thread before the wave flushes (deeper FP64 queues cost less
-// occupancy than the extra flushes)
-template <typename T>
-constexpr int qcap() { return sizeof(T) == 4 ? 32 : 48; }
+// occupancy than the extra flushes; in FP32 the gradient pass, whose pairs cost twice
+// as much, measured faster at 48 and the value pass at 32, of 24, 32 and 48)
+#ifndef FSE_QCAP32
+#define FSE_QCAP32 32
+#endif
+#ifndef FSE_QCAP32G
+#define FSE_QCAP32G 48
+#endif
+template <typename T, bool GRAD>
+constexpr int qcap() { return sizeof(T) == 4 ? (GRAD ? FSE_QCAP32G : FSE_QCAP32) : 48; }
 // 1 when the sign bit of v is set (v < 0 or v = -0), else 0
 __device__ __forceinline__ unsigned sign_bit(float v) { return __float_as_uint(v) >> 31; }
 __device__ __forceinline__ unsigned sign_bit(double v) {
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         const int QROW = queue_row(nthr);
         const int qsh = QROW == 64 ? 7 : QROW == 128 ? 8 : 9;  // log2 of a row in bytes
         unsigned short* const q0 = qd + tid;
-        unsigned short* const qlim = q0 + (qcap<T>() - 8) * QROW;
+        unsigned short* const qlim = q0 + (qcap<T, GRAD>() - 8) * QROW;
         unsigned short* qp = q0;
         // widened test threshold folded into the target term: a hit is a negative sign
         const T Atc = At - rc2t;
@@ -592,7 +599,7 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned thr = (unsigned)p.real_S;
     // at most ceil(n / S) + ncells work items; the surplus workgroups return at once
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)qcap<T>() * queue_row((int)thr) * sizeof(unsigned short);
+    const size_t qbytes = (size_t)qcap<T, false>() * queue_row((int)thr) * sizeof(unsigned short);
     dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
     hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p.cell_start, p.x_r, src_a_r, \
@@ -614,7 +621,7 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.real_S;
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)qcap<T>() * queue_row((int)thr) * sizeof(unsigned short);
+    const size_t qbytes = (size_t)qcap<T, true>() * queue_row((int)thr) * sizeof(unsigned short);
     // batch members in groups of 4 per pass; each pass adds to dx (and dsrc)
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
