@@ -8,9 +8,9 @@
 // Points are binned by the bin (TB^3 nodes, TB = GridGeo::TS) holding their
 // window start, x-fastest bin order, so a row of bins is one contiguous range.
 //
-// Spreading: output-stationary (see k_spread); every node is written exactly
-// once, coalesced, by the thread that owns it: no floating-point atomics and no
-// clearing of the grid.  The order in which a node's terms are summed follows
+// Spreading: output-stationary (k_spread_mfma in FP32, on the matrix cores;
+// k_spread in FP64); every node is written exactly once, coalesced, by the lane
+// that accumulated it: no floating-point atomics and no clearing of the grid.  The order in which a node's terms are summed follows
 // the staging order of its points, which an LDS counter sets, so repeated runs
 // agree to rounding, not bit for bit.
 //
