@@ -180,6 +180,47 @@ fse_status_t fse_plan_set_timing(fse_plan_t *plan, int32_t enable);
 fse_status_t fse_plan_timings(fse_plan_t *plan, double *ms, int64_t *launches);
 const char *fse_stage_name(int32_t stage);
 
+/*
+ * Truncation-error estimates for a parameter set (host only): the RMS over
+ * targets of the real-space truncation error, Table est_real (Section 7.2),
+ * and of the Fourier-space truncation error, Table est_fourier (Section 7.1,
+ * with kinf = pi/h and R = sqrt(3) Lt), both absolute.  Q = sum_n |f_n|^2
+ * (stokeslet, rotlet; eq. Q_stokeslet) or sum_n |q_n|^2 |n_n|^2 (stresslet,
+ * eq. Q_stresslet).  Either output may be NULL.
+ */
+fse_status_t fse_error_estimates(fse_kernel_t kernel, const fse_params_t *params, double Q,
+                                 double *est_real, double *est_fourier);
+
+/*
+ * Parameter selection (host only; Section 8.2).  For n points in the cube
+ * [box_lo, box_lo + L)^3 and a target relative max-norm error rel_tol, picks
+ * P = 2 points per digit of rel_tol (even, in [8, 32]; Section 8.2's 16 for 8
+ * digits and 24 for 12), and for each xi of a geometric sweep the r_c and M
+ * that hold the estimates of Tables est_real and est_fourier at an absolute
+ * RMS target eps = rel_tol * share * u_rms / sqrt 2 (share = 1 in FP64, 1/2 in
+ * FP32 to leave room for rounding); FP32 plans also keep eta <= 0.7.  Of the
+ * sweep it returns the xi (with its r_c, M, P and Mt = the smallest 7-smooth
+ * size above M + P) that minimises a cost model of this library's kernels on
+ * one MI355X (real-space pairs, transform nodes, window nodes; uniform
+ * density assumed).  Q as in fse_error_estimates; u_rms is the RMS of |u| over
+ * the targets, or <= 0 for an estimate for points uniform in the cube.
+ * FSE_EINVAL for rel_tol outside (0, 1), FP32 with rel_tol < 1e-6, or when no
+ * xi fits the grid limit.  deltaL_rule = 0 and C = 0 in *out.
+ */
+fse_status_t fse_choose_params(fse_kernel_t kernel, fse_dtype_t dtype, int64_t n, const double box_lo[3],
+                               double L, double rel_tol, double Q, double u_rms, fse_params_t *out);
+
+/*
+ * Bounding-cube default of the box (Section 8 assumes a cube holding every
+ * point): box_lo = the componentwise minimum of the n points x (device, (n,3),
+ * dtype) and L = the largest extent times (1 + 2^-20), so that the largest
+ * coordinate lies strictly inside [box_lo, box_lo + L).  Runs a reduction on
+ * `stream` (a hipStream_t) and synchronises it; allocates a small temporary.
+ * FSE_ERANGE if a coordinate is not finite.
+ */
+fse_status_t fse_bounding_box(fse_dtype_t dtype, int64_t n, const void *x, void *stream,
+                              double box_lo[3], double *L);
+
 /* Device bytes held by the plan.  Synchronises nothing. */
 fse_status_t fse_plan_workspace(const fse_plan_t *plan, size_t *bytes);
 

@@ -4,5 +4,6 @@ rotlet sums (af Klinteberg, Shamshirgar & Tornberg, arXiv:1607.04808).
 The computation lives in the HIP library ``lib/libfse.so`` (C ABI in
 ``include/fse.h``); :mod:`.fse` is its Python binding.
 """
-from .fse import (FseError, Geometry, Plan, Params, fse_sum, geometry, lib,  # noqa: F401
-                  make_params)
+from .fse import (FseError, Geometry, Plan, Params, bounding_box, choose_params,  # noqa: F401
+                  error_estimates, fse_sum, geometry, lib, make_params, rotlet, stokeslet,
+                  stresslet)

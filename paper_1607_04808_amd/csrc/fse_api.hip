@@ -201,6 +201,15 @@ struct TimedStage {
 
 }  // namespace
 
+namespace fse {
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+}  // namespace fse
+
 struct fse_plan {
     fse_kernel_t kernel;
     fse_dtype_t dtype;
@@ -220,7 +229,10 @@ struct fse_plan {
     Timer timer;
 
     // points
-    int *key_s, *rank_s, *key_r, *rank_r, *bpack, *perm_s, *bpack_s, *perm_r, *inv_r;
+    int *key_s, *key_r, *idx, *key_tmp, *bpack, *perm_s, *bpack_s, *perm_r, *inv_r;
+    void* sort_tmp;
+    size_t sort_bytes = 0;
+    int bits_s = 1, bits_r = 1;
     void *coff, *coff_s, *x_r;
     int *cnt_s, *start_s, *cnt_r, *start_r, *work_r, *scan_tmp, *flag;
     int real_S = 256;
@@ -234,10 +246,32 @@ struct fse_plan {
     void* tw;
     int *rev, *revinv;
 
+    // Workspace source: hipMalloc (a plan), or carved in 256-byte steps from a
+    // caller-owned device arena (the no-allocation entry point); `dry` counts the
+    // carved bytes without touching memory.
+    char* arena = nullptr;
+    size_t arena_cap = 0;
+    bool dry = false;
+
     template <typename X> fse_status_t alloc(X** p, size_t count) {
         void* q = nullptr;
         size_t b = count * sizeof(X);
         if (b == 0) b = 16;
+        if (arena || dry) {
+            b = (b + 255) & ~(size_t)255;
+            if (dry) {
+                *p = nullptr;
+                bytes += b;
+                return FSE_OK;
+            }
+            if (bytes + b > arena_cap) {
+                set_err("workspace of %zu bytes exceeds the %zu-byte arena", bytes + b, arena_cap);
+                return FSE_EINVAL;
+            }
+            *p = (X*)(arena + bytes);
+            bytes += b;
+            return FSE_OK;
+        }
         hipError_t e = hipMalloc(&q, b);
         if (e != hipSuccess) {
             set_err("hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
@@ -283,9 +317,9 @@ template <typename T> fse_status_t allocate(fse_plan* p) {
     const int64_t M3 = Mt * Mt * Mt;
     using V = C2<T>;
     TRY(p->alloc(&p->key_s, nm));
-    TRY(p->alloc(&p->rank_s, nm));
     TRY(p->alloc(&p->key_r, nm));
-    TRY(p->alloc(&p->rank_r, nm));
+    TRY(p->alloc(&p->idx, nm));
+    TRY(p->alloc(&p->key_tmp, nm));
     TRY(p->alloc(&p->bpack, nm));
     TRY(p->alloc(&p->perm_s, nm));
     TRY(p->alloc(&p->bpack_s, nm));
@@ -304,6 +338,14 @@ template <typename T> fse_status_t allocate(fse_plan* p) {
     const size_t st = scan_tmp_ints(p->ntiles3 + 1) > scan_tmp_ints(p->ncells3 + 1)
                           ? scan_tmp_ints(p->ntiles3 + 1) : scan_tmp_ints(p->ncells3 + 1);
     TRY(p->alloc(&p->scan_tmp, st));
+    p->bits_s = key_bits(p->ntiles3);
+    p->bits_r = key_bits(p->ncells3);
+    {
+        const size_t b1 = sort_tmp_bytes(nm, p->bits_s), b2 = sort_tmp_bytes(nm, p->bits_r);
+        if (b1 == 0 || b2 == 0) { set_err("sort workspace query failed"); return FSE_EHIP; }
+        p->sort_bytes = b1 > b2 ? b1 : b2;
+        TRY(p->alloc((char**)&p->sort_tmp, p->sort_bytes));
+    }
     TRY(p->alloc(&p->flag, 1));
     TRY(p->alloc((T**)&p->src_s, B * nm * p->c_in));
     TRY(p->alloc((T**)&p->src_ra, B * nm * 3));
@@ -341,20 +383,30 @@ template <typename T> fse_status_t upload_fft_tables(fse_plan* p) {
     return FSE_OK;
 }
 
-// Section 4.3 precompute, FP64, then fold in the scalar factors.
+// Section 4.3 precompute, FP64, then fold in the scalar factors.  Its four
+// temporaries come from hipMalloc (freed at the end), or from the plan's arena.
 template <typename T> fse_status_t precompute(fse_plan* p) {
     const int Mt = p->geo.Mt, Mg = p->geo.Mg, Mp = Mt + 1, H = Mg / 2 + 1;
     const int64_t big = (int64_t)H * H * H > (int64_t)Mp * H * H ? (int64_t)H * H * H : (int64_t)Mp * H * H;
     double *t0 = nullptr, *t1 = nullptr, *c1 = nullptr, *c2 = nullptr;
+    const bool carve = p->arena || p->dry;
     auto cleanup = [&]() {
+        if (carve) return;
         if (t0) (void)hipFree(t0);
         if (t1) (void)hipFree(t1);
         if (c1) (void)hipFree(c1);
         if (c2) (void)hipFree(c2);
     };
-    if (hipMalloc(&t0, big * sizeof(double)) != hipSuccess || hipMalloc(&t1, big * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c1, (size_t)Mp * H * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c2, (size_t)Mp * Mp * sizeof(double)) != hipSuccess) {
+    if (carve) {
+        TRY(p->alloc(&t0, big));
+        TRY(p->alloc(&t1, big));
+        TRY(p->alloc(&c1, (size_t)Mp * H));
+        TRY(p->alloc(&c2, (size_t)Mp * Mp));
+        if (p->dry) return FSE_OK;
+    } else if (hipMalloc(&t0, big * sizeof(double)) != hipSuccess ||
+               hipMalloc(&t1, big * sizeof(double)) != hipSuccess ||
+               hipMalloc(&c1, (size_t)Mp * H * sizeof(double)) != hipSuccess ||
+               hipMalloc(&c2, (size_t)Mp * Mp * sizeof(double)) != hipSuccess) {
         cleanup();
         set_err("precompute: out of device memory");
         return FSE_ENOMEM;
@@ -412,6 +464,18 @@ template <typename T> fse_status_t plan_init(fse_plan* p) {
     return FSE_OK;
 }
 
+// Device bytes plan_init would take (workspace plus the precompute's temporaries).
+template <typename T> fse_status_t plan_bytes(fse_plan* p, size_t* out) {
+    p->dry = true;
+    p->bytes = 0;
+    fse_status_t rc = allocate<T>(p);
+    if (rc == FSE_OK) rc = precompute<T>(p);
+    p->dry = false;
+    *out = p->bytes;
+    p->bytes = 0;
+    return rc;
+}
+
 template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T* x, int validate) {
     hipStream_t st = p->stream;
     {
@@ -419,17 +483,23 @@ template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T*
         launch_fill_i32(p->cnt_s, p->ntiles3 + 1, 0, st);
         launch_fill_i32(p->cnt_r, p->ncells3 + 1, 0, st);
         launch_fill_i32(p->flag, 1, 0, st);
-        launch_bin<T>(x, n, p->gg, p->cg, p->key_s, p->rank_s, p->key_r, p->rank_r, p->cnt_s, p->cnt_r,
-                      p->bpack, (T*)p->coff, p->flag, st);
+        launch_bin<T>(x, n, p->gg, p->cg, p->key_s, p->key_r, p->idx, p->cnt_s, p->cnt_r, p->bpack, (T*)p->coff,
+                      p->flag, st);
+        // stable sorts by tile and by cell: perm_s and perm_r list the point indices in order
+        if (sort_tmp_bytes(n, p->bits_s) > p->sort_bytes || sort_tmp_bytes(n, p->bits_r) > p->sort_bytes) {
+            set_err("sort workspace too small for n=%lld", (long long)n);
+            return FSE_EINVAL;
+        }
+        HIPCHK(launch_sort_pairs(p->sort_tmp, p->sort_bytes, p->key_s, p->key_tmp, p->idx, p->perm_s, n, p->bits_s, st));
+        HIPCHK(launch_sort_pairs(p->sort_tmp, p->sort_bytes, p->key_r, p->key_tmp, p->idx, p->perm_r, n, p->bits_r, st));
         launch_scan_exclusive(p->cnt_s, p->start_s, p->ntiles3 + 1, p->scan_tmp, st);
         launch_scan_exclusive(p->cnt_r, p->start_r, p->ncells3 + 1, p->scan_tmp, st);
         // real-space work items: slices of up to real_S targets of one cell
         p->real_S = (int)real_threads(n, p->ncells3);
         launch_cell_slices(p->cnt_r, p->ncells3, p->real_S, st);
         launch_scan_exclusive(p->cnt_r, p->work_r, p->ncells3 + 1, p->scan_tmp, st);
-        launch_scatter<T>(x, n, p->key_s, p->rank_s, p->start_s, p->key_r, p->rank_r, p->start_r, p->bpack,
-                          (const T*)p->coff, p->perm_s, p->bpack_s, (T*)p->coff_s, p->perm_r, (T*)p->x_r,
-                          p->inv_r, st);
+        launch_scatter<T>(x, n, p->perm_s, p->perm_r, p->bpack, (const T*)p->coff, p->bpack_s, (T*)p->coff_s,
+                          (T*)p->x_r, p->inv_r, st);
     }
     LAUNCHCHK();
     p->n = n;
@@ -545,38 +615,27 @@ fse_status_t adjoint_t(fse_plan* p, const T* f, const T* w, T* dsrc, T* dx, int 
 
 }  // namespace
 
-extern "C" {
 
-const char* fse_last_error(void) { return g_err; }
+namespace {
 
-const char* fse_status_string(fse_status_t s) {
-    switch (s) {
-        case FSE_OK: return "ok";
-        case FSE_EINVAL: return "invalid argument";
-        case FSE_ERANGE: return "point outside the box";
-        case FSE_ENOMEM: return "out of device memory";
-        case FSE_EHIP: return "HIP runtime error";
-        case FSE_EUNSUPPORTED: return "unsupported";
-        case FSE_ESTATE: return "call order violated";
-    }
-    return "unknown status";
-}
-
-fse_status_t fse_geometry(fse_kernel_t kernel, const fse_params_t* params, fse_geometry_t* out) {
-    return compute_geometry(kernel, params, out);
-}
-
-fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t* params, int32_t batch,
-                             int64_t nmax, void* stream, fse_plan_t** out) {
-    if (!out) { set_err("null plan pointer"); return FSE_EINVAL; }
-    *out = nullptr;
+fse_status_t check_plan_args(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t* params, int32_t batch,
+                             int64_t nmax, fse_geometry_t* geo) {
     if (dtype != FSE_F32 && dtype != FSE_F64) { set_err("unknown dtype"); return FSE_EINVAL; }
     if (batch < 1) { set_err("batch must be >= 1"); return FSE_EINVAL; }
     if (nmax < 2 || nmax > (int64_t)1 << 30) { set_err("nmax must be in [2, 2^30]"); return FSE_EINVAL; }
-    fse_geometry_t geo;
-    TRY(compute_geometry(kernel, params, &geo));
-    fse_plan* p = new (std::nothrow) fse_plan();
-    if (!p) { set_err("host allocation failed"); return FSE_ENOMEM; }
+    TRY(compute_geometry(kernel, params, geo));
+    if (dtype == FSE_F32 && !(geo->eta < 1.0)) {
+        // for eta >= 1 the scaling factor exp(-(1 - eta) k^2 / 4 xi^2) of Section 5.3
+        // grows with k and amplifies the FP32 rounding of the spread grid and the FFTs
+        set_err("eta = %.3f >= 1: the FP32 form needs eta < 1 (smaller xi h P, or larger M)", geo->eta);
+        return FSE_EINVAL;
+    }
+    return FSE_OK;
+}
+
+// Fill a plan's constants: kernel, dtype, geometry, bin/cell/FFT descriptors.
+void setup_plan(fse_plan* p, fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t* params,
+                const fse_geometry_t& geo, int32_t batch, int64_t nmax, void* stream) {
     p->kernel = kernel;
     p->dtype = dtype;
     p->prm = *params;
@@ -626,6 +685,40 @@ fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
             s += 1;
         }
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fse_last_error(void) { return g_err; }
+
+const char* fse_status_string(fse_status_t s) {
+    switch (s) {
+        case FSE_OK: return "ok";
+        case FSE_EINVAL: return "invalid argument";
+        case FSE_ERANGE: return "point outside the box";
+        case FSE_ENOMEM: return "out of device memory";
+        case FSE_EHIP: return "HIP runtime error";
+        case FSE_EUNSUPPORTED: return "unsupported";
+        case FSE_ESTATE: return "call order violated";
+    }
+    return "unknown status";
+}
+
+fse_status_t fse_geometry(fse_kernel_t kernel, const fse_params_t* params, fse_geometry_t* out) {
+    return compute_geometry(kernel, params, out);
+}
+
+fse_status_t fse_plan_create(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t* params, int32_t batch,
+                             int64_t nmax, void* stream, fse_plan_t** out) {
+    if (!out) { set_err("null plan pointer"); return FSE_EINVAL; }
+    *out = nullptr;
+    fse_geometry_t geo;
+    TRY(check_plan_args(kernel, dtype, params, batch, nmax, &geo));
+    fse_plan* p = new (std::nothrow) fse_plan();
+    if (!p) { set_err("host allocation failed"); return FSE_ENOMEM; }
+    setup_plan(p, kernel, dtype, params, geo, batch, nmax, stream);
     fse_status_t rc = dtype == FSE_F32 ? plan_init<float>(p) : plan_init<double>(p);
     if (rc != FSE_OK) {
         delete p;

@@ -1,6 +1,11 @@
 // Binning of the points (integer work): Gaussian-window starts and offsets in
-// FP64 (the P^3 windows of the fast Gaussian gridding, Section 5.2), counting
-// sort by spreading tile and by real-space cell (the cell list of Section 6).
+// FP64 (the P^3 windows of the fast Gaussian gridding, Section 5.2), and a
+// stable sort by spreading tile and by real-space cell (the cell list of
+// Section 6).  The sort is a stable LSD radix sort of (key, point index), so
+// within a tile or cell the points keep their input order and every later
+// summation order is the same from run to run.
+#include <hipcub/hipcub.hpp>
+
 #include "fse_common.h"
 
 namespace fse {
@@ -51,9 +56,8 @@ __global__ void k_scan_add(int* out, int64_t n, const int* offs) {
 }
 
 template <typename T>
-__global__ void k_bin(const T* __restrict__ x, int64_t n, GridGeo g, CellGeo c, int* key_s,
-                      int* rank_s, int* key_r, int* rank_r, int* cnt_s, int* cnt_r, int* bpack,
-                      T* coff, int* flag) {
+__global__ void k_bin(const T* __restrict__ x, int64_t n, GridGeo g, CellGeo c, int* key_s, int* key_r,
+                      int* idx, int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int b[3], cl[3];
@@ -78,27 +82,28 @@ __global__ void k_bin(const T* __restrict__ x, int64_t n, GridGeo g, CellGeo c, 
     int kr = (cl[2] * c.ncell + cl[1]) * c.ncell + cl[0];
     key_s[i] = ks;
     key_r[i] = kr;
-    rank_s[i] = atomicAdd(&cnt_s[ks], 1);
-    rank_r[i] = atomicAdd(&cnt_r[kr], 1);
+    idx[i] = (int)i;
+    // counts only: the order within a tile or cell comes from the stable sort
+    atomicAdd(&cnt_s[ks], 1);
+    atomicAdd(&cnt_r[kr], 1);
     if (bad) atomicOr(flag, 1);
 }
 
+// Gather the per-point data into the two sorted orders (perm_s and perm_r hold
+// the point index at each sorted position).
 template <typename T>
-__global__ void k_scatter(const T* __restrict__ x, int64_t n, const int* key_s, const int* rank_s,
-                          const int* start_s, const int* key_r, const int* rank_r, const int* start_r,
-                          const int* bpack, const T* coff, int* perm_s, int* bpack_s, T* coff_s,
-                          int* perm_r, T* x_r, int* inv_r) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int js = start_s[key_s[i]] + rank_s[i];
-    perm_s[js] = (int)i;
-    bpack_s[js] = bpack[i];
-    int jr = start_r[key_r[i]] + rank_r[i];
-    perm_r[jr] = (int)i;
-    inv_r[i] = jr;
+__global__ void k_scatter(const T* __restrict__ x, int64_t n, const int* __restrict__ perm_s,
+                          const int* __restrict__ perm_r, const int* __restrict__ bpack,
+                          const T* __restrict__ coff, int* bpack_s, T* coff_s, T* x_r, int* inv_r) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int is = perm_s[j];
+    bpack_s[j] = bpack[is];
+    const int ir = perm_r[j];
+    inv_r[ir] = (int)j;
     for (int d = 0; d < 3; ++d) {
-        coff_s[3 * js + d] = coff[3 * i + d];
-        x_r[3 * jr + d] = x[3 * i + d];
+        coff_s[3 * j + d] = coff[3 * (int64_t)is + d];
+        x_r[3 * j + d] = x[3 * (int64_t)ir + d];
     }
 }
 
@@ -191,21 +196,37 @@ void launch_scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStre
 }
 
 template <typename T>
-void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* rank_s,
-                int* key_r, int* rank_r, int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag,
-                hipStream_t st) {
-    hipLaunchKernelGGL(k_bin<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, g, c, key_s, rank_s,
-                       key_r, rank_r, cnt_s, cnt_r, bpack, coff, flag);
+void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* key_r, int* idx,
+                int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, g, c, key_s, key_r, idx, cnt_s,
+                       cnt_r, bpack, coff, flag);
+}
+
+int key_bits(int64_t nkeys) {
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < nkeys) ++b;
+    return b;
+}
+
+size_t sort_tmp_bytes(int64_t n, int bits) {
+    size_t b = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const int*)nullptr, (int*)nullptr, (const int*)nullptr,
+                                           (int*)nullptr, (int)n, 0, bits, (hipStream_t)0) != hipSuccess)
+        return 0;
+    return b;
+}
+
+hipError_t launch_sort_pairs(void* tmp, size_t tmp_bytes, const int* keys, int* keys_out, const int* vals,
+                             int* vals_out, int64_t n, int bits, hipStream_t st) {
+    size_t b = tmp_bytes;
+    return hipcub::DeviceRadixSort::SortPairs(tmp, b, keys, keys_out, vals, vals_out, (int)n, 0, bits, st);
 }
 
 template <typename T>
-void launch_scatter(const T* x, int64_t n, const int* key_s, const int* rank_s, const int* start_s,
-                    const int* key_r, const int* rank_r, const int* start_r, const int* bpack,
-                    const T* coff, int* perm_s, int* bpack_s, T* coff_s, int* perm_r, T* x_r,
-                    int* inv_r, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, key_s, rank_s,
-                       start_s, key_r, rank_r, start_r, bpack, coff, perm_s, bpack_s, coff_s, perm_r,
-                       x_r, inv_r);
+void launch_scatter(const T* x, int64_t n, const int* perm_s, const int* perm_r, const int* bpack, const T* coff,
+                    int* bpack_s, T* coff_s, T* x_r, int* inv_r, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, perm_s, perm_r, bpack, coff,
+                       bpack_s, coff_s, x_r, inv_r);
 }
 
 template <typename T>
@@ -221,11 +242,10 @@ void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, 
 }
 
 #define INST(T)                                                                                     \
-    template void launch_bin<T>(const T*, int64_t, const GridGeo&, const CellGeo&, int*, int*, int*, \
-                                int*, int*, int*, int*, T*, int*, hipStream_t);                     \
-    template void launch_scatter<T>(const T*, int64_t, const int*, const int*, const int*,          \
-                                    const int*, const int*, const int*, const int*, const T*, int*, \
-                                    int*, T*, int*, T*, int*, hipStream_t);                         \
+    template void launch_bin<T>(const T*, int64_t, const GridGeo&, const CellGeo&, int*, int*, int*, int*, \
+                                int*, int*, T*, int*, hipStream_t);                                 \
+    template void launch_scatter<T>(const T*, int64_t, const int*, const int*, const int*, const T*,   \
+                                    int*, T*, T*, int*, hipStream_t);                               \
     template void launch_permute_sources<T>(int, const T*, const T*, int64_t, int, const int*, T*,  \
                                             hipStream_t);                                           \
     template void launch_permute3<T>(const T*, int64_t, int, const int*, T*, hipStream_t);

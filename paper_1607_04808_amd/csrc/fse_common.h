@@ -155,6 +155,9 @@ template <typename T> struct PointsDev {
     int real_S;               // targets per real-space work item (= threads per workgroup)
 };
 
+// thread-local message returned by fse_last_error (printf format)
+void set_error(const char* fmt, ...);
+
 // ---------------------------------------------------------------------------
 // launchers (one per translation unit); all enqueue on `st`
 // ---------------------------------------------------------------------------
@@ -166,15 +169,23 @@ void launch_cell_slices(int* cnt, int64_t ncells, int S, hipStream_t st);
 unsigned real_threads(int64_t n, int64_t ncells);
 size_t scan_tmp_ints(int64_t n);
 
+// window starts/offsets, tile and cell keys, per-key counts (cnt_s, cnt_r
+// accumulate), idx[i] = i, flag |= 1 for a point outside the box
 template <typename T>
-void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* rank_s,
-                int* key_r, int* rank_r, int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag,
-                hipStream_t st);
+void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* key_r, int* idx,
+                int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag, hipStream_t st);
+// bits that hold keys in [0, nkeys)
+int key_bits(int64_t nkeys);
+// device scratch bytes of one launch_sort_pairs over n keys of `bits` bits (0 on failure)
+size_t sort_tmp_bytes(int64_t n, int bits);
+// stable radix sort of (keys, vals) by the low `bits` bits of the keys
+hipError_t launch_sort_pairs(void* tmp, size_t tmp_bytes, const int* keys, int* keys_out, const int* vals,
+                             int* vals_out, int64_t n, int bits, hipStream_t st);
+// sorted copies: bpack_s/coff_s in spread order (perm_s), x_r in real-space
+// order (perm_r), inv_r = the inverse of perm_r
 template <typename T>
-void launch_scatter(const T* x, int64_t n, const int* key_s, const int* rank_s, const int* start_s,
-                    const int* key_r, const int* rank_r, const int* start_r, const int* bpack,
-                    const T* coff, int* perm_s, int* bpack_s, T* coff_s, int* perm_r, T* x_r,
-                    int* inv_r, hipStream_t st);
+void launch_scatter(const T* x, int64_t n, const int* perm_s, const int* perm_r, const int* bpack, const T* coff,
+                    int* bpack_s, T* coff_s, T* x_r, int* inv_r, hipStream_t st);
 
 // source permutation to spread order: out (batch, n, c_in) with the per-point
 // components the grid carries (f_l, or the symmetric n_l q_m for the stresslet)

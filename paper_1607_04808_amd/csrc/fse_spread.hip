@@ -10,9 +10,9 @@
 //
 // Spreading: output-stationary (k_spread_mfma in FP32, on the matrix cores;
 // k_spread in FP64); every node is written exactly once, coalesced, by the lane
-// that accumulated it: no floating-point atomics and no clearing of the grid.  The order in which a node's terms are summed follows
-// the staging order of its points, which an LDS counter sets, so repeated runs
-// agree to rounding, not bit for bit.
+// that accumulated it: no floating-point atomics and no clearing of the grid.
+// A node's terms are summed in the sorted point order, so repeated runs agree
+// bit for bit.
 //
 // Quadrature: one workgroup per bin stages the (TB+P-1)^3 block of the field
 // that the bin's windows cover in LDS (when it fits) and each wave reduces one
@@ -64,28 +64,37 @@ __device__ __forceinline__ void load_point(ChunkPoint<T, NC>& pt, int base, int 
 }
 
 // Stage the loaded points whose window overlaps the core (lox, loy, loz) +
-// [0,16) x [0,16) x [0,TZ) into LDS, compacted (their order follows an LDS
-// counter).  Returns the number staged, the same in every thread.
+// [0,16) x [0,16) x [0,TZ) into LDS, compacted in thread order (wave ballots,
+// then the waves' counts in wave order), so the staged order is the sorted
+// point order.  Returns the number staged, the same in every thread.  s_wc
+// holds the four waves' counts; it is written before the first barrier, which
+// is safe because every read of it in the previous call precedes that call's
+// second barrier.
 template <typename T, int NC, int TZ>
 __device__ __forceinline__ int stage_points(const ChunkPoint<T, NC>& pt, int P, int lox, int loy, int loz,
-                                            T (*s_c)[3], T (*s_v)[NC], int* s_bp, int& s_cnt) {
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
+                                            T (*s_c)[3], T (*s_v)[NC], int* s_bp, int* s_wc) {
+    bool ov = false;
     if (pt.bp >= 0) {
         const int bx = pt.bp & 1023, by = (pt.bp >> 10) & 1023, bz = pt.bp >> 20;
-        const bool ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy &&
-                        bz <= loz + TZ - 1 && bz + P > loz;
-        if (ov) {
-            const int k = atomicAdd(&s_cnt, 1);
-            s_bp[k] = pt.bp;
+        ov = bx <= lox + 15 && bx + P > lox && by <= loy + 15 && by + P > loy && bz <= loz + TZ - 1 &&
+             bz + P > loz;
+    }
+    const unsigned long long m = __ballot(ov);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) s_wc[wid] = __popcll(m);
+    __syncthreads();
+    const int c0 = s_wc[0], c1 = s_wc[1], c2 = s_wc[2], c3 = s_wc[3];
+    if (ov) {
+        const int k = (wid > 0 ? c0 : 0) + (wid > 1 ? c1 : 0) + (wid > 2 ? c2 : 0) +
+                      __popcll(m & ((1ull << lane) - 1ull));
+        s_bp[k] = pt.bp;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) s_c[k][d] = pt.cc[d];
+        for (int d = 0; d < 3; ++d) s_c[k][d] = pt.cc[d];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) s_v[k][c] = pt.vv[c];
-        }
+        for (int c = 0; c < NC; ++c) s_v[k][c] = pt.vv[c];
     }
     __syncthreads();
-    return s_cnt;
+    return c0 + c1 + c2 + c3;
 }
 
 // Gaussian factors of the cnt staged points at the core's 16 + 16 + TZ node
@@ -124,10 +133,10 @@ __device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, i
                                            int bm, int64_t n, const int* __restrict__ bpack_s,
                                            const T* __restrict__ coff_s, const T* __restrict__ src_s,
                                            T (*s_w)[32 + TZ], T (*s_c)[3], T (*s_v)[NC], int* s_bp,
-                                           int& s_cnt) {
+                                           int* s_wc) {
     ChunkPoint<T, NC> pt;
     load_point<T, NC, CH>(pt, base, j1, bm, n, bpack_s, coff_s, src_s);
-    const int cnt = stage_points<T, NC, TZ>(pt, g.P, lox, loy, loz, s_c, s_v, s_bp, s_cnt);
+    const int cnt = stage_points<T, NC, TZ>(pt, g.P, lox, loy, loz, s_c, s_v, s_bp, s_wc);
     chunk_factors<T, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
     return cnt;
 }
@@ -155,7 +164,7 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     __shared__ T s_c[CH][3];
     __shared__ T s_v[CH][NC];
     __shared__ int s_bp[CH];
-    __shared__ int s_cnt;
+    __shared__ int s_wc[4];
     // per wave: the staged points whose window meets its tile, as k | (z-group mask << 8)
     __shared__ unsigned short s_list[4][CH];
     static_assert(CH <= 256 && TZ <= 32, "list entries: point index byte and z-group mask");
@@ -187,7 +196,7 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
             const int j0 = tile_start[row + bx0], j1 = tile_start[row + bx1 + 1];
             for (int base = j0; base < j1; base += CH) {
                 const int cnt = stage_chunk<T, NC, TZ, CH>(g, lox, loy, loz, base, j1, bm, n, bpack_s, coff_s,
-                                                           src_s, s_w, s_c, s_v, s_bp, s_cnt);
+                                                           src_s, s_w, s_c, s_v, s_bp, s_wc);
                 // this wave's list: the staged points whose window reaches its 8 x 8 tile
                 int nl = 0;
                 for (int k0 = 0; k0 < cnt; k0 += 64) {
@@ -280,7 +289,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4
     __shared__ float s_c[CH][3];
     __shared__ float s_v[CH][NC];
     __shared__ int s_bp[CH];
-    __shared__ int s_cnt;
+    __shared__ int s_wc[4];
     __shared__ unsigned char s_list[4][CH];  // per wave: the staged points that meet its tile
     static_assert(CH <= 256, "list entries are point index bytes");
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
@@ -324,7 +333,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4
     ChunkPoint<float, NC> pt;
     if (r < nrows) load_point<float, NC, CH>(pt, base, end, bm, n, bpack_s, coff_s, src_s);
     while (r < nrows) {
-        const int cnt = stage_points<float, NC, TZ>(pt, P, lox, loy, loz, s_c, s_v, s_bp, s_cnt);
+        const int cnt = stage_points<float, NC, TZ>(pt, P, lox, loy, loz, s_c, s_v, s_bp, s_wc);
         // the next chunk: the rest of this row, else the next non-empty row
         int nr = r, nbase = base + CH, nend = end;
         if (nbase >= end) nr = find_row(r + 1, nbase, nend);

@@ -23,7 +23,8 @@ STATUS = {0: "FSE_OK", 1: "FSE_EINVAL", 2: "FSE_ERANGE", 3: "FSE_ENOMEM", 4: "FS
 EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set_stream",
            "fse_set_points", "fse_eval", "fse_eval_parts", "fse_eval_adjoint", "fse_plan_multiplier",
            "fse_plan_workspace", "fse_plan_grid", "fse_plan_set_timing", "fse_plan_timings",
-           "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error")
+           "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error",
+           "fse_error_estimates", "fse_choose_params", "fse_bounding_box")
 NSTAGES = 12
 
 
@@ -77,6 +78,11 @@ def lib():
             L.fse_plan_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
             L.fse_stage_name.argtypes = [i32]
             L.fse_stage_name.restype = ctypes.c_char_p
+            dp = ctypes.POINTER(ctypes.c_double)
+            L.fse_error_estimates.argtypes = [ctypes.c_int, ctypes.POINTER(Params), ctypes.c_double, dp, dp]
+            L.fse_choose_params.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.POINTER(Params)]
+            L.fse_bounding_box.argtypes = [ctypes.c_int, i64, vp, vp, dp, dp]
             L.fse_plan_destroy.argtypes = [vp]
             L.fse_plan_destroy.restype = None
             L.fse_status_string.argtypes = [ctypes.c_int]
@@ -274,6 +280,34 @@ class Plan:
         return b.value
 
 
+def error_estimates(kernel, params: Params, Q):
+    """(est_real, est_fourier): Tables est_real and est_fourier (absolute RMS), host only."""
+    er, ef = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fse_error_estimates(_kid(kernel), ctypes.byref(params), float(Q), ctypes.byref(er),
+                                     ctypes.byref(ef)))
+    return er.value, ef.value
+
+
+def choose_params(kernel, dtype, n, box_lo, L, tol, Q, u_rms=0.0) -> Params:
+    """fse_choose_params (Section 8.2): parameters for a relative max-norm tolerance, host only."""
+    p = Params()
+    lo = (ctypes.c_double * 3)(*[float(v) for v in box_lo])
+    _check(lib().fse_choose_params(_kid(kernel), DTYPES[dtype], int(n), lo, float(L), float(tol), float(Q),
+                                   float(u_rms), ctypes.byref(p)))
+    return p
+
+
+def bounding_box(x):
+    """fse_bounding_box: (box_lo, L) of the bounding cube of the device points x (n, 3)."""
+    torch = _torch()
+    dtype = "f32" if x.dtype == torch.float32 else "f64"
+    x = x.contiguous()
+    lo = (ctypes.c_double * 3)()
+    L = ctypes.c_double()
+    _check(lib().fse_bounding_box(DTYPES[dtype], x.shape[0], _ptr(x), _stream_ptr(), lo, ctypes.byref(L)))
+    return tuple(lo), L.value
+
+
 def _autograd():
     torch = _torch()
 
@@ -313,3 +347,70 @@ def fse_sum(x, f, plan: Plan):
     if _FN is None:
         _FN = _autograd()
     return _FN.apply(x, f, plan)
+
+
+# ---------------------------------------------------------------------------
+# Tolerance-driven sums: the box is the points' bounding cube, the parameters
+# come from fse_choose_params, and the scale u_rms it needs comes from one coarse
+# evaluation (relative tolerance 1e-2) of the same sum.  Plans are cached by
+# kernel, dtype, batch, size and parameters.
+# ---------------------------------------------------------------------------
+_PLANS = {}
+_PLAN_CACHE = 4
+
+
+def _cached_plan(kernel, dtype, params: Params, batch, n):
+    key = (kernel, dtype, batch, n, params.xi, params.rc, params.M, params.P, tuple(params.box_lo), params.L,
+           params.Mt, params.deltaL_rule)
+    plan = _PLANS.get(key)
+    if plan is None:
+        while len(_PLANS) >= _PLAN_CACHE:
+            _PLANS.pop(next(iter(_PLANS))).close()
+        plan = Plan(kernel, dtype, params, batch=batch, nmax=n)
+        _PLANS[key] = plan
+    return plan
+
+
+def _source_norm(a, b):
+    """Q of eq. Q_stokeslet (sum |f|^2) or eq. Q_stresslet (sum |q|^2 |n|^2), summed over the batch."""
+    if b is None:
+        return float((a.double() * a.double()).sum())
+    return float(((a.double() ** 2).sum(-1) * (b.double() ** 2).sum(-1)).sum())
+
+
+def plan_for(kernel, x, a, b=None, tol=1e-6, dtype=None, u_rms=None):
+    """The cached plan fse_choose_params picks for these points and sources (and the points set)."""
+    torch = _torch()
+    if dtype is None:
+        dtype = "f32" if x.dtype == torch.float32 else "f64"
+    n = x.shape[0]
+    batch = 1 if a.dim() == 2 else a.shape[0]
+    box_lo, L = bounding_box(x.detach().to(torch.float32 if dtype == "f32" else torch.float64))
+    Q = _source_norm(a.detach(), None if b is None else b.detach()) / batch
+    if u_rms is None:
+        coarse = _cached_plan(kernel, dtype, choose_params(kernel, dtype, n, box_lo, L, 1e-2, Q), batch, n)
+        coarse.set_points(x.detach())
+        uc = coarse.eval(a.detach(), None if b is None else b.detach())
+        u_rms = float((uc.double() ** 2).sum(-1).mean().sqrt())
+    prm = choose_params(kernel, dtype, n, box_lo, L, tol, Q, u_rms)
+    return _cached_plan(kernel, dtype, prm, batch, n)
+
+
+def stokeslet(x, f, tol=1e-6, dtype=None, u_rms=None):
+    """u(x_m) = sum_{n != m} S(x_m - x_n) f_n at relative max-norm tolerance `tol`
+    (differentiable in x and f).  f: (n, 3) or (batch, n, 3)."""
+    plan = plan_for("stokeslet", x, f, None, tol, dtype, u_rms)
+    return fse_sum(x, f, plan)
+
+
+def rotlet(x, f, tol=1e-6, dtype=None, u_rms=None):
+    """u(x_m) = sum_{n != m} Omega(x_m - x_n) f_n at relative tolerance `tol` (differentiable in x and f)."""
+    plan = plan_for("rotlet", x, f, None, tol, dtype, u_rms)
+    return fse_sum(x, f, plan)
+
+
+def stresslet(x, q, nrm, tol=1e-6, dtype=None, u_rms=None):
+    """u_j(x_m) = sum_{n != m} T_jlm(x_m - x_n) q_l n_m at relative tolerance `tol`."""
+    plan = plan_for("stresslet", x, q, nrm, tol, dtype, u_rms)
+    plan.set_points(x.detach())
+    return plan.eval(q.detach(), nrm.detach()).reshape(q.shape)

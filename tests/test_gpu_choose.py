@@ -1,0 +1,112 @@
+"""Tolerance-driven evaluation: fse_bounding_box + fse_choose_params (Section 8.2,
+Tables est_real / est_fourier) choose every parameter, through the Python
+wrappers stokeslet / rotlet / stresslet, and the result meets the requested
+relative max-norm tolerance against the oracle's FP64 direct sum (sampled
+targets at the larger sizes; every target at N = 1000)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1607_04808_amd as F  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _t(a, dtype, grad=False):
+    t = torch.tensor(np.asarray(a), dtype=torch.float32 if dtype == "f32" else torch.float64, device=DEV)
+    return t.requires_grad_(grad)
+
+
+def _exact(a, dtype):
+    return np.asarray(a, dtype=np.float32).astype(np.float64) if dtype == "f32" else np.asarray(a)
+
+
+def _err(u, ref):
+    return direct.rel_errors(u, ref)[0]
+
+
+def _targets(n, seed, T):
+    return np.sort(W.rng(seed).choice(n, size=min(T, n), replace=False)).astype(np.int64)
+
+
+def test_bounding_box_is_the_points_cube():
+    x = W.gaussian_blobs(5000, 17)
+    lo, L = F.bounding_box(_t(x, "f64"))
+    assert np.allclose(lo, x.min(axis=0), rtol=0, atol=0)
+    ext = (x.max(axis=0) - x.min(axis=0)).max()
+    assert ext < L <= ext * (1 + 2.0 ** -19)
+    xf = _t(x, "f32")
+    lo32, L32 = F.bounding_box(xf)
+    assert np.all(np.asarray(lo32) == _exact(x, "f32").min(axis=0))
+
+
+def test_c1_stokeslet_1000_f64_every_target():
+    n = 1000
+    x = W.uniform_cube(n, 1001)
+    f = W.normal_strengths(n, 2001)
+    u = F.stokeslet(_t(x, "f64"), _t(f, "f64"), tol=1e-6).detach().cpu().numpy()
+    assert _err(u, direct.direct("stokeslet", x, f)) < 1e-6
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f64", 1e-6), ("f64", 1e-10)])
+def test_c2_stokeslet_100k_chosen(dtype, tol):
+    n = 100_000
+    x = W.uniform_cube(n, 1002)
+    f = W.normal_strengths(n, 2002)
+    print("C2 chosen", dtype, tol, flush=True)
+    u = F.stokeslet(_t(x, dtype), _t(f, dtype), tol=tol).detach().cpu().numpy()
+    tg = _targets(n, 4002, 256)
+    ref = direct.direct("stokeslet", _exact(x, dtype), _exact(f, dtype), targets=tg)
+    e = _err(u[tg], ref)
+    print("C2 chosen", dtype, tol, "err %.2e" % e)
+    assert e < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f64", 1e-10)])
+def test_headline_chosen_forward_adjoint(dtype, tol):
+    """N = 1e6 uniform stokeslet, forward and adjoint through torch.autograd."""
+    n = 1_000_000
+    x = W.uniform_cube(n, 1000)
+    f = W.normal_strengths(n, 2000)
+    w = W.normal_strengths(n, 3000)
+    print("headline chosen", dtype, flush=True)
+    xt, ft = _t(x, dtype, True), _t(f, dtype, True)
+    u = F.stokeslet(xt, ft, tol=tol)
+    (u * _t(w, dtype)).sum().backward()
+    u = u.detach().cpu().numpy()
+    tg = _targets(n, 4000, 512)
+    xs, fs, ws = (_exact(a, dtype) for a in (x, f, w))
+    eu = _err(u[tg], direct.direct("stokeslet", xs, fs, targets=tg))
+    ef = _err(ft.grad.cpu().numpy()[tg], direct.direct("stokeslet", xs, ws, targets=tg))
+    ex = _err(xt.grad.cpu().numpy()[tg], direct.grad_direct("stokeslet", xs, fs, ws, targets=tg))
+    print("headline chosen", dtype, "u %.2e dL/df %.2e dL/dx %.2e" % (eu, ef, ex))
+    assert eu < tol and ef < tol and ex < tol
+
+
+@pytest.mark.parametrize("kernel,dtype,tol", [("rotlet", "f64", 1e-8), ("rotlet", "f32", 1e-6),
+                                              ("stresslet", "f64", 1e-8), ("stresslet", "f32", 1e-6)])
+def test_rotlet_stresslet_chosen(kernel, dtype, tol):
+    n = 20_000
+    x = W.uniform_cube(n, 1010, L=2.0) - 1.0
+    a = W.normal_strengths(n, 2010)
+    b = W.normal_strengths(n, 2011) if kernel == "stresslet" else None
+    xt, at = _t(x, dtype), _t(a, dtype)
+    if kernel == "rotlet":
+        u = F.rotlet(xt, at, tol=tol)
+    else:
+        u = F.stresslet(xt, at, _t(b, dtype), tol=tol)
+    u = u.detach().cpu().numpy()
+    tg = _targets(n, 4010, 256)
+    ref = direct.direct(kernel, _exact(x, dtype), _exact(a, dtype), None if b is None else _exact(b, dtype),
+                        targets=tg)
+    e = _err(u[tg], ref)
+    print(kernel, dtype, tol, "err %.2e" % e)
+    assert e < tol

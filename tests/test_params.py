@@ -1,0 +1,82 @@
+"""Host-side parameter selection (fse_choose_params, fse_error_estimates): the C
+transcription of Tables est_real / est_fourier against the oracle's (which the
+oracle tests pin), and the properties Section 8.2's strategy gives the chosen
+parameters.  No GPU needed."""
+import math
+
+import pytest
+
+from oracle import se
+
+F = pytest.importorskip("paper_1607_04808_amd")
+
+KERNELS = ("stokeslet", "stresslet", "rotlet")
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("xi,rc,M,P,L", [(7.0, 0.63, 48, 16, 2.0), (75.0, 0.0476, 236, 12, 1.0),
+                                          (20.0, 0.2, 90, 14, 2.0)])
+def test_error_estimates_match_oracle_tables(kernel, xi, rc, M, P, L):
+    prm = F.make_params(xi, rc, M, P, L=L)
+    g = F.geometry(kernel, prm)
+    er, ef = F.error_estimates(kernel, prm, 123.0)
+    assert er == pytest.approx(se.est_real(kernel, 123.0, xi, L, rc), rel=1e-12)
+    assert ef == pytest.approx(se.est_fourier(kernel, 123.0, xi, L, g.kinf, g.R), rel=1e-12)
+
+
+def _smooth7(n):
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f64", 1e-6), ("f64", 1e-10), ("f64", 1e-3)])
+def test_choose_params_meets_estimates(kernel, dtype, tol):
+    n, L, Q, urms = 100_000, 1.0, 3e5, 2.0e3
+    p = F.choose_params(kernel, dtype, n, (0.0, 0.0, 0.0), L, tol, Q, urms)
+    g = F.geometry(kernel, p)
+    eps = tol * (0.5 if dtype == "f32" else 1.0) * urms / math.sqrt(2.0)
+    er, ef = F.error_estimates(kernel, p, Q)
+    assert er <= eps * (1 + 1e-9) and ef <= eps * (1 + 1e-9)
+    # M is the smallest grid meeting the Fourier estimate (or set by eta in FP32)
+    q = F.make_params(p.xi, p.rc, p.M - 1, p.P, L=L)
+    ef1 = F.error_estimates(kernel, q, Q)[1]
+    eta_bound = dtype == "f32" and g.eta > 0.6
+    assert ef1 > eps or eta_bound
+    # r_c is tight: 1 % less misses the real-space estimate
+    q = F.make_params(p.xi, p.rc * 0.99, p.M, p.P, L=L)
+    assert F.error_estimates(kernel, q, Q)[0] > eps
+    # P: two points per digit, even; Mt: 7-smooth FFT size with slack beyond M + P
+    digits = -math.log10(tol)
+    assert p.P % 2 == 0 and p.P >= 2 * digits - 1e-9 and p.P <= max(8, 2 * digits + 2)
+    assert _smooth7(2 * g.Mt) and g.Mt >= p.M + p.P + 1
+    if dtype == "f32":
+        assert g.eta <= 0.7 + 1e-12
+
+
+def test_choose_params_cost_tradeoff_follows_tolerance():
+    """Tighter tolerances need larger xi r_c and M / xi (Section 8.1: both set the error level)."""
+    prev = None
+    for tol in (1e-3, 1e-6, 1e-9):
+        p = F.choose_params("stokeslet", "f64", 10**6, (0.0, 0.0, 0.0), 1.0, tol, 3e6, 4.5e3)
+        cur = (p.xi * p.rc, p.M / p.xi)
+        if prev:
+            assert cur[0] > prev[0] and cur[1] > prev[1]
+        prev = cur
+
+
+def test_choose_params_rejects():
+    with pytest.raises(F.FseError):
+        F.choose_params("stokeslet", "f32", 1000, (0, 0, 0), 1.0, 1e-8, 3e3, 0.0)   # below FP32 reach
+    with pytest.raises(F.FseError):
+        F.choose_params("stokeslet", "f64", 1000, (0, 0, 0), 1.0, 0.0, 3e3, 0.0)
+    with pytest.raises(F.FseError):
+        F.choose_params("stokeslet", "f64", 1, (0, 0, 0), 1.0, 1e-6, 3e3, 0.0)
+
+
+def test_default_scale_is_used_without_u_rms():
+    a = F.choose_params("rotlet", "f64", 10**5, (0, 0, 0), 1.0, 1e-6, 3e5, 0.0)
+    b = F.choose_params("rotlet", "f64", 10**5, (0, 0, 0), 1.0, 1e-6, 3e5, -1.0)
+    assert (a.xi, a.rc, a.M) == (b.xi, b.rc, b.M) and a.M > 0
