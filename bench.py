@@ -6,9 +6,11 @@ bin/sort the points, forward FSE sum (spread, FFT, scale, IFFT, gather, real
 space), and the adjoint (dL/df and dL/dx for L = sum_m w_m . u(x_m)).
 
 Prints ONE JSON line.  `value` is the FP32-form forward+adjoint throughput;
-the FP64 form, forward-only rates, per-stage times, the roofline of the
-dominant kernel and the CPU baseline (the oracle on a bounded target sample,
-which also gives the sampled relative error) are extra fields.
+the FP64 form, the batched form (16 force vectors over the same points),
+forward-only rates, per-stage times, the roofline of the dominant kernel, the
+FP32 form's error over all N against the FP64 form at the same (FP32-rounded)
+inputs, and the CPU baseline (the oracle on a bounded target sample, which also
+gives the sampled relative errors) are extra fields.
 """
 from __future__ import annotations
 
@@ -179,7 +181,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-targets", type=int, default=6144, help="oracle target sample size")
-    ap.add_argument("--forms", default="f32,f64")
+    ap.add_argument("--forms", default="f32,f64,batched")
+    ap.add_argument("--batch", type=int, default=16, help="force vectors of the batched form")
     ap.add_argument("--set", action="append", default=[], metavar="FORM.KEY=VALUE",
                     help="override a parameter of a form, e.g. f32.xi=90 (repeatable)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -224,18 +227,29 @@ def main():
 
     results = {}
     outputs = {}
+    results_full = None
     forms = [f for f in args.forms.split(",") if f]
     if args.no_fp64 and "f64" in forms:
         forms.remove("f64")
+    B = args.batch
     for form in forms:
-        prm = FORMS[form]
-        tdt = torch.float32 if form == "f32" else torch.float64
+        batched = form == "batched"
+        dform = "f32" if batched else form  # the batched form is FP32 at the FP32 parameters
+        nb = B if batched else 1
+        prm = FORMS[dform]
+        tdt = torch.float32 if dform == "f32" else torch.float64
         x = torch.tensor(x64, dtype=tdt, device=dev)
-        f = torch.tensor(f64, dtype=tdt, device=dev)
-        w = torch.tensor(w64, dtype=tdt, device=dev)
+        if batched:
+            fb = W.normal_strengths(n, 2100, batch=B)
+            wb = W.normal_strengths(n, 3100, batch=B)
+            f = torch.tensor(fb, dtype=tdt, device=dev)
+            w = torch.tensor(wb, dtype=tdt, device=dev)
+        else:
+            f = torch.tensor(f64, dtype=tdt, device=dev)
+            w = torch.tensor(w64, dtype=tdt, device=dev)
         params = F.make_params(prm["xi"], prm["rc"], prm["M"], prm["P"], (0.0, 0.0, 0.0), L_BOX, Mt=prm["Mt"])
         t0 = time.time()
-        plan = F.Plan("stokeslet", form, params, batch=1, nmax=n)
+        plan = F.Plan("stokeslet", dform, params, batch=nb, nmax=n)
         torch.cuda.synchronize()
         t_plan = time.time() - t0
         plan.set_points(x, validate=True)
@@ -272,14 +286,37 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_fwd = e0.elapsed_time(e1) / args.steps
-        outputs[form] = (u.cpu().numpy()[0], df.cpu().numpy()[0], dx.cpu().numpy())
+        if batched:
+            # two members for the sampled error check
+            outputs[form] = (u.cpu().numpy()[:2], df.cpu().numpy()[:2], fb[:2], wb[:2])
+        else:
+            outputs[form] = (u.cpu().numpy()[0], df.cpu().numpy()[0], dx.cpu().numpy())
+        if form == "f32" and "f64" in forms:
+            # the FP64 form at the FP32-rounded inputs (untimed): the reference for the
+            # FP32 form's error over all N (the FP64 form is ~1e-11 from the direct sum)
+            xs, fs, ws = (np.asarray(a, np.float32).astype(np.float64) for a in (x64, f64, w64))
+            p64 = F.make_params(FORMS["f64"]["xi"], FORMS["f64"]["rc"], FORMS["f64"]["M"], FORMS["f64"]["P"],
+                                (0.0, 0.0, 0.0), L_BOX, Mt=FORMS["f64"]["Mt"])
+            ref_plan = F.Plan("stokeslet", "f64", p64, batch=1, nmax=n)
+            xr, fr, wr = (torch.tensor(a, device=dev) for a in (xs, fs, ws))
+            ref_plan.set_points(xr)
+            ur = ref_plan.eval(fr)
+            dfr, dxr = ref_plan.adjoint(fr, wr, recompute=False)
+            full = {}
+            for key, a32, a64 in (("u", u[0], ur[0]), ("dL_df", df[0], dfr[0]), ("dL_dx", dx, dxr)):
+                d = (a32.double() - a64).abs().max() / a64.abs().max()
+                full[key] = float("%.3g" % float(d))
+            full["targets"] = n
+            results_full = full
+            ref_plan.close()
+            del xr, fr, wr, ur, dfr, dxr
         pairs = n * (n - 1) * cube_pair_cdf(prm["rc"] / L_BOX)
         stage_tab = {}
         for name, (tot, cnt) in stages.items():
             if cnt == 0:
                 continue
             per = tot / cnt
-            b, fl = stage_work(name, geo, n, prm["P"], form, pairs / 1.0)
+            b, fl = stage_work(name, geo, n, prm["P"], dform, pairs / 1.0, batch=nb)
             # launches per step of this stage (e.g. two spreads per forward+adjoint step)
             stage_tab[name] = dict(ms_per_step=tot / args.steps, ms_per_launch=per, launches=cnt,
                                    GBs=(b / per / 1e6 if b else None),
@@ -288,6 +325,10 @@ def main():
                              ms_per_step=ms, ms_forward=ms_fwd, targets_per_s=n / (ms / 1e3),
                              forward_targets_per_s=n / (ms_fwd / 1e3), plan_seconds=t_plan,
                              workspace_GB=plan.workspace_bytes() / 1e9, stages=stage_tab)
+        if batched:
+            results[form].update(batch=B, dtype="f32",
+                                 vector_targets_per_s=n * B / (ms / 1e3),
+                                 forward_vector_targets_per_s=n * B / (ms_fwd / 1e3))
         plan.close()
         del x, f, w
         torch.cuda.empty_cache()
@@ -330,15 +371,36 @@ def main():
         "stages": {k: v["stages"] for k, v in results.items()},
     }
 
+    if "batched" in results:
+        br = results["batched"]
+        bd, bdom = max(br["stages"].items(), key=lambda kv: kv[1]["ms_per_step"])
+        if bdom["TFLOPs"] is not None:
+            line["forms"]["batched"]["roofline"] = dict(kernel=bd, bound="mfma" if ("f32", bd) in MFMA_STAGES else "alu",
+                                                        achieved=round(bdom["TFLOPs"], 2), peak=PEAK["f32_TFLOPs"],
+                                                        unit="TFLOP/s", frac=round(bdom["TFLOPs"] / PEAK["f32_TFLOPs"], 4))
+        else:
+            line["forms"]["batched"]["roofline"] = dict(kernel=bd, bound="hbm", achieved=round(bdom["GBs"], 1),
+                                                        peak=PEAK["hbm_GBs"], unit="GB/s",
+                                                        frac=round(bdom["GBs"] / PEAK["hbm_GBs"], 4))
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["error"] = cpu_baseline(x64, f64, w64, outputs, args.cpu_targets)
+    if results_full is not None:
+        line.setdefault("error", {}).setdefault("f32", {})["all_targets_vs_f64_form"] = results_full
     print(json.dumps(line))
 
 
 def cpu_baseline(x64, f64, w64, outputs, T):
-    """The oracle (FP64 direct sum and analytic gradient) on a seeded sample of T
-    targets with all N sources; gives the CPU rate and the sampled errors."""
+    """The oracle (FP64 direct sum, its K w, and the analytic gradient: the work of
+    one GPU step) on a seeded sample of T targets with all N sources, built for the
+    host it runs on; gives the CPU rate on all cores and on one core, and the
+    sampled errors."""
+    import tempfile
     from oracle import direct
+    try:
+        direct.use_library(direct.build(path=os.path.join(tempfile.mkdtemp(), "liboracle_native.so"), native=True))
+        build = "gcc -O3 -march=native -fopenmp"
+    except Exception:  # no compiler on this host: the portable build
+        build = "gcc -O3 -march=x86-64-v3 -fopenmp"
     n = len(x64)
     tg = np.sort(W.rng(4000).choice(n, size=min(T, n), replace=False)).astype(np.int64)
     errs = {}
@@ -348,7 +410,30 @@ def cpu_baseline(x64, f64, w64, outputs, T):
     g_ref = direct.grad_direct("stokeslet", x64, f64, w64, targets=tg)
     t2 = time.time()
     df_ref = direct.direct("stokeslet", x64, w64, targets=tg)
-    for form, (u, df, dx) in outputs.items():
+    t3 = time.time()
+    # one core, on the first 256 sampled targets
+    t1c = tg[:256]
+    direct.set_threads(1)
+    s0 = time.time()
+    direct.direct("stokeslet", x64, f64, targets=t1c)
+    direct.grad_direct("stokeslet", x64, f64, w64, targets=t1c)
+    direct.direct("stokeslet", x64, w64, targets=t1c)
+    s1 = time.time()
+    direct.set_threads(0)
+    for form, out in outputs.items():
+        if form == "batched":
+            u, df, fb, wb = out
+            xs = x64.astype(np.float32).astype(np.float64)
+            ts = tg[:512]
+            e_u = e_f = 0.0
+            for m in range(len(u)):
+                fs, ws = (a.astype(np.float32).astype(np.float64) for a in (fb[m], wb[m]))
+                e_u = max(e_u, direct.rel_errors(u[m][ts], direct.direct("stokeslet", xs, fs, targets=ts))[0])
+                e_f = max(e_f, direct.rel_errors(df[m][ts], direct.direct("stokeslet", xs, ws, targets=ts))[0])
+            errs[form] = {"u": {"max": float("%.3g" % e_u)}, "dL_df": {"max": float("%.3g" % e_f)},
+                          "members_checked": len(u), "targets_sampled": int(len(ts))}
+            continue
+        u, df, dx = out
         # the FP32 form evaluates the FP32-rounded inputs; its reference uses them
         if form == "f32":
             xs, fs, ws = (a.astype(np.float32).astype(np.float64) for a in (x64, f64, w64))
@@ -364,10 +449,13 @@ def cpu_baseline(x64, f64, w64, outputs, T):
             "targets_sampled": int(len(tg)),
         }
     cores = direct.num_threads()
-    rate = len(tg) / ((t1 - t0) + (t2 - t1))
+    rate = len(tg) / (t3 - t0)
     base = {"value": round(rate, 2), "unit": "targets/s", "cores": cores, "kind": "oracle",
-            "sample": "%d seeded targets x %d sources, FP64 direct sum + analytic gradient "
-                      "(forward %.2fs, gradient %.2fs)" % (len(tg), n, t1 - t0, t2 - t1)}
+            "one_core_value": round(len(t1c) / (s1 - s0), 2),
+            "build": build,
+            "sample": "%d seeded targets x %d sources, FP64: direct sum u, K w and the analytic gradient "
+                      "dL/dx (the GPU step's outputs; %.2fs, %.2fs, %.2fs); one core: the first %d of "
+                      "those targets" % (len(tg), n, t1 - t0, t2 - t1, t3 - t2, len(t1c))}
     return base, errs
 
 

@@ -68,6 +68,15 @@ typedef struct {
                             2*Mt must factor into 2,3,5,7)                      */
     double C;            /* Gaussian shape constant of m = C sqrt(pi P);
                             0 selects 0.976 (Section 5.3)                       */
+    int32_t periodic;    /* 0: the free-space sum (eq. usumfree);
+                            1: the triply periodic stokeslet sum of Section 1.1
+                            (eq. usumper, period L in every direction, by the
+                            Hasimoto split eq. usum_SR_SF_limit with eqs.
+                            SR_Hasimoto, ShatH, Slimit): no domain extension or
+                            precompute, the M^3 grid is the period, 2M must
+                            factor into 2,3,5,7, P <= M and rc <= L/2;
+                            deltaL_rule and Mt are ignored.  Stokeslet only;
+                            fse_eval and fse_eval_parts only.                   */
 } fse_params_t;
 
 /*
@@ -142,6 +151,27 @@ fse_status_t fse_eval_parts(fse_plan_t *plan, const void *src_a, const void *src
                             void *u_fourier);
 
 /*
+ * Separate targets (Section 2: the sums may be evaluated at the sources or at
+ * any other points): bins the nt (>= 1) targets y (device, (nt, 3), plan dtype)
+ * like fse_set_points does the points; they must lie in the same box.  The
+ * plan keeps them until the next call, which may change nt (buffers grow on
+ * demand with hipMalloc, after a stream synchronisation).  validate as in
+ * fse_set_points.
+ */
+fse_status_t fse_set_targets(fse_plan_t *plan, int64_t nt, const void *y, int32_t validate);
+
+/*
+ * u(y_t) = sum_n G(y_t - x_n) . f_n at the targets of fse_set_targets from the
+ * points of fse_set_points (sources as in fse_eval): u^F by the quadrature at
+ * the targets and u^R over the sources within r_c; no self term, and a target
+ * that coincides with a source skips that pair.  With u_fourier == NULL,
+ * u_real receives the whole sum u (batch, nt, 3); otherwise u_real (may be
+ * NULL) gets u^R and u_fourier gets u^F separately.
+ */
+fse_status_t fse_eval_targets(fse_plan_t *plan, const void *src_a, const void *src_b, void *u_real,
+                              void *u_fourier);
+
+/*
  * Adjoint of fse_eval for L = sum_m w_m . u(x_m) (stokeslet and rotlet, whose
  * discrete operator is symmetric): dsrc = dL/df = K w (batch, n, 3) and
  * dx = dL/dx (n, 3), summed over the batch, from the derivatives of the
@@ -153,6 +183,20 @@ fse_status_t fse_eval_parts(fse_plan_t *plan, const void *src_a, const void *src
  */
 fse_status_t fse_eval_adjoint(fse_plan_t *plan, const void *src_a, const void *w, void *dsrc,
                               void *dx, int32_t recompute);
+
+/*
+ * Adjoint of fse_eval for the stresslet (eq. def_stresslet), L = sum_m w_m .
+ * u(x_m) with u_j(x_m) = sum_{n != m} T_jlm(x_m - x_n) q_l(n) n_m(n): at each
+ * point b, D_lm = sum_{a != b} w_j(a) T_jlm(x_a - x_b) (T fully symmetric, so D
+ * is the symmetric 2-tensor of the transposed chain: w spread as 3 components,
+ * the transposed multiplier +i P_j,lm(k) of eq. AT, six output components,
+ * plus the real-space pairs within r_c), and dq_l = dL/dq_l = D_lm n_m,
+ * dn_m = dL/dn_m = D_lm q_l.  q, nrm, w: (batch, n, 3); dq, dn: (batch, n, 3),
+ * overwritten.  The plan's field buffer then holds the adjoint field, so a
+ * following fse_eval_adjoint must recompute the forward field.
+ */
+fse_status_t fse_eval_adjoint_stresslet(fse_plan_t *plan, const void *q, const void *nrm, const void *w,
+                                        void *dq, void *dn);
 
 /* Copy the (Mt+1)^3 FP64 octant of the scalar Fourier multiplier (the
  * precomputed mollified kernel transform times the kernel's scalar factors
@@ -181,6 +225,21 @@ fse_status_t fse_plan_timings(fse_plan_t *plan, double *ms, int64_t *launches);
 const char *fse_stage_name(int32_t stage);
 
 /*
+ * Free-space harmonic and biharmonic solver (Section 4: the truncated-kernel
+ * method of Section 4.1 with the oversampling of Section 4.2 moved into the
+ * precompute of Section 4.3): u = G * f, u(x_i) = integral of G(x_i - y) f(y)
+ * dy over the box, for family 0 the biharmonic G = r (eq. BhatR's kernel) and
+ * family 1 the harmonic G = 1/r (eq. HhatR's), with f sampled on the M^3 grid
+ * of spacing h (nodes j h, j = 0..M-1, and f negligible at the faces) and u
+ * returned at the same nodes.  Spectrally accurate for smooth f (Table 1's
+ * closed forms, e.g. H * gamma_E = erf(xi r)/r).  f, u: ncomp device fields of
+ * M^3 in the dtype, x fastest; 2M must factor into 2,3,5,7 (M <= 540).
+ * Allocates its workspace, runs on `stream` and synchronises it.
+ */
+fse_status_t fse_freespace_solve(int32_t family, fse_dtype_t dtype, int32_t M, double h, int32_t ncomp,
+                                 const void *f, void *u, void *stream);
+
+/*
  * Truncation-error estimates for a parameter set (host only): the RMS over
  * targets of the real-space truncation error, Table est_real (Section 7.2),
  * and of the Fourier-space truncation error, Table est_fourier (Section 7.1,
@@ -197,15 +256,18 @@ fse_status_t fse_error_estimates(fse_kernel_t kernel, const fse_params_t *params
  * P = 2 points per digit of rel_tol (even, in [8, 32]; Section 8.2's 16 for 8
  * digits and 24 for 12), and for each xi of a geometric sweep the r_c and M
  * that hold the estimates of Tables est_real and est_fourier at an absolute
- * RMS target eps = rel_tol * share * u_rms / sqrt 2 (share = 1 in FP64, 1/2 in
- * FP32 to leave room for rounding); FP32 plans also keep eta <= 0.7.  Of the
- * sweep it returns the xi (with its r_c, M, P and Mt = the smallest 7-smooth
- * size above M + P) that minimises a cost model of this library's kernels on
+ * RMS target eps = rel_tol * share * u_rms / sqrt 2 (share = 0.6 in FP64, a
+ * margin for the adjoint's gradient, 0.4 in FP32 to leave room for rounding),
+ * with eta <= 0.95 (FP64) or 0.7 (FP32).  Of the
+ * sweep it returns the xi (with its r_c, M, P, and Mt = the smallest size with
+ * 2 Mt 7-smooth that holds the box extended by eq. deltaL_cond's deltaL, the
+ * Section 5.3 rule that keeps the remainder Gaussians' support inside the
+ * grid) that minimises a cost model of this library's kernels on
  * one MI355X (real-space pairs, transform nodes, window nodes; uniform
  * density assumed).  Q as in fse_error_estimates; u_rms is the RMS of |u| over
  * the targets, or <= 0 for an estimate for points uniform in the cube.
  * FSE_EINVAL for rel_tol outside (0, 1), FP32 with rel_tol < 1e-6, or when no
- * xi fits the grid limit.  deltaL_rule = 0 and C = 0 in *out.
+ * xi fits the grid limit.  deltaL_rule = 1 and C = 0 in *out.
  */
 fse_status_t fse_choose_params(fse_kernel_t kernel, fse_dtype_t dtype, int64_t n, const double box_lo[3],
                                double L, double rel_tol, double Q, double u_rms, fse_params_t *out);

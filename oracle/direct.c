@@ -287,6 +287,17 @@ int oracle_grad_real_trunc(int kernel, double xi, double rc, int64_t n, const do
     return grad_generic(1, kernel, xi, rc, n, x, f, w, nt, tgt, out);
 }
 
+/* Threads of the OpenMP loops above (t <= 0: the runtime default).  Timing only. */
+void oracle_set_threads(int t) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    extern int omp_get_num_procs(void);
+    omp_set_num_threads(t > 0 ? t : omp_get_num_procs());
+#else
+    (void)t;
+#endif
+}
+
 int oracle_num_threads(void) {
     int t = 1;
 #pragma omp parallel

@@ -21,15 +21,43 @@ _lib = None
 KERNELS = {"stokeslet": 0, "stresslet": 1, "rotlet": 2}
 
 
-def build(force: bool = True) -> str:
-    """Compile ``direct.c`` with gcc (FP64, OpenMP) into ``liboracle.so``."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared",
-               "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
+def build(force: bool = True, path: str | None = None, native: bool = False) -> str:
+    """Compile ``direct.c`` with gcc (FP64, OpenMP) into ``liboracle.so`` (or `path`).
+
+    The default build targets x86-64-v3, so the library built here also runs on
+    the GPU host; ``native=True`` compiles for the machine it runs on (the CPU
+    baseline's timing build, made on that host)."""
+    out = path or _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O3", "-march=native" if native else "-march=x86-64-v3", "-fopenmp", "-fPIC",
+               "-shared", "-fno-fast-math", _SRC, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from `path` (a build of the same source) for the rest of the process."""
+    global _lib
+    with _lock:
+        _lib = _load(path)
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    d, i64, vp, i = ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+    L.oracle_direct.argtypes = [i, i64, vp, vp, vp, i64, vp, vp, vp]
+    L.oracle_real_trunc.argtypes = [i, d, d, i64, vp, vp, vp, i64, vp, vp, vp]
+    L.oracle_fourier_dir.argtypes = [i, d, i64, vp, vp, vp, i64, vp, vp, vp]
+    L.oracle_grad_direct.argtypes = [i, i64, vp, vp, vp, i64, vp, vp]
+    L.oracle_grad_real_trunc.argtypes = [i, d, d, i64, vp, vp, vp, i64, vp, vp]
+    L.oracle_set_threads.argtypes = [i]
+    L.oracle_set_threads.restype = None
+    for fn in ("oracle_direct", "oracle_real_trunc", "oracle_fourier_dir",
+               "oracle_grad_direct", "oracle_grad_real_trunc", "oracle_num_threads"):
+        getattr(L, fn).restype = ctypes.c_int
+    return L
 
 
 def lib():
@@ -38,18 +66,13 @@ def lib():
         if _lib is None:
             if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
                 build()
-            L = ctypes.CDLL(_LIB)
-            d, i64, vp, i = ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
-            L.oracle_direct.argtypes = [i, i64, vp, vp, vp, i64, vp, vp, vp]
-            L.oracle_real_trunc.argtypes = [i, d, d, i64, vp, vp, vp, i64, vp, vp, vp]
-            L.oracle_fourier_dir.argtypes = [i, d, i64, vp, vp, vp, i64, vp, vp, vp]
-            L.oracle_grad_direct.argtypes = [i, i64, vp, vp, vp, i64, vp, vp]
-            L.oracle_grad_real_trunc.argtypes = [i, d, d, i64, vp, vp, vp, i64, vp, vp]
-            for fn in ("oracle_direct", "oracle_real_trunc", "oracle_fourier_dir",
-                       "oracle_grad_direct", "oracle_grad_real_trunc", "oracle_num_threads"):
-                getattr(L, fn).restype = ctypes.c_int
-            _lib = L
+            _lib = _load(_LIB)
     return _lib
+
+
+def set_threads(t: int) -> None:
+    """OpenMP threads of the sums (t <= 0: all cores)."""
+    lib().oracle_set_threads(int(t))
 
 
 def num_threads() -> int:
@@ -139,6 +162,37 @@ def grad_real_trunc(kernel, xi, rc, x, f, w, targets=None):
     _check(lib().oracle_grad_real_trunc(_kid(kernel), float(xi), float(rc), len(x), _p(x),
                                         _p(f), _p(w), len(targets), _p(targets), _p(out)))
     return out
+
+
+def stresslet_adjoint(x, q, nrm, w, targets=None, chunk=4096):
+    """dL/dq and dL/dn of L = sum_m w_m . u(x_m) for the stresslet direct sum.
+
+    u_j(x_m) = sum_{n != m} T_jlm(x_m - x_n) q_l(n) n_m(n) with
+    T_jlm(r) = -6 r_j r_l r_m / |r|^5 (eq. def_stresslet).  L is linear in q and
+    in n, so at source b: D_lm = sum_{a != b} w_j(a) T_jlm(x_a - x_b) and
+    dL/dq_l(b) = D_lm n_m(b), dL/dn_m(b) = D_lm q_l(b).  Plain numpy, FP64, for
+    the given target indices b (all by default).
+    """
+    x, q, nrm, w = (np.asarray(a, dtype=np.float64) for a in (x, q, nrm, w))
+    if targets is None:
+        targets = np.arange(len(x), dtype=np.int64)
+    dq = np.zeros((len(targets), 3))
+    dn = np.zeros((len(targets), 3))
+    for k, b in enumerate(targets):
+        for s0 in range(0, len(x), chunk):
+            r = x[s0:s0 + chunk] - x[b]                     # x_a - x_b
+            ww = w[s0:s0 + chunk]
+            r2 = np.einsum("ij,ij->i", r, r)
+            own = (np.arange(s0, s0 + len(r)) == b)
+            if np.any((r2 == 0.0) & ~own):
+                raise ValueError("oracle: coincident distinct points (undefined sum)")
+            r2[own] = 1.0
+            c = -6.0 * np.einsum("ij,ij->i", r, ww) / r2 ** 2.5  # w_j r_j times -6/|r|^5
+            c[own] = 0.0
+            D = np.einsum("i,ij,ik->jk", c, r, r)               # sum_a c_a r_l r_m
+            dq[k] += D @ nrm[b]
+            dn[k] += D @ q[b]
+    return dq, dn
 
 
 def rel_errors(u, ref):

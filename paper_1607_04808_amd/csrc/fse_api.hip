@@ -104,8 +104,42 @@ fse_status_t compute_geometry(fse_kernel_t kernel, const fse_params_t* p, fse_ge
         if (!isfinite(p->box_lo[d])) { set_err("box_lo must be finite"); return FSE_EINVAL; }
     if (p->deltaL_rule != 0 && p->deltaL_rule != 1) { set_err("deltaL_rule must be 0 or 1"); return FSE_EINVAL; }
     if (!(p->C >= 0 && p->C < 10)) { set_err("C out of range"); return FSE_EINVAL; }
+    if (p->periodic != 0 && p->periodic != 1) { set_err("periodic must be 0 or 1"); return FSE_EINVAL; }
     memset(g, 0, sizeof *g);
     const double C = p->C > 0 ? p->C : 0.976;
+    if (p->periodic) {
+        // Section 1.1: the M^3 grid covers one period; its DFT is taken as the even
+        // frequencies of the doubled grid the transforms work on
+        if (kernel != FSE_STOKESLET) { set_err("the triply periodic sum is the stokeslet's (Section 1.1)"); return FSE_EINVAL; }
+        if (!(p->rc <= 0.5 * p->L)) { set_err("periodic: rc must be <= L/2"); return FSE_EINVAL; }
+        if (p->P > p->M) { set_err("periodic: P must be <= M"); return FSE_EINVAL; }
+        if (!smooth7(2 * p->M)) { set_err("periodic: 2*M=%d does not factor into 2,3,5,7", 2 * p->M); return FSE_EINVAL; }
+        if (p->M > MAX_MT) { set_err("grid size M=%d above the supported %d", p->M, MAX_MT); return FSE_EINVAL; }
+        const double h = p->L / p->M, d = h * p->P, m = C * sqrt(PI * p->P);
+        g->Mt = p->M;
+        g->n_fft = 2 * p->M;
+        g->h = h;
+        g->d = d;
+        g->m = m;
+        g->eta = (p->xi * d / m) * (p->xi * d / m);
+        g->alpha = 2.0 * p->xi * p->xi / g->eta;
+        g->Lt = p->L;
+        g->deltaL = 0.0;
+        for (int k = 0; k < 3; ++k) g->x0[k] = p->box_lo[k];
+        g->Mg = 0;
+        g->R = 0.0;
+        g->kinf = PI / h;
+        int nc = (int)floor(p->L / p->rc);
+        if (nc < 1) nc = 1;
+        if (nc > MAX_CELLS_PER_SIDE) nc = MAX_CELLS_PER_SIDE;
+        g->ncell = nc;
+        g->cell = p->L / nc;
+        int rad[MAX_RADICES];
+        const int ns = factorize(g->n_fft, rad);
+        if (ns < 0 || ns > 7) { set_err("cannot factor n=%d", g->n_fft); return FSE_EINVAL; }
+        for (int s = 0; s < ns; ++s) g->radices[s] = rad[s];
+        return FSE_OK;
+    }
     const double h = p->L / p->M;
     const double d = h * p->P;
     const double m = C * sqrt(PI * p->P);
@@ -220,8 +254,14 @@ struct fse_plan {
     int64_t n = 0;
     hipStream_t stream;
     int c_in;
-    GridGeo gg;
+    GridGeo gg;  // the spreading and quadrature grid
+    GridGeo gf;  // the transforms' grid (gg, except for periodic sums: the M^3 period)
     CellGeo cg;
+    bool periodic = false;
+    bool solver = false;  // fse_freespace_solve: sigma is the plain truncated kernel transform
+    int family = 0;       // 0 biharmonic (eq. BhatR), 1 harmonic (eq. HhatR)
+    int pshift = 0;  // periodic: index of period node 0 in the extended grid (ceil(P/2) - 1)
+    void* gext = nullptr;  // periodic: spread grid and quadrature field on the extended grid
     FftGeo fg;
     size_t bytes = 0;
     bool forward_valid = false;
@@ -237,8 +277,19 @@ struct fse_plan {
     int *cnt_s, *start_s, *cnt_r, *start_r, *work_r, *scan_tmp, *flag;
     int real_S = 256;
     int64_t ntiles3, ncells3;
+    // separate targets (fse_set_targets): binned like the points, own buffers
+    struct Targets {
+        int64_t cap = 0, n = 0;
+        int *key_s, *key_r, *idx, *key_tmp, *bpack, *perm_s, *bpack_s, *perm_r, *inv_r;
+        void *coff, *coff_s, *x_r, *sort_tmp;
+        size_t sort_bytes = 0;
+        int *cnt_s, *start_s, *cnt_r, *start_r, *work_r;
+        int real_S = 64;
+        std::vector<void*> allocs;
+    } tg;
     // sources
     void *src_s, *src_ra, *src_rb, *adj_s, *adj_r;
+    void* tadj;  // stresslet adjoint: quadrature of its transpose field (2 batch, n, 3)
     // grids
     void *grid, *A, *B, *phi, *phi_w;
     double* sig64;
@@ -282,7 +333,13 @@ struct fse_plan {
         *p = (X*)q;
         return FSE_OK;
     }
+    void free_targets() {
+        for (void* q : tg.allocs) (void)hipFree(q);
+        tg.allocs.clear();
+        tg.cap = tg.n = 0;
+    }
     ~fse_plan() {
+        free_targets();
         for (void* q : allocs) (void)hipFree(q);
     }
 };
@@ -302,6 +359,12 @@ template <typename T> PointsDev<T> points(const fse_plan* p) {
     d.inv_r = p->inv_r;
     d.work_start = p->work_r;
     d.real_S = p->real_S;
+    d.t_n = d.n;
+    d.t_x_r = d.x_r;
+    d.t_cell_start = d.cell_start;
+    d.t_perm_r = d.perm_r;
+    d.t_work_start = d.work_start;
+    d.t_real_S = d.real_S;
     return d;
 }
 
@@ -353,9 +416,15 @@ template <typename T> fse_status_t allocate(fse_plan* p) {
     TRY(p->alloc((T**)&p->adj_s, B * nm * 3));
     TRY(p->alloc((T**)&p->adj_r, B * nm * 3));
     TRY(p->alloc((T**)&p->grid, B * p->c_in * M3));
+    if (p->periodic) {
+        const int64_t Me = p->gg.Mt;
+        TRY(p->alloc((T**)&p->gext, B * 3 * Me * Me * Me));
+    }
     TRY(p->alloc((V**)&p->A, B * p->c_in * Mp * Mt * (size_t)p->fg.sy));
     TRY(p->alloc((V**)&p->B, B * p->c_in * Mp * n * (size_t)p->fg.sz));
-    TRY(p->alloc((T**)&p->phi, B * 3 * M3));
+    // the stresslet's adjoint field has 6 components (the symmetric D_lm)
+    TRY(p->alloc((T**)&p->phi, B * (p->kernel == FSE_STRESSLET ? 6 : 3) * M3));
+    TRY(p->alloc((T**)&p->tadj, p->kernel == FSE_STRESSLET ? 6 * B * nm : 1));
     TRY(p->alloc((T**)&p->phi_w, p->kernel == FSE_STRESSLET ? 1 : B * 3 * M3));
     TRY(p->alloc(&p->sig64, Mp * Mp * Mp));
     TRY(p->alloc((T**)&p->sig, Mp * Mp * Mp));
@@ -386,6 +455,20 @@ template <typename T> fse_status_t upload_fft_tables(fse_plan* p) {
 // Section 4.3 precompute, FP64, then fold in the scalar factors.  Its four
 // temporaries come from hipMalloc (freed at the end), or from the plan's arena.
 template <typename T> fse_status_t precompute(fse_plan* p) {
+    if (p->periodic) {
+        if (p->dry) return FSE_OK;
+        const double nn = (double)p->geo.n_fft;
+        const double norm = 8.0 * pow(p->geo.alpha / PI, 3.0) * pow(p->geo.h, 3.0) / (nn * nn * nn);
+        launch_pre_periodic<T>(p->geo.Mt, PI / p->geo.Lt, p->prm.xi, p->geo.eta, norm, p->sig64, (T*)p->sig,
+                               p->stream);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) {
+            set_err("precompute failed: %s", hipGetErrorString(e));
+            return FSE_EHIP;
+        }
+        return FSE_OK;
+    }
     const int Mt = p->geo.Mt, Mg = p->geo.Mg, Mp = Mt + 1, H = Mg / 2 + 1;
     const int64_t big = (int64_t)H * H * H > (int64_t)Mp * H * H ? (int64_t)H * H * H : (int64_t)Mp * H * H;
     double *t0 = nullptr, *t1 = nullptr, *c1 = nullptr, *c2 = nullptr;
@@ -434,8 +517,7 @@ template <typename T> fse_status_t precompute(fse_plan* p) {
         set_err("precompute: copy failed");
         return FSE_EHIP;
     }
-    const int family = p->kernel == FSE_ROTLET ? 1 : 0;
-    launch_pre_fill(t0, Mg, p->geo.h, p->geo.R, family, st);
+    launch_pre_fill(t0, Mg, p->geo.h, p->geo.R, p->family, st);
     launch_pre_contract(t0, t1, c1, Mp, H, (int64_t)H * H, st);    // [j3][k1][k2]
     launch_pre_contract(t1, t0, c1, Mp, H, (int64_t)Mp * H, st);   // [j2][j3][k1]
     launch_pre_contract(t0, t1, c1, Mp, H, (int64_t)Mp * Mp, st);  // [j1][j2][j3]: G octant
@@ -444,9 +526,12 @@ template <typename T> fse_status_t precompute(fse_plan* p) {
     launch_pre_contract(t1, t0, c2, Mp, Mp, (int64_t)Mp * Mp, st); // [k1][k2][k3]: mollified transform
     const double a = p->geo.alpha;
     const double nn = (double)p->geo.n_fft;
-    const double norm = pow(a / PI, 3.0) * pow(p->geo.h, 3.0) / (nn * nn * nn);
-    launch_pre_finalize<T>(t0, Mt, PI / p->geo.Lt, p->prm.xi, p->geo.eta, (int)p->kernel, norm, p->sig64,
-                           (T*)p->sig, st);
+    // the Gaussian normalisations (alpha/pi)^{3/2} of spreading and quadrature, the
+    // quadrature weight h^3 and the inverse transform's 1/n^3 (the transform Bt
+    // already carries the convolution's h^3: the solver's plain convolution is 1/n^3)
+    const double norm = p->solver ? 1.0 / (nn * nn * nn) : pow(a / PI, 3.0) * pow(p->geo.h, 3.0) / (nn * nn * nn);
+    launch_pre_finalize<T>(t0, Mt, PI / p->geo.Lt, p->prm.xi, p->geo.eta, p->solver ? KSCALAR : (int)p->kernel,
+                           norm, p->sig64, (T*)p->sig, st);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -516,27 +601,149 @@ template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T*
     return FSE_OK;
 }
 
-// spread -> FFT -> scale -> IFFT into `field`
+template <typename X> fse_status_t talloc(fse_plan* p, X** q, size_t count) {
+    void* v = nullptr;
+    const size_t b = count * sizeof(X) > 0 ? count * sizeof(X) : 16;
+    hipError_t e = hipMalloc(&v, b);
+    if (e != hipSuccess) {
+        set_err("hipMalloc(%zu bytes) for targets failed: %s", b, hipGetErrorString(e));
+        return FSE_ENOMEM;
+    }
+    p->tg.allocs.push_back(v);
+    *q = (X*)v;
+    return FSE_OK;
+}
+
+// (Re)allocate the target buffers for nt targets (plan dtype T).
+template <typename T> fse_status_t reserve_targets(fse_plan* p, int64_t nt) {
+    auto& t = p->tg;
+    if (t.cap >= nt) return FSE_OK;
+    HIPCHK(hipStreamSynchronize(p->stream));  // earlier work may still read the old buffers
+    p->free_targets();
+    TRY(talloc(p, &t.key_s, nt));
+    TRY(talloc(p, &t.key_r, nt));
+    TRY(talloc(p, &t.idx, nt));
+    TRY(talloc(p, &t.key_tmp, nt));
+    TRY(talloc(p, &t.bpack, nt));
+    TRY(talloc(p, &t.perm_s, nt));
+    TRY(talloc(p, &t.bpack_s, nt));
+    TRY(talloc(p, &t.perm_r, nt));
+    TRY(talloc(p, &t.inv_r, nt));
+    TRY(talloc(p, (T**)&t.coff, 3 * nt));
+    TRY(talloc(p, (T**)&t.coff_s, 3 * nt));
+    TRY(talloc(p, (T**)&t.x_r, 3 * nt));
+    TRY(talloc(p, &t.cnt_s, p->ntiles3 + 1));
+    TRY(talloc(p, &t.start_s, p->ntiles3 + 1));
+    TRY(talloc(p, &t.cnt_r, p->ncells3 + 1));
+    TRY(talloc(p, &t.start_r, p->ncells3 + 1));
+    TRY(talloc(p, &t.work_r, p->ncells3 + 1));
+    const size_t b1 = sort_tmp_bytes(nt, p->bits_s), b2 = sort_tmp_bytes(nt, p->bits_r);
+    if (b1 == 0 || b2 == 0) { set_err("sort workspace query failed"); return FSE_EHIP; }
+    t.sort_bytes = b1 > b2 ? b1 : b2;
+    TRY(talloc(p, (char**)&t.sort_tmp, t.sort_bytes));
+    t.cap = nt;
+    return FSE_OK;
+}
+
+// Bin the targets exactly as the points (window starts for the quadrature,
+// cells for the real-space pass), into the target buffers.
+template <typename T> fse_status_t set_targets_t(fse_plan* p, int64_t nt, const T* y, int validate) {
+    TRY(reserve_targets<T>(p, nt));
+    auto& t = p->tg;
+    hipStream_t st = p->stream;
+    {
+        TimedStage ts(p->timer, ST_BIN, st);
+        launch_fill_i32(t.cnt_s, p->ntiles3 + 1, 0, st);
+        launch_fill_i32(t.cnt_r, p->ncells3 + 1, 0, st);
+        launch_fill_i32(p->flag, 1, 0, st);
+        launch_bin<T>(y, nt, p->gg, p->cg, t.key_s, t.key_r, t.idx, t.cnt_s, t.cnt_r, t.bpack, (T*)t.coff, p->flag,
+                      st);
+        HIPCHK(launch_sort_pairs(t.sort_tmp, t.sort_bytes, t.key_s, t.key_tmp, t.idx, t.perm_s, nt, p->bits_s, st));
+        HIPCHK(launch_sort_pairs(t.sort_tmp, t.sort_bytes, t.key_r, t.key_tmp, t.idx, t.perm_r, nt, p->bits_r, st));
+        launch_scan_exclusive(t.cnt_s, t.start_s, p->ntiles3 + 1, p->scan_tmp, st);
+        launch_scan_exclusive(t.cnt_r, t.start_r, p->ncells3 + 1, p->scan_tmp, st);
+        t.real_S = (int)real_threads(nt, p->ncells3);
+        launch_cell_slices(t.cnt_r, p->ncells3, t.real_S, st);
+        launch_scan_exclusive(t.cnt_r, t.work_r, p->ncells3 + 1, p->scan_tmp, st);
+        launch_scatter<T>(y, nt, t.perm_s, t.perm_r, t.bpack, (const T*)t.coff, t.bpack_s, (T*)t.coff_s,
+                          (T*)t.x_r, t.inv_r, st);
+    }
+    LAUNCHCHK();
+    t.n = nt;
+    if (validate) {
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (flag) {
+            set_err("a target lies outside [box_lo, box_lo + L)^3 or is not finite");
+            return FSE_ERANGE;
+        }
+    }
+    return FSE_OK;
+}
+
+// The targets as the points of a quadrature (their spread-order arrays).
+template <typename T> PointsDev<T> target_points(const fse_plan* p) {
+    const auto& t = p->tg;
+    PointsDev<T> d = points<T>(p);
+    d.n = t.n;
+    d.perm_s = t.perm_s;
+    d.bpack_s = t.bpack_s;
+    d.coff_s = (const T*)t.coff_s;
+    d.tile_start = t.start_s;
+    return d;
+}
+
+// The points as real-space sources and the targets as real-space targets.
+template <typename T> PointsDev<T> source_target_points(const fse_plan* p) {
+    const auto& t = p->tg;
+    PointsDev<T> d = points<T>(p);
+    d.t_n = t.n;
+    d.t_x_r = (const T*)t.x_r;
+    d.t_cell_start = t.start_r;
+    d.t_perm_r = t.perm_r;
+    d.t_work_start = t.work_r;
+    d.t_real_S = t.real_S;
+    return d;
+}
+
+// spread -> FFT -> scale -> IFFT into `field` (periodic: spread onto the
+// extended grid and fold it onto the period first)
 template <typename T> void fourier_chain(fse_plan* p, const T* src_s, T* field) {
     hipStream_t st = p->stream;
     PointsDev<T> pd = points<T>(p);
     Timer& tm = p->timer;
-    { TimedStage ts(tm, ST_SPREAD, st); launch_spread<T>(p->gg, pd, src_s, p->c_in, p->batch, (T*)p->grid, st); }
+    if (p->periodic) {
+        TimedStage ts(tm, ST_SPREAD, st);
+        launch_spread<T>(p->gg, pd, src_s, p->c_in, p->batch, (T*)p->gext, st);
+        launch_fold<T>((const T*)p->gext, p->gg.Mt, p->gf.Mt, p->pshift, p->batch * p->c_in, (T*)p->grid, st);
+    } else {
+        TimedStage ts(tm, ST_SPREAD, st);
+        launch_spread<T>(p->gg, pd, src_s, p->c_in, p->batch, (T*)p->grid, st);
+    }
     { TimedStage ts(tm, ST_FFTX, st);
-      launch_fft_forward<T>(p->fg, p->gg, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
+      launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
                             p->rev, p->revinv, st, 1); }
     { TimedStage ts(tm, ST_FFTY, st);
-      launch_fft_forward<T>(p->fg, p->gg, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
+      launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
                             p->rev, p->revinv, st, 2); }
     { TimedStage ts(tm, ST_FFTZ, st);
-      launch_fft_zscale<T>(p->fg, p->gg, (int)p->kernel, p->B, p->c_in, p->batch, (const T*)p->sig,
+      launch_fft_zscale<T>(p->fg, p->gf, (int)p->kernel, p->B, p->c_in, p->batch, (const T*)p->sig,
                            PI / p->geo.Lt, (const T*)p->tw, p->rev, p->revinv, st); }
     { TimedStage ts(tm, ST_FFTYI, st);
-      launch_fft_inverse<T>(p->fg, p->gg, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
+      launch_fft_inverse<T>(p->fg, p->gf, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
                             p->revinv, st, 1); }
     { TimedStage ts(tm, ST_FFTXI, st);
-      launch_fft_inverse<T>(p->fg, p->gg, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
+      launch_fft_inverse<T>(p->fg, p->gf, p->B, p->A, field, p->c_in, p->batch, (const T*)p->tw, p->rev,
                             p->revinv, st, 2); }
+}
+
+// The field the quadrature reads: `field` itself, or for periodic sums its
+// copy unfolded onto the extended grid.
+template <typename T> const T* quad_field(fse_plan* p, const T* field) {
+    if (!p->periodic) return field;
+    launch_unfold<T>(field, p->gf.Mt, p->gg.Mt, p->pshift, p->batch * 3, (T*)p->gext, p->stream);
+    return (const T*)p->gext;
 }
 
 double self_coef(const fse_plan* p) {
@@ -558,17 +765,50 @@ fse_status_t eval_t(fse_plan* p, const T* a, const T* b, T* u_real, T* u_four, b
     fourier_chain<T>(p, (const T*)p->src_s, (T*)p->phi);
     p->forward_valid = true;
     if (combined) {
-        { TimedStage ts(tm, ST_GATHER, st); launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_real, st); }
+        { TimedStage ts(tm, ST_GATHER, st);
+          launch_gather<T>(p->gg, pd, quad_field<T>(p, (const T*)p->phi), p->batch, u_real, st); }
         { TimedStage ts(tm, ST_REAL, st);
           launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, p->batch,
                          p->prm.xi, self_coef(p), u_real, 1, st); }
     } else {
-        if (u_four) { TimedStage ts(tm, ST_GATHER, st); launch_gather<T>(p->gg, pd, (const T*)p->phi, p->batch, u_four, st); }
+        if (u_four) {
+            TimedStage ts(tm, ST_GATHER, st);
+            launch_gather<T>(p->gg, pd, quad_field<T>(p, (const T*)p->phi), p->batch, u_four, st);
+        }
         if (u_real) {
             TimedStage ts(tm, ST_REAL, st);
             launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, p->batch,
                            p->prm.xi, self_coef(p), u_real, 0, st);
         }
+    }
+    LAUNCHCHK();
+    return FSE_OK;
+}
+
+// u at the separate targets: u^F by quadrature at the targets, plus u^R over
+// the sources within r_c of each target (no self term: a target is no source).
+template <typename T> fse_status_t eval_targets_t(fse_plan* p, const T* a, const T* b, T* u_real, T* u_four) {
+    hipStream_t st = p->stream;
+    const int64_t n = p->n;
+    Timer& tm = p->timer;
+    {
+        TimedStage ts(tm, ST_PERMUTE, st);
+        launch_permute_sources<T>((int)p->kernel, a, b, n, p->batch, p->perm_s, (T*)p->src_s, st);
+        launch_permute3<T>(a, n, p->batch, p->perm_r, (T*)p->src_ra, st);
+        if (p->kernel == FSE_STRESSLET) launch_permute3<T>(b, n, p->batch, p->perm_r, (T*)p->src_rb, st);
+    }
+    fourier_chain<T>(p, (const T*)p->src_s, (T*)p->phi);
+    p->forward_valid = true;
+    const bool combined = u_four == nullptr;
+    T* uf = combined ? u_real : u_four;
+    if (uf) {
+        TimedStage ts(tm, ST_GATHER, st);
+        launch_gather<T>(p->gg, target_points<T>(p), (const T*)p->phi, p->batch, uf, st);
+    }
+    if (u_real) {
+        TimedStage ts(tm, ST_REAL, st);
+        launch_real<T>((int)p->kernel, p->cg, source_target_points<T>(p), (const T*)p->src_ra,
+                       (const T*)p->src_rb, p->batch, p->prm.xi, 0.0, u_real, combined ? 1 : 0, st);
     }
     LAUNCHCHK();
     return FSE_OK;
@@ -613,8 +853,62 @@ fse_status_t adjoint_t(fse_plan* p, const T* f, const T* w, T* dsrc, T* dx, int 
     return FSE_OK;
 }
 
-}  // namespace
+// Stresslet adjoint for L = sum_m w_m . u(x_m): D_lm(x_b) = sum_a w_j(a)
+// T_jlm(x_a - x_b) by the transposed chain (w spread as 3 components, each
+// member's spectrum duplicated so that the z-pass with the transposed
+// multiplier fills the six symmetric components as two halves of three, the
+// inverse passes and quadrature of those six), contracted with the points' own
+// n and q, plus the real-space part over the pairs within r_c.
+template <typename T>
+fse_status_t adjoint_stresslet_t(fse_plan* p, const T* q, const T* nrm, const T* w, T* dq, T* dn) {
+    using V = C2<T>;
+    hipStream_t st = p->stream;
+    const int64_t n = p->n;
+    const int B = p->batch;
+    PointsDev<T> pd = points<T>(p);
+    Timer& tm = p->timer;
+    {
+        TimedStage ts(tm, ST_PERMUTE, st);
+        launch_permute3<T>(w, n, B, p->perm_s, (T*)p->adj_s, st);
+        launch_permute3<T>(w, n, B, p->perm_r, (T*)p->adj_r, st);
+        launch_permute3<T>(q, n, B, p->perm_r, (T*)p->src_ra, st);
+        launch_permute3<T>(nrm, n, B, p->perm_r, (T*)p->src_rb, st);
+    }
+    const int64_t lstride = (int64_t)(p->geo.Mt + 1) * p->fg.n * p->fg.sz;  // one component of B
+    V* Bs = (V*)p->B;
+    for (int b = 0; b < B; ++b) {
+        const T* wb = (const T*)p->adj_s + (int64_t)b * n * 3;
+        { TimedStage ts(tm, ST_SPREAD, st); launch_spread<T>(p->gg, pd, wb, 3, 1, (T*)p->grid, st); }
+        { TimedStage ts(tm, ST_FFTX, st);
+          launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, Bs + 6 * b * lstride, 3, (const T*)p->tw,
+                                p->rev, p->revinv, st, 1); }
+        { TimedStage ts(tm, ST_FFTY, st);
+          launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, Bs + 6 * b * lstride, 3, (const T*)p->tw,
+                                p->rev, p->revinv, st, 2);
+          HIPCHK(hipMemcpyAsync(Bs + (6 * b + 3) * lstride, Bs + 6 * b * lstride, 3 * lstride * sizeof(V),
+                                hipMemcpyDeviceToDevice, st)); }
+    }
+    { TimedStage ts(tm, ST_FFTZ, st);
+      launch_fft_zscale<T>(p->fg, p->gf, KTADJ, p->B, 3, 2 * B, (const T*)p->sig, PI / p->geo.Lt,
+                           (const T*)p->tw, p->rev, p->revinv, st); }
+    { TimedStage ts(tm, ST_FFTYI, st);
+      launch_fft_inverse<T>(p->fg, p->gf, p->B, p->A, (T*)p->phi, 3, 2 * B, (const T*)p->tw, p->rev, p->revinv,
+                            st, 1); }
+    { TimedStage ts(tm, ST_FFTXI, st);
+      launch_fft_inverse<T>(p->fg, p->gf, p->B, p->A, (T*)p->phi, 3, 2 * B, (const T*)p->tw, p->rev, p->revinv,
+                            st, 2); }
+    p->forward_valid = false;  // phi now holds the adjoint field
+    { TimedStage ts(tm, ST_GATHER, st);
+      launch_gather<T>(p->gg, pd, (const T*)p->phi, 2 * B, (T*)p->tadj, st);
+      launch_tadj_contract<T>((const T*)p->tadj, q, nrm, n, B, dq, dn, st); }
+    { TimedStage ts(tm, ST_REAL, st);
+      launch_real_tadj<T>(p->cg, pd, (const T*)p->src_ra, (const T*)p->src_rb, (const T*)p->adj_r, B, p->prm.xi,
+                          dq, dn, st); }
+    LAUNCHCHK();
+    return FSE_OK;
+}
 
+}  // namespace
 
 namespace {
 
@@ -653,12 +947,27 @@ void setup_plan(fse_plan* p, fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
     for (int d = 0; d < 3; ++d) gg.x0[d] = geo.x0[d];
     gg.h = geo.h;
     gg.ahh = geo.alpha * geo.h * geo.h;
+    p->gf = gg;
+    p->family = kernel == FSE_ROTLET ? 1 : 0;
+    p->periodic = params->periodic != 0;
+    if (p->periodic) {
+        // windows start at floor(t - P/2 + 1) >= -(ceil(P/2) - 1) in period units:
+        // the extended grid starts that many nodes below the box and has P - 1
+        // nodes more than the period, so no window wraps
+        p->pshift = (params->P + 1) / 2 - 1;
+        // window starts run from -pshift to M - P/2 (even P) or M - (P - 1)/2 (odd
+        // P), so the windows span M + P - 1 (even) or M + P (odd) nodes
+        gg.Mt = geo.Mt + params->P - 1 + (params->P & 1);
+        gg.nt = (gg.Mt + gg.TS - 1) / gg.TS;
+        for (int d = 0; d < 3; ++d) gg.x0[d] = geo.x0[d] - p->pshift * geo.h;
+    }
     CellGeo& cg = p->cg;
     cg.ncell = geo.ncell;
     for (int d = 0; d < 3; ++d) cg.lo[d] = params->box_lo[d];
     cg.L = params->L;
     cg.cell = geo.cell;
     cg.rc2 = params->rc * params->rc;
+    cg.periodic = params->periodic != 0;
     FftGeo& fg = p->fg;
     fg.n = geo.n_fft;
     fg.ns = 0;
@@ -685,6 +994,44 @@ void setup_plan(fse_plan* p, fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
             s += 1;
         }
     }
+}
+
+// Free-space solver (Section 4.1-4.3): u = G * f on the M^3 grid with the
+// truncated kernel's transform (precompute of Section 4.3) and the zero-padded
+// transforms of size 2M; f, u: ncomp fields of M^3, processed three at a time.
+template <typename T> fse_status_t freespace_solve_t(fse_plan* p, int ncomp, const T* f, T* u) {
+    using V = C2<T>;
+    const int M = p->geo.Mt, n = p->geo.n_fft, groups = p->batch;
+    const int64_t M3 = (int64_t)M * M * M, Mp = M + 1;
+    TRY(p->alloc((T**)&p->grid, 3 * groups * M3));
+    TRY(p->alloc((T**)&p->phi, 3 * groups * M3));
+    TRY(p->alloc((V**)&p->A, 3 * groups * Mp * M * (size_t)p->fg.sy));
+    TRY(p->alloc((V**)&p->B, 3 * groups * Mp * n * (size_t)p->fg.sz));
+    TRY(p->alloc(&p->sig64, Mp * Mp * Mp));
+    TRY(p->alloc((T**)&p->sig, Mp * Mp * Mp));
+    TRY(p->alloc((T**)&p->tw, 2 * n));
+    TRY(p->alloc(&p->rev, n));
+    TRY(p->alloc(&p->revinv, n));
+    TRY(upload_fft_tables<T>(p));
+    TRY(precompute<T>(p));
+    hipStream_t st = p->stream;
+    HIPCHK(hipMemcpyAsync(p->grid, f, ncomp * M3 * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (3 * groups > ncomp)
+        HIPCHK(hipMemsetAsync((T*)p->grid + ncomp * M3, 0, (3 * groups - ncomp) * M3 * sizeof(T), st));
+    launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, p->B, 3 * groups, (const T*)p->tw, p->rev,
+                          p->revinv, st, 1);
+    launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, p->B, 3 * groups, (const T*)p->tw, p->rev,
+                          p->revinv, st, 2);
+    launch_fft_zscale<T>(p->fg, p->gf, KSCALAR, p->B, 3, groups, (const T*)p->sig, PI / p->geo.Lt, (const T*)p->tw,
+                         p->rev, p->revinv, st);
+    launch_fft_inverse<T>(p->fg, p->gf, p->B, p->A, (T*)p->phi, 3, groups, (const T*)p->tw, p->rev, p->revinv, st,
+                          1);
+    launch_fft_inverse<T>(p->fg, p->gf, p->B, p->A, (T*)p->phi, 3, groups, (const T*)p->tw, p->rev, p->revinv, st,
+                          2);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(u, p->phi, ncomp * M3 * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));  // the workspace is freed on return
+    return FSE_OK;
 }
 
 }  // namespace
@@ -766,9 +1113,29 @@ fse_status_t fse_eval_parts(fse_plan_t* plan, const void* a, const void* b, void
                                 false);
 }
 
+fse_status_t fse_set_targets(fse_plan_t* plan, int64_t nt, const void* y, int32_t validate) {
+    if (!plan || !y) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->periodic) { set_err("not implemented for the periodic sum"); return FSE_EUNSUPPORTED; }
+    if (nt < 1 || nt > (int64_t)1 << 30) { set_err("nt=%lld outside [1, 2^30]", (long long)nt); return FSE_EINVAL; }
+    return plan->dtype == FSE_F32 ? set_targets_t<float>(plan, nt, (const float*)y, validate)
+                                  : set_targets_t<double>(plan, nt, (const double*)y, validate);
+}
+
+fse_status_t fse_eval_targets(fse_plan_t* plan, const void* a, const void* b, void* u_real, void* u_fourier) {
+    if (!plan || !a || (!u_real && !u_fourier)) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->kernel == FSE_STRESSLET && !b) { set_err("stresslet needs the normals (src_b)"); return FSE_EINVAL; }
+    if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
+    if (plan->tg.n == 0) { set_err("fse_set_targets must come first"); return FSE_ESTATE; }
+    return plan->dtype == FSE_F32
+               ? eval_targets_t<float>(plan, (const float*)a, (const float*)b, (float*)u_real, (float*)u_fourier)
+               : eval_targets_t<double>(plan, (const double*)a, (const double*)b, (double*)u_real,
+                                        (double*)u_fourier);
+}
+
 fse_status_t fse_eval_adjoint(fse_plan_t* plan, const void* a, const void* w, void* dsrc, void* dx,
                               int32_t recompute) {
     if (!plan || !a || !w) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->periodic) { set_err("not implemented for the periodic sum"); return FSE_EUNSUPPORTED; }
     if (plan->kernel == FSE_STRESSLET) { set_err("the stresslet adjoint is not implemented"); return FSE_EUNSUPPORTED; }
     if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
     if (!dsrc && !dx) return FSE_OK;
@@ -776,6 +1143,18 @@ fse_status_t fse_eval_adjoint(fse_plan_t* plan, const void* a, const void* w, vo
                ? adjoint_t<float>(plan, (const float*)a, (const float*)w, (float*)dsrc, (float*)dx, recompute)
                : adjoint_t<double>(plan, (const double*)a, (const double*)w, (double*)dsrc, (double*)dx,
                                    recompute);
+}
+
+fse_status_t fse_eval_adjoint_stresslet(fse_plan_t* plan, const void* q, const void* nrm, const void* w, void* dq,
+                                        void* dn) {
+    if (!plan || !q || !nrm || !w || !dq || !dn) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->kernel != FSE_STRESSLET) { set_err("not a stresslet plan"); return FSE_EINVAL; }
+    if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
+    return plan->dtype == FSE_F32
+               ? adjoint_stresslet_t<float>(plan, (const float*)q, (const float*)nrm, (const float*)w, (float*)dq,
+                                            (float*)dn)
+               : adjoint_stresslet_t<double>(plan, (const double*)q, (const double*)nrm, (const double*)w,
+                                             (double*)dq, (double*)dn);
 }
 
 fse_status_t fse_plan_multiplier(fse_plan_t* plan, double* out) {
@@ -834,6 +1213,49 @@ fse_status_t fse_plan_workspace(const fse_plan_t* plan, size_t* bytes) {
     if (!plan || !bytes) { set_err("null argument"); return FSE_EINVAL; }
     *bytes = plan->bytes;
     return FSE_OK;
+}
+
+fse_status_t fse_freespace_solve(int32_t family, fse_dtype_t dtype, int32_t M, double h, int32_t ncomp, const void* f,
+                                 void* u, void* stream) {
+    if (!f || !u) { set_err("null argument"); return FSE_EINVAL; }
+    if (family != 0 && family != 1) { set_err("family must be 0 (biharmonic) or 1 (harmonic)"); return FSE_EINVAL; }
+    if (dtype != FSE_F32 && dtype != FSE_F64) { set_err("unknown dtype"); return FSE_EINVAL; }
+    if (M < 2 || M > MAX_MT || !smooth7(2 * M)) {
+        set_err("M=%d: need 2 <= M <= %d and 2M factoring into 2,3,5,7", M, MAX_MT);
+        return FSE_EINVAL;
+    }
+    if (!(h > 0) || !isfinite(h) || ncomp < 1) { set_err("need h > 0 and ncomp >= 1"); return FSE_EINVAL; }
+    fse_geometry_t geo;
+    memset(&geo, 0, sizeof geo);
+    geo.Mt = M;
+    geo.n_fft = 2 * M;
+    geo.h = h;
+    geo.Lt = M * h;
+    geo.R = sqrt(3.0) * geo.Lt;  // Section 4.1: the truncation radius covers the box diagonal
+    int Mg = (int)floor((1.0 + sqrt(3.0)) * M) + 1;
+    if (Mg % 2) ++Mg;
+    geo.Mg = Mg;
+    geo.kinf = PI / h;
+    geo.ncell = 1;
+    geo.cell = geo.Lt;
+    int rad[MAX_RADICES];
+    const int ns = factorize(geo.n_fft, rad);
+    if (ns < 0 || ns > 7) { set_err("cannot factor n=%d", geo.n_fft); return FSE_EINVAL; }
+    for (int s = 0; s < ns; ++s) geo.radices[s] = rad[s];
+    fse_params_t prm;
+    memset(&prm, 0, sizeof prm);
+    prm.xi = 1.0;
+    prm.rc = geo.Lt;
+    prm.M = M;
+    prm.P = 2;
+    prm.L = geo.Lt;
+    prm.Mt = M;
+    fse_plan p;  // host object; its device buffers are freed on return
+    setup_plan(&p, FSE_STOKESLET, dtype, &prm, geo, (ncomp + 2) / 3, 2, stream);
+    p.solver = true;
+    p.family = family;
+    return dtype == FSE_F32 ? freespace_solve_t<float>(&p, ncomp, (const float*)f, (float*)u)
+                            : freespace_solve_t<double>(&p, ncomp, (const double*)f, (double*)u);
 }
 
 void fse_plan_destroy(fse_plan_t* plan) {

@@ -150,6 +150,59 @@ __global__ void k_permute3(const T* __restrict__ a, int64_t n, const int* __rest
     o[2] = ai[2];
 }
 
+template <typename T>
+__global__ void k_tadj_contract(const T* __restrict__ dg, const T* __restrict__ q, const T* __restrict__ nrm,
+                                int64_t n, T* dq, T* dn) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int bm = blockIdx.y;
+    if (i >= n) return;
+    const T* d0 = dg + ((int64_t)(2 * bm) * n + i) * 3;
+    const T* d1 = dg + ((int64_t)(2 * bm + 1) * n + i) * 3;
+    const T D[3][3] = {{d0[0], d1[0], d1[1]}, {d1[0], d0[1], d1[2]}, {d1[1], d1[2], d0[2]}};
+    const int64_t o = ((int64_t)bm * n + i) * 3;
+    const T nv[3] = {nrm[o], nrm[o + 1], nrm[o + 2]}, qv[3] = {q[o], q[o + 1], q[o + 2]};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        dq[o + l] = D[l][0] * nv[0] + D[l][1] * nv[1] + D[l][2] * nv[2];
+        dn[o + l] = D[0][l] * qv[0] + D[1][l] * qv[1] + D[2][l] * qv[2];
+    }
+}
+
+template <typename T>
+__global__ void k_fold(const T* __restrict__ ext, int Me, int M, int s, T* grid) {
+    const int64_t M3 = (int64_t)M * M * M;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (q >= M3) return;
+    const int x = (int)(q % M), y = (int)((q / M) % M), z = (int)(q / ((int64_t)M * M));
+    // the extended indices of periodic index j: j + s, and j + s - M or j + s + M when in range
+    int ex[3], ey[3], ez[3], nx = 0, ny = 0, nz = 0;
+    auto images = [&](int j, int* e, int& k) {
+        for (int a = j + s - M; a < Me; a += M)
+            if (a >= 0) e[k++] = a;
+    };
+    images(x, ex, nx);
+    images(y, ey, ny);
+    images(z, ez, nz);
+    const T* src = ext + (int64_t)c * Me * Me * Me;
+    T v = (T)0;
+    for (int a = 0; a < nz; ++a)
+        for (int b = 0; b < ny; ++b)
+            for (int d = 0; d < nx; ++d) v += src[((int64_t)ez[a] * Me + ey[b]) * Me + ex[d]];
+    grid[(int64_t)c * M3 + q] = v;
+}
+
+template <typename T>
+__global__ void k_unfold(const T* __restrict__ field, int M, int Me, int s, T* ext) {
+    const int64_t E3 = (int64_t)Me * Me * Me;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (q >= E3) return;
+    const int x = (int)(q % Me), y = (int)((q / Me) % Me), z = (int)(q / ((int64_t)Me * Me));
+    auto wrap = [&](int e) { const int j = e - s; return j < 0 ? j + M : (j >= M ? j - M : j); };
+    ext[(int64_t)c * E3 + q] = field[(int64_t)c * M * M * M + ((int64_t)wrap(z) * M + wrap(y)) * M + wrap(x)];
+}
+
 // per-cell work items of the real-space pass: ceil(count / S); the extra entry is 0
 __global__ void k_cell_slices(int* cnt, int64_t ncells, int S) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,6 +290,24 @@ void launch_permute_sources(int kernel, const T* a, const T* b, int64_t n, int b
 }
 
 template <typename T>
+void launch_fold(const T* ext, int Me, int M, int s, int ncomp, T* grid, hipStream_t st) {
+    const int64_t M3 = (int64_t)M * M * M;
+    hipLaunchKernelGGL(k_fold<T>, dim3(nblk(M3, 256), ncomp), dim3(256), 0, st, ext, Me, M, s, grid);
+}
+
+template <typename T>
+void launch_unfold(const T* field, int M, int Me, int s, int ncomp, T* ext, hipStream_t st) {
+    const int64_t E3 = (int64_t)Me * Me * Me;
+    hipLaunchKernelGGL(k_unfold<T>, dim3(nblk(E3, 256), ncomp), dim3(256), 0, st, field, M, Me, s, ext);
+}
+
+template <typename T>
+void launch_tadj_contract(const T* dg, const T* q, const T* nrm, int64_t n, int batch, T* dq, T* dn,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_tadj_contract<T>, dim3(nblk(n, 256), batch), dim3(256), 0, st, dg, q, nrm, n, dq, dn);
+}
+
+template <typename T>
 void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, hipStream_t st) {
     hipLaunchKernelGGL(k_permute3<T>, dim3(nblk(n, 256), batch), dim3(256), 0, st, a, n, perm, out);
 }
@@ -248,7 +319,10 @@ void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, 
                                     int*, T*, T*, int*, hipStream_t);                               \
     template void launch_permute_sources<T>(int, const T*, const T*, int64_t, int, const int*, T*,  \
                                             hipStream_t);                                           \
-    template void launch_permute3<T>(const T*, int64_t, int, const int*, T*, hipStream_t);
+    template void launch_permute3<T>(const T*, int64_t, int, const int*, T*, hipStream_t);                 \
+    template void launch_tadj_contract<T>(const T*, const T*, const T*, int64_t, int, T*, T*, hipStream_t); \
+    template void launch_fold<T>(const T*, int, int, int, int, T*, hipStream_t);                           \
+    template void launch_unfold<T>(const T*, int, int, int, int, T*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -10,6 +10,12 @@
 namespace fse {
 
 constexpr int WAVE = 64;
+// Kernel index of the stresslet's transpose (its adjoint from a 3-vector field to
+// the symmetric 2-tensor D_lm), beside FSE_STOKESLET / FSE_STRESSLET / FSE_ROTLET.
+constexpr int KTADJ = 3;
+// Kernel index of the plain scalar convolution (the free-space solver): each of
+// three components multiplied by the scalar transform.
+constexpr int KSCALAR = 4;
 
 // ---------------------------------------------------------------------------
 // complex helpers (float2 / double2)
@@ -117,6 +123,7 @@ struct CellGeo {
     double L;        // box side
     double cell;     // cell side (>= rc)
     double rc2;      // rc^2
+    int periodic;    // 1: the cells wrap with period L (triply periodic sums)
 };
 
 constexpr int MAX_RADICES = 12;
@@ -153,6 +160,15 @@ template <typename T> struct PointsDev {
     const int* work_start;    // (ncell^3 + 1) real-space work items: cell c owns items
                               // [work_start[c], work_start[c+1]), each of up to real_S targets
     int real_S;               // targets per real-space work item (= threads per workgroup)
+    // Targets of the real-space pass (the same arrays as above when the targets
+    // are the sources): positions in their cell order, cell offsets, cell order
+    // -> user index, work items, and their count.
+    int64_t t_n;
+    const T* t_x_r;
+    const int* t_cell_start;
+    const int* t_perm_r;
+    const int* t_work_start;
+    int t_real_S;
 };
 
 // thread-local message returned by fse_last_error (printf format)
@@ -192,6 +208,20 @@ void launch_scatter(const T* x, int64_t n, const int* perm_s, const int* perm_r,
 template <typename T>
 void launch_permute_sources(int kernel, const T* a, const T* b, int64_t n, int batch, const int* perm,
                             T* out, hipStream_t st);
+// Contract the quadrature of the stresslet-transpose field with the points' own
+// q and n: dg (2 batch, n, 3) holds D = (D00, D11, D22) in row 2b and (D01, D02,
+// D12) in row 2b + 1 (user order); dq_l = D_lm n_m, dn_m = D_lm q_l (overwritten).
+template <typename T>
+void launch_tadj_contract(const T* dg, const T* q, const T* nrm, int64_t n, int batch, T* dq, T* dn,
+                          hipStream_t st);
+// Periodic grids: the spreading grid extends the M^3 period by P - 1 nodes (P
+// for odd P; index e = j + s, s = ceil(P/2) - 1, j the periodic index), so that
+// windows never wrap.  fold: grid(j) = sum of ext(e) over the e = j + s (mod M) in range;
+// unfold: ext(e) = field((e - s) mod M).  ncomp components of M^3 / Me^3 each.
+template <typename T>
+void launch_fold(const T* ext, int Me, int M, int s, int ncomp, T* grid, hipStream_t st);
+template <typename T>
+void launch_unfold(const T* field, int M, int Me, int s, int ncomp, T* ext, hipStream_t st);
 // permute plain 3-vectors (batch, n, 3) by perm
 template <typename T>
 void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, hipStream_t st);
@@ -231,6 +261,12 @@ template <typename T>
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
                       int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st);
 
+// dq += D^R n, dn += D^R q with D^R_lm(t) = sum_s T^R_jlm(x_s - x_t) w_j(s), the
+// real-space part of the stresslet adjoint (q_r, n_r, w_r in real-space order)
+template <typename T>
+void launch_real_tadj(const CellGeo& c, const PointsDev<T>& p, const T* q_r, const T* n_r, const T* w_r,
+                      int batch, double xi, T* dq, T* dn, hipStream_t st);
+
 // precompute (FP64)
 void launch_pre_fill(double* out, int Mg, double h, double R, int family, hipStream_t st);
 void launch_pre_contract(const double* in, double* out, const double* Cm, int J, int K, int64_t A,
@@ -238,5 +274,9 @@ void launch_pre_contract(const double* in, double* out, const double* Cm, int J,
 template <typename T>
 void launch_pre_finalize(const double* Bt, int Mt, double kunit, double xi, double eta, int kernel,
                          double norm, double* sig64, T* sig, hipStream_t st);
+// periodic stokeslet: the eq. ShatH kernel at the even indices of the (2 Mt)^3 grid
+template <typename T>
+void launch_pre_periodic(int Mt, double kunit, double xi, double eta, double norm, double* sig64, T* sig,
+                         hipStream_t st);
 
 }  // namespace fse

@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_fft_y(FftGeo fg, int Mt, const C2<T>* _
 // Apply the k-polynomial of the kernel at wavevector k (physical units) to the
 // c_in grid components g, giving 3 outputs (the scalar sigma is applied after).
 template <typename T, int KERNEL>
-__device__ __forceinline__ void kpoly(const T k[3], const C2<T>* g, C2<T>* w) {
+__device__ __forceinline__ void kpoly(const T k[3], const C2<T>* g, C2<T>* w, int half = 0) {
     using V = C2<T>;
     const T k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     if constexpr (KERNEL == FSE_STOKESLET) {
@@ -416,6 +416,25 @@ __device__ __forceinline__ void kpoly(const T k[3], const C2<T>* g, C2<T>* w) {
         w[0] = cmuli<-1>(c0);
         w[1] = cmuli<-1>(c1);
         w[2] = cmuli<-1>(c2);
+    } else if constexpr (KERNEL == KSCALAR) {
+        w[0] = g[0];
+        w[1] = g[1];
+        w[2] = g[2];
+    } else if constexpr (KERNEL == KTADJ) {
+        // The stresslet's transpose: its multiplier -i P_j,lm(k) (P fully symmetric)
+        // has the adjoint +i P_j,lm(k) g_j = +i [k^2 (g_l k_m + g_m k_l + d_lm k.g)
+        // - 2 k_l k_m k.g], three of the six symmetric (l, m) per half:
+        // half 0: (00, 11, 22), half 1: (01, 02, 12)
+        const V kg = cadd(cadd(cscale(g[0], k[0]), cscale(g[1], k[1])), cscale(g[2], k[2]));
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            const int l = half ? (o == 2 ? 1 : 0) : o;
+            const int m = half ? (o == 0 ? 1 : 2) : o;
+            V t = cadd(cscale(g[l], k[m]), cscale(g[m], k[l]));
+            if (!half) t = cadd(t, kg);
+            t = csub(cscale(t, k2), cscale(kg, (T)2 * k[l] * k[m]));
+            w[o] = cmuli<1>(t);
+        }
     } else {
         // -i [ k^2 (2 (G k)_j + k_j tr G) - 2 k_j (k.G.k) ],  G symmetric:
         // g = (G00, G11, G22, G01, G02, G12)
@@ -620,13 +639,13 @@ __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, int zc, C2<T>*
             // wavenumbers in [-Mt, Mt): the Nyquist index carries -Mt in every direction
             T k[3] = {ks * (T)(nyx ? -Mt : kx), ks * (T)kys, ks * (T)kzs};
             V w[3];
-            kpoly<T, KERNEL>(k, g, w);
+            kpoly<T, KERNEL>(k, g, w, bm & 1);
             if (nyx || nyy || nyz) {
                 // Nyquist planes: use the Hermitian part of the multiplier, the mean
                 // of its values at k and at k with the Nyquist components negated.
                 T kr[3] = {nyx ? -k[0] : k[0], nyy ? -k[1] : k[1], nyz ? -k[2] : k[2]};
                 V wr[3];
-                kpoly<T, KERNEL>(kr, g, wr);
+                kpoly<T, KERNEL>(kr, g, wr, bm & 1);
 #pragma unroll
                 for (int j = 0; j < 3; ++j) w[j] = cscale(cadd(w[j], wr[j]), (T)0.5);
             }
@@ -850,7 +869,7 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
 #define FSE_ZBT32 256
 #endif
     if constexpr (sizeof(T) == 4 && FSE_ZB32 > 1) {
-        if (kernel != FSE_STRESSLET) {
+        if (kernel == FSE_STOKESLET || kernel == FSE_ROTLET) {
 #ifndef FSE_ZBG32
 #define FSE_ZBG32 2
 #endif
@@ -872,6 +891,8 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
     }
     if (kernel == FSE_STOKESLET) ZPICK(FSE_STOKESLET, 3);
     else if (kernel == FSE_ROTLET) ZPICK(FSE_ROTLET, 3);
+    else if (kernel == KTADJ) ZPICK(KTADJ, 3);  // batch = 2 x members: halves of the 6 outputs
+    else if (kernel == KSCALAR) ZPICK(KSCALAR, 3);
     else ZPICK(FSE_STRESSLET, 6);
 #undef ZPICK
 #undef ZLAUNCH

@@ -17,6 +17,7 @@
 // thread and evaluated wave-wide.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "fse_common.h"
 
@@ -142,13 +143,23 @@ struct __align__(4 * sizeof(T)) Pos4 {
 //   WVAL (with GRAD): also out2 += sum_pairs G^R w_s + self_coef w_t per batch
 //                 member (the real-space part of dL/df = K w), in the same pass
 template <typename T, int KERNEL, int NB, bool GRAD, bool WVAL = false>
-__global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict__ cell_start,
-                                             const T* __restrict__ x_r, const T* __restrict__ a_r,
+__global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const T* __restrict__ a_r,
                                              const T* __restrict__ b_r, const T* __restrict__ w_r,
-                                             int64_t n, int batch, T xi, T self_coef,
-                                             const int* __restrict__ perm_r, T* out, int accumulate,
-                                             T* out2, const int* __restrict__ work_start) {
-    constexpr int NS = (KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3;  // staged values per source and batch
+                                             int batch, T xi, T self_coef, T* out, int accumulate,
+                                             T* out2) {
+    // sources: the cell list of the points; targets: their own cell list (the
+    // same one when the targets are the sources; GRAD needs that)
+    const int* __restrict__ cell_start = pd.cell_start;
+    const T* __restrict__ x_r = pd.x_r;
+    const int64_t n = pd.n;
+    const int* __restrict__ tcell_start = pd.t_cell_start;
+    const T* __restrict__ tx_r = pd.t_x_r;
+    const int64_t nt = pd.t_n;
+    const int* __restrict__ perm_r = pd.t_perm_r;
+    const int* __restrict__ work_start = pd.t_work_start;
+    constexpr bool TADJ = KERNEL == KTADJ;  // the stresslet adjoint: sources carry w, targets q and n
+    constexpr int NS = TADJ ? 3 : ((KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3);  // staged values per source
+    constexpr int NO = TADJ ? 6 : 3;  // accumulated values per target and batch member
     // source slots per LDS chunk
     constexpr int CH = sizeof(T) == 4 ? FSE_REAL_CH32 : FSE_REAL_CH64;
     static_assert(CH % 8 == 0, "candidates are tested in groups of 8");
@@ -171,8 +182,8 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     const int cell = lo;
     const int cx = cell % nc, cy = (cell / nc) % nc, cz = cell / (nc * nc);
     const int b0 = blockIdx.y * NB;
-    const int t0 = cell_start[cell] + (item - work_start[cell]) * nthr;
-    const int t1 = min(cell_start[cell + 1], t0 + nthr);
+    const int t0 = tcell_start[cell] + (item - work_start[cell]) * nthr;
+    const int t1 = min(tcell_start[cell + 1], t0 + nthr);
     const T rc2 = (T)cg.rc2;
     // the candidate test uses |xl|^2 + |xs_l|^2 - 2 xl . xs_l in coordinates about
     // the cell corner, slightly widened (its rounding is ~1e-7 of rc^2 in FP32);
@@ -186,6 +197,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     // the 27 neighbour cells (empty beyond the box): lane k < 27 of every wave
     // holds the start and count of cell k
     __shared__ int ch_off[28], ch_base[27];
+    __shared__ T ch_sh[27][3];  // periodic: the image shift of each neighbour cell's sources
     __shared__ int s_kc[4];    // kept sources per wave in a staging round
     __shared__ T s_bb[4][6];   // per wave: target bounding box (low x, y, z, high x, y, z)
     __shared__ T s_box[6];     // the work item's target bounding box
@@ -193,12 +205,28 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
     {
         const int lane = tid & 63;
         if (lane < 27) {
-            const int nx = cx + lane % 3 - 1, ny = cy + (lane / 3) % 3 - 1, nz = cz + lane / 9 - 1;
-            if (nx >= 0 && nx < nc && ny >= 0 && ny < nc && nz >= 0 && nz < nc) {
-                const int cc = (nz * nc + ny) * nc + nx;
+            int nb[3] = {cx + lane % 3 - 1, cy + (lane / 3) % 3 - 1, cz + lane / 9 - 1};
+            T sh[3] = {(T)0, (T)0, (T)0};
+            bool ok = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (cg.periodic) {
+                    // the neighbour beyond a face is the cell across the box, its
+                    // sources taken at their image next to this cell
+                    if (nb[d] < 0) { nb[d] += nc; sh[d] = (T)-cg.L; }
+                    else if (nb[d] >= nc) { nb[d] -= nc; sh[d] = (T)cg.L; }
+                } else if (nb[d] < 0 || nb[d] >= nc) {
+                    ok = false;
+                }
+            }
+            if (ok) {
+                const int cc = (nb[2] * nc + nb[1]) * nc + nb[0];
                 nb_s = cell_start[cc];
                 nb_n = cell_start[cc + 1] - nb_s;
             }
+            if (tid < 27)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ch_sh[tid][d] = sh[d];
         }
     }
     int tot = nb_n;
@@ -211,31 +239,42 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         const bool act = j < t1;
         T xt0 = 0, xt1 = 0, xt2 = 0;
         if (act) {
-            xt0 = x_r[3 * (int64_t)j];
-            xt1 = x_r[3 * (int64_t)j + 1];
-            xt2 = x_r[3 * (int64_t)j + 2];
+            xt0 = tx_r[3 * (int64_t)j];
+            xt1 = tx_r[3 * (int64_t)j + 1];
+            xt2 = tx_r[3 * (int64_t)j + 2];
         }
         const T xl0 = xt0 - ox, xl1 = xt1 - oy, xl2 = xt2 - oz;
         // idle lanes: a squared norm beyond any cutoff
         const T At = act ? xl0 * xl0 + xl1 * xl1 + xl2 * xl2 : (T)FAR;
-        // target-side values for the gradient: f_t, w_t per batch member
+        // target-side values: f_t, w_t per batch member (gradient), or the target's
+        // own q_t, n_t (stresslet adjoint)
         T ft[NB][3], wt[NB][3];
         // acc holds the pairs of one flush; sum the flush totals: the FP32 rounding of
         // a target whose total is dominated by a close pair then grows with the
         // number of flushes, not with the number of pairs
-        T acc[NB][3], sum[NB][3];
+        // the gradient pass keeps its flush totals in FP64 (FP32 form): dL/dx sums
+        // 1/r^2-type terms whose FP32 totals lose digits in dense clusters
+        using S = typename std::conditional<GRAD, double, T>::type;
+        T acc[NB][NO];
+        S sum[NB][NO];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int d = 0; d < NO; ++d) {
+                acc[b][d] = (T)0;
+                sum[b][d] = (S)0;
+            }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                acc[b][d] = sum[b][d] = (T)0;
                 ft[b][d] = wt[b][d] = (T)0;
-                if (GRAD && act && b0 + b < batch) {
+                if ((GRAD || TADJ) && act && b0 + b < batch) {
                     ft[b][d] = a_r[((int64_t)(b0 + b) * n + j) * 3 + d];
-                    wt[b][d] = w_r[((int64_t)(b0 + b) * n + j) * 3 + d];
+                    wt[b][d] = (TADJ ? b_r : w_r)[((int64_t)(b0 + b) * n + j) * 3 + d];
                 }
             }
-        T g0 = 0, g1 = 0, g2 = 0, gs0 = 0, gs1 = 0, gs2 = 0;
+        }
+        T g0 = 0, g1 = 0, g2 = 0;
+        double gs0 = 0, gs1 = 0, gs2 = 0;
         // this thread's hit queue: column tid of qd, QROW entries per row
         const int QROW = queue_row(nthr);
         const int qsh = QROW == 64 ? 7 : QROW == 128 ? 8 : 9;  // log2 of a row in bytes
@@ -308,6 +347,34 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                         acc[b][0] += c * (f1 * r2v - f2 * r1);
                         acc[b][1] += c * (f2 * r0 - f0 * r2v);
                         acc[b][2] += c * (f0 * r1 - f1 * r0);
+                    }
+                } else if constexpr (TADJ) {
+                    // D_lm(t) += T^R_jlm(x_s - x_t) w_j = -T^R_jlm(r) w_j, r = x_t - x_s:
+                    //   -(A1 (h.w) h_l h_m + A2 (w_l h_m + w_m h_l + d_lm h.w)),
+                    // contracted at once with the target's n (dq) and q (dn)
+                    const T A1 = -(T)2 * ir * ((T)3 * ec * ir + c2x * ((T)3 + (T)2 * xi2 * r2) * e);
+                    const T A2 = c4x3 * r * e;
+                    const T h0 = r0 * ir, h1 = r1 * ir, h2 = r2v * ir;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const T w0 = ss[b][0][kk], w1 = ss[b][1][kk], w2 = ss[b][2][kk];
+                        const T* qv = ft[b];
+                        const T* nv = wt[b];
+                        const T hw = h0 * w0 + h1 * w1 + h2 * w2;
+                        // r . n_t in FP64: n_t is the target's normal, so for points on a
+                        // smooth surface r . n_t ~ r^2 / 2 cancels as in the forward pass
+                        const T hn = (T)((double)r0 * nv[0] + (double)r1 * nv[1] + (double)r2v * nv[2]) * ir;
+                        const T hq = h0 * qv[0] + h1 * qv[1] + h2 * qv[2];
+                        const T wn = w0 * nv[0] + w1 * nv[1] + w2 * nv[2];
+                        const T wq = w0 * qv[0] + w1 * qv[1] + w2 * qv[2];
+                        const T cq = A1 * hw * hn + A2 * wn, cn = A1 * hw * hq + A2 * wq;
+                        const T a2hw = A2 * hw;
+                        acc[b][0] -= cq * h0 + A2 * hn * w0 + a2hw * nv[0];
+                        acc[b][1] -= cq * h1 + A2 * hn * w1 + a2hw * nv[1];
+                        acc[b][2] -= cq * h2 + A2 * hn * w2 + a2hw * nv[2];
+                        acc[b][3] -= cn * h0 + A2 * hq * w0 + a2hw * qv[0];
+                        acc[b][4] -= cn * h1 + A2 * hq * w1 + a2hw * qv[1];
+                        acc[b][5] -= cn * h2 + A2 * hq * w2 + a2hw * qv[2];
                     }
                 } else {
                     const T A1 = -(T)2 * ir * ((T)3 * ec * ir + c2x * ((T)3 + (T)2 * xi2 * r2) * e);
@@ -405,8 +472,8 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    sum[b][d] += acc[b][d];
+                for (int d = 0; d < NO; ++d) {
+                    sum[b][d] += (S)acc[b][d];
                     acc[b][d] = (T)0;
                 }
             if constexpr (GRAD) {
@@ -472,6 +539,11 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
                     ps.x = x_r[3 * (int64_t)k];
                     ps.y = x_r[3 * (int64_t)k + 1];
                     ps.z = x_r[3 * (int64_t)k + 2];
+                    if (cg.periodic) {
+                        ps.x += ch_sh[kc][0];
+                        ps.y += ch_sh[kc][1];
+                        ps.z += ch_sh[kc][2];
+                    }
                     ps.pad = (T)0;
                     src = k;
                     const T l0 = ps.x - ox, l1 = ps.y - oy, l2 = ps.z - oz;
@@ -500,7 +572,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         if (b0 + b < batch) {
-                            const T* ap = a_r + ((int64_t)(b0 + b) * n + src) * 3;
+                            const T* ap = (TADJ ? w_r : a_r) + ((int64_t)(b0 + b) * n + src) * 3;
 #pragma unroll
                             for (int d = 0; d < 3; ++d) ss[b][d][slot] = ap[d];
                             if constexpr (NS == 6) {
@@ -549,29 +621,48 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, const int* __restrict_
         }
         if (act) {
             const int64_t i = perm_r[j];
-            if constexpr (!GRAD) {
+            if constexpr (TADJ) {
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     if (b0 + b >= batch) break;
-                    T* o = out + ((int64_t)(b0 + b) * n + i) * 3;
-                    const T* a = a_r + ((int64_t)(b0 + b) * n + j) * 3;
+                    T* o1 = out + ((int64_t)(b0 + b) * nt + i) * 3;
+                    T* o2 = out2 + ((int64_t)(b0 + b) * nt + i) * 3;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        o1[d] += sum[b][d];
+                        o2[d] += sum[b][3 + d];
+                    }
+                }
+            } else if constexpr (!GRAD) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (b0 + b >= batch) break;
+                    T* o = out + ((int64_t)(b0 + b) * nt + i) * 3;
+                    // the self term exists only where a target is its own source
+                    // (self_coef = 0 for separate targets)
+                    T self[3] = {(T)0, (T)0, (T)0};
+                    if (self_coef != (T)0) {
+                        const T* a = a_r + ((int64_t)(b0 + b) * n + j) * 3;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) self[d] = self_coef * a[d];
+                    }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         const T prev = accumulate ? o[d] : (T)0;
-                        o[d] = prev + sum[b][d] + self_coef * a[d];
+                        o[d] = prev + sum[b][d] + self[d];
                     }
                 }
             } else {
-                out[3 * i] += gs0;
-                out[3 * i + 1] += gs1;
-                out[3 * i + 2] += gs2;
+                out[3 * i] = (T)((double)out[3 * i] + gs0);
+                out[3 * i + 1] = (T)((double)out[3 * i + 1] + gs1);
+                out[3 * i + 2] = (T)((double)out[3 * i + 2] + gs2);
                 if constexpr (WVAL) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         if (b0 + b >= batch) break;
                         T* o = out2 + ((int64_t)(b0 + b) * n + i) * 3;
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) o[d] += sum[b][d] + self_coef * wt[b][d];
+                        for (int d = 0; d < 3; ++d) o[d] = (T)((S)o[d] + sum[b][d] + (S)(self_coef * wt[b][d]));
                     }
                 }
             }
@@ -596,15 +687,14 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
                  hipStream_t st) {
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const int NBc = batch == 1 ? 1 : 4;
-    const unsigned thr = (unsigned)p.real_S;
-    // at most ceil(n / S) + ncells work items; the surplus workgroups return at once
-    const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
+    const unsigned thr = (unsigned)p.t_real_S;
+    // at most ceil(nt / S) + ncells work items; the surplus workgroups return at once
+    const unsigned items = (unsigned)((p.t_n + thr - 1) / thr + ncells);
     const size_t qbytes = (size_t)qcap<T, false>() * queue_row((int)thr) * sizeof(unsigned short);
     dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
-    hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p.cell_start, p.x_r, src_a_r, \
-                       src_b_r, (const T*)nullptr, p.n, batch, (T)xi, (T)self_coef, p.perm_r, u, accumulate,  \
-                       (T*)nullptr, p.work_start)
+    hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p, src_a_r, src_b_r,        \
+                       (const T*)nullptr, batch, (T)xi, (T)self_coef, u, accumulate, (T*)nullptr)
     if (kernel == FSE_STOKESLET) {
         if (NBc == 1) LAUNCH(FSE_STOKESLET, 1); else LAUNCH(FSE_STOKESLET, 4);
     } else if (kernel == FSE_ROTLET) {
@@ -629,9 +719,8 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
         const T* w = w_r + (int64_t)b0 * p.n * 3;
         T* ds = dsrc ? dsrc + (int64_t)b0 * p.n * 3 : nullptr;
 #define LAUNCHG(K, NB, WV)                                                                                \
-        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(items), dim3(thr), qbytes, st, c, p.cell_start,  \
-                           p.x_r, f, (const T*)nullptr, w, p.n, nb, (T)xi, (T)self_coef, p.perm_r, dx, 1, ds,   \
-                           p.work_start)
+        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(items), dim3(thr), qbytes, st, c, p, f,          \
+                           (const T*)nullptr, w, nb, (T)xi, (T)self_coef, dx, 1, ds)
 #define LAUNCHK(K)                                                                                        \
         if (ds) { if (nb == 1) LAUNCHG(K, 1, true); else LAUNCHG(K, 4, true); }                           \
         else { if (nb == 1) LAUNCHG(K, 1, false); else LAUNCHG(K, 4, false); }
@@ -645,7 +734,21 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
     }
 }
 
+template <typename T>
+void launch_real_tadj(const CellGeo& c, const PointsDev<T>& p, const T* q_r, const T* n_r, const T* w_r,
+                      int batch, double xi, T* dq, T* dn, hipStream_t st) {
+    const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
+    const unsigned thr = (unsigned)p.t_real_S;
+    const unsigned items = (unsigned)((p.t_n + thr - 1) / thr + ncells);
+    const size_t qbytes = (size_t)qcap<T, false>() * queue_row((int)thr) * sizeof(unsigned short);
+    // one batch member per workgroup row (six accumulators per member)
+    hipLaunchKernelGGL((k_real<T, KTADJ, 1, false>), dim3(items, batch), dim3(thr), qbytes, st, c, p, q_r, n_r,
+                       w_r, batch, (T)xi, (T)0, dq, 1, dn);
+}
+
 #define INST(T)                                                                                     \
+    template void launch_real_tadj<T>(const CellGeo&, const PointsDev<T>&, const T*, const T*, const T*, \
+                                      int, double, T*, T*, hipStream_t);                            \
     template void launch_real<T>(int, const CellGeo&, const PointsDev<T>&, const T*, const T*, int, \
                                  double, double, T*, int, hipStream_t);                             \
     template void launch_real_grad<T>(int, const CellGeo&, const PointsDev<T>&, const T*, const T*, \

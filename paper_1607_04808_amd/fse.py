@@ -24,7 +24,8 @@ EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set
            "fse_set_points", "fse_eval", "fse_eval_parts", "fse_eval_adjoint", "fse_plan_multiplier",
            "fse_plan_workspace", "fse_plan_grid", "fse_plan_set_timing", "fse_plan_timings",
            "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error",
-           "fse_error_estimates", "fse_choose_params", "fse_bounding_box")
+           "fse_error_estimates", "fse_choose_params", "fse_bounding_box", "fse_set_targets", "fse_eval_targets",
+           "fse_eval_adjoint_stresslet", "fse_freespace_solve")
 NSTAGES = 12
 
 
@@ -37,7 +38,8 @@ class FseError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("xi", ctypes.c_double), ("rc", ctypes.c_double), ("M", ctypes.c_int32),
                 ("P", ctypes.c_int32), ("box_lo", ctypes.c_double * 3), ("L", ctypes.c_double),
-                ("deltaL_rule", ctypes.c_int32), ("Mt", ctypes.c_int32), ("C", ctypes.c_double)]
+                ("deltaL_rule", ctypes.c_int32), ("Mt", ctypes.c_int32), ("C", ctypes.c_double),
+                ("periodic", ctypes.c_int32)]
 
 
 class GeometryC(ctypes.Structure):
@@ -71,6 +73,10 @@ def lib():
             L.fse_eval.argtypes = [vp, vp, vp, vp]
             L.fse_eval_parts.argtypes = [vp, vp, vp, vp, vp]
             L.fse_eval_adjoint.argtypes = [vp, vp, vp, vp, vp, i32]
+            L.fse_eval_adjoint_stresslet.argtypes = [vp, vp, vp, vp, vp, vp]
+            L.fse_freespace_solve.argtypes = [i32, ctypes.c_int, i32, ctypes.c_double, i32, vp, vp, vp]
+            L.fse_set_targets.argtypes = [vp, i64, vp, i32]
+            L.fse_eval_targets.argtypes = [vp, vp, vp, vp, vp]
             L.fse_plan_multiplier.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
             L.fse_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
             L.fse_plan_grid.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
@@ -100,12 +106,13 @@ def _check(status):
         raise FseError(status, lib().fse_last_error().decode())
 
 
-def make_params(xi, rc, M, P, box_lo=(0.0, 0.0, 0.0), L=1.0, deltaL_rule=0, Mt=0, C=0.0) -> Params:
+def make_params(xi, rc, M, P, box_lo=(0.0, 0.0, 0.0), L=1.0, deltaL_rule=0, Mt=0, C=0.0, periodic=0) -> Params:
     p = Params()
     p.xi, p.rc, p.M, p.P = float(xi), float(rc), int(M), int(P)
     for d in range(3):
         p.box_lo[d] = float(box_lo[d])
     p.L, p.deltaL_rule, p.Mt, p.C = float(L), int(deltaL_rule), int(Mt), float(C)
+    p.periodic = int(periodic)
     return p
 
 
@@ -227,6 +234,28 @@ class Plan:
         self.generation += 1
         return out
 
+    def set_targets(self, y, validate=True):
+        """Separate targets (fse_set_targets)."""
+        y = self._prep(y, (y.shape[0], 3))
+        self._sync_stream()
+        self._y = y
+        _check(lib().fse_set_targets(self._h, y.shape[0], _ptr(y), 1 if validate else 0))
+        self.nt = y.shape[0]
+        return self
+
+    def eval_targets(self, a, b=None, parts=False):
+        """u at the targets (fse_eval_targets); parts=True gives (u^R, u^F)."""
+        torch = _torch()
+        a = self._prep(a, self._src_shape())
+        b = None if b is None else self._prep(b, self._src_shape())
+        shape = (self.batch, self.nt, 3)
+        u = torch.empty(shape, dtype=self.tdtype, device=a.device)
+        uF = torch.empty(shape, dtype=self.tdtype, device=a.device) if parts else None
+        self._sync_stream()
+        _check(lib().fse_eval_targets(self._h, _ptr(a), _ptr(b), _ptr(u), _ptr(uF)))
+        self.generation += 1
+        return (u, uF) if parts else u
+
     def eval_parts(self, a, b=None):
         torch = _torch()
         a = self._prep(a, self._src_shape())
@@ -248,6 +277,19 @@ class Plan:
         _check(lib().fse_eval_adjoint(self._h, _ptr(f), _ptr(w), _ptr(df), _ptr(dx), 1 if recompute else 0))
         self.generation += 1
         return df, dx
+
+    def adjoint_stresslet(self, q, nrm, w):
+        """(dL/dq, dL/dn) of L = sum w . u for a stresslet plan (fse_eval_adjoint_stresslet)."""
+        torch = _torch()
+        q = self._prep(q, self._src_shape())
+        nrm = self._prep(nrm, self._src_shape())
+        w = self._prep(w, self._src_shape())
+        dq = torch.empty(self._src_shape(), dtype=self.tdtype, device=q.device)
+        dn = torch.empty_like(dq)
+        self._sync_stream()
+        _check(lib().fse_eval_adjoint_stresslet(self._h, _ptr(q), _ptr(nrm), _ptr(w), _ptr(dq), _ptr(dn)))
+        self.generation += 1
+        return dq, dn
 
     def multiplier(self):
         Mp = self.geometry.Mt + 1
@@ -278,6 +320,22 @@ class Plan:
         b = ctypes.c_size_t()
         _check(lib().fse_plan_workspace(self._h, ctypes.byref(b)))
         return b.value
+
+
+def freespace_solve(f, h, family="harmonic"):
+    """fse_freespace_solve: u = G * f on the grid (G = 1/r harmonic, r biharmonic).
+    f: device tensor (M, M, M) or (ncomp, M, M, M) indexed [z][y][x]; returns u alike."""
+    torch = _torch()
+    dtype = "f32" if f.dtype == torch.float32 else "f64"
+    single = f.dim() == 3
+    g = (f[None] if single else f).contiguous()
+    M = g.shape[-1]
+    if tuple(g.shape[1:]) != (M, M, M):
+        raise ValueError("f must be (M, M, M) or (ncomp, M, M, M)")
+    u = torch.empty_like(g)
+    fam = {"biharmonic": 0, "harmonic": 1}[family]
+    _check(lib().fse_freespace_solve(fam, DTYPES[dtype], M, float(h), g.shape[0], _ptr(g), _ptr(u), _stream_ptr()))
+    return u[0] if single else u
 
 
 def error_estimates(kernel, params: Params, Q):
@@ -338,12 +396,48 @@ def _autograd():
     return FSEFunction
 
 
+def _autograd_stresslet():
+    torch = _torch()
+
+    class FSEStressletFunction(torch.autograd.Function):
+        """u = FSE stresslet sum of (q, n) at x; backward gives dL/dq and dL/dn."""
+
+        @staticmethod
+        def forward(ctx, x, q, nrm, plan: Plan):
+            plan.set_points(x.detach())
+            u = plan.eval(q.detach(), nrm.detach())
+            ctx.plan = plan
+            ctx.gen = plan.generation
+            ctx.save_for_backward(x, q, nrm)
+            return u.reshape(q.shape)
+
+        @staticmethod
+        def backward(ctx, gu):
+            x, q, nrm = ctx.saved_tensors
+            if ctx.needs_input_grad[0]:
+                raise NotImplementedError("dL/dx of the stresslet sum is not implemented")
+            plan = ctx.plan
+            if plan.generation != ctx.gen:
+                plan.set_points(x.detach())
+            dq, dn = plan.adjoint_stresslet(q.detach(), nrm.detach(), gu.detach())
+            return None, dq.reshape(q.shape), dn.reshape(nrm.shape), None
+
+    return FSEStressletFunction
+
+
 _FN = None
+_FNT = None
 
 
-def fse_sum(x, f, plan: Plan):
-    """Differentiable FSE sum (stokeslet or rotlet plan): u(x_m) = sum_{n != m} G(x_m - x_n) f_n."""
-    global _FN
+def fse_sum(x, f, plan: Plan, nrm=None):
+    """Differentiable FSE sum u(x_m) = sum_{n != m} G(x_m - x_n) f_n (stokeslet or
+    rotlet plan: gradients in x and f), or, with the normals nrm, the stresslet sum
+    of (q = f, n) (gradients in q and n)."""
+    global _FN, _FNT
+    if nrm is not None:
+        if _FNT is None:
+            _FNT = _autograd_stresslet()
+        return _FNT.apply(x, f, nrm, plan)
     if _FN is None:
         _FN = _autograd()
     return _FN.apply(x, f, plan)
@@ -352,7 +446,7 @@ def fse_sum(x, f, plan: Plan):
 # ---------------------------------------------------------------------------
 # Tolerance-driven sums: the box is the points' bounding cube, the parameters
 # come from fse_choose_params, and the scale u_rms it needs comes from one coarse
-# evaluation (relative tolerance 1e-2) of the same sum.  Plans are cached by
+# evaluation (relative tolerance 1e-3) of the same sum.  Plans are cached by
 # kernel, dtype, batch, size and parameters.
 # ---------------------------------------------------------------------------
 _PLANS = {}
@@ -388,7 +482,7 @@ def plan_for(kernel, x, a, b=None, tol=1e-6, dtype=None, u_rms=None):
     box_lo, L = bounding_box(x.detach().to(torch.float32 if dtype == "f32" else torch.float64))
     Q = _source_norm(a.detach(), None if b is None else b.detach()) / batch
     if u_rms is None:
-        coarse = _cached_plan(kernel, dtype, choose_params(kernel, dtype, n, box_lo, L, 1e-2, Q), batch, n)
+        coarse = _cached_plan(kernel, dtype, choose_params(kernel, dtype, n, box_lo, L, 1e-3, Q), batch, n)
         coarse.set_points(x.detach())
         uc = coarse.eval(a.detach(), None if b is None else b.detach())
         u_rms = float((uc.double() ** 2).sum(-1).mean().sqrt())
@@ -410,7 +504,7 @@ def rotlet(x, f, tol=1e-6, dtype=None, u_rms=None):
 
 
 def stresslet(x, q, nrm, tol=1e-6, dtype=None, u_rms=None):
-    """u_j(x_m) = sum_{n != m} T_jlm(x_m - x_n) q_l n_m at relative tolerance `tol`."""
+    """u_j(x_m) = sum_{n != m} T_jlm(x_m - x_n) q_l n_m at relative tolerance `tol`
+    (differentiable in q and n)."""
     plan = plan_for("stresslet", x, q, nrm, tol, dtype, u_rms)
-    plan.set_points(x.detach())
-    return plan.eval(q.detach(), nrm.detach()).reshape(q.shape)
+    return fse_sum(x, q, plan, nrm)

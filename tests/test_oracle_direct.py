@@ -121,3 +121,34 @@ def test_coincident_points_rejected():
     f = np.ones((3, 3))
     with pytest.raises(ValueError):
         direct.direct("stokeslet", x, f)
+
+
+def test_stresslet_adjoint_is_the_derivative_of_the_direct_sum():
+    """dL/dq and dL/dn of L = w . u_T(q, n): u is linear in q and in n, so a
+    central difference in any direction is exact up to rounding; brute-force one-hot
+    differences on a tiny system and random directions on a larger one."""
+    rng = np.random.default_rng(77)
+    n = 9
+    x = rng.uniform(size=(n, 3))
+    q, nn, w = (rng.normal(size=(n, 3)) for _ in range(3))
+    dq, dn = direct.stresslet_adjoint(x, q, nn, w)
+    L = lambda qq, nv: float(np.sum(w * direct.direct("stresslet", x, qq, nv)))
+    for b in range(n):
+        for l in range(3):
+            e = np.zeros((n, 3))
+            e[b, l] = 1.0
+            assert abs((L(q + e, nn) - L(q - e, nn)) / 2 - dq[b, l]) < 1e-9 * (1 + abs(dq[b, l]))
+            assert abs((L(q, nn + e) - L(q, nn - e)) / 2 - dn[b, l]) < 1e-9 * (1 + abs(dn[b, l]))
+    n = 300
+    x = rng.uniform(size=(n, 3))
+    q, nn, w = (rng.normal(size=(n, 3)) for _ in range(3))
+    tg = np.array([0, 17, 123, 299])
+    dq, dn = direct.stresslet_adjoint(x, q, nn, w, targets=tg)
+    dqa, dna = direct.stresslet_adjoint(x, q, nn, w)
+    assert np.allclose(dq, dqa[tg], rtol=1e-13, atol=0) and np.allclose(dn, dna[tg], rtol=1e-13, atol=0)
+    for _ in range(3):
+        d = rng.normal(size=(n, 3))
+        gq = (L(q + d, nn) - L(q - d, nn)) / 2
+        gn = (L(q, nn + d) - L(q, nn - d)) / 2
+        assert abs(gq - np.sum(dqa * d)) < 1e-10 * abs(gq)
+        assert abs(gn - np.sum(dna * d)) < 1e-10 * abs(gn)
