@@ -283,6 +283,27 @@ fse_status_t fse_choose_params(fse_kernel_t kernel, fse_dtype_t dtype, int64_t n
 fse_status_t fse_bounding_box(fse_dtype_t dtype, int64_t n, const void *x, void *stream,
                               double box_lo[3], double *L);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): fse_plan_create,
+ * fse_set_points and fse_eval in one call, with every workspace buffer (grids,
+ * spectra, sort buffers, the precompute's temporaries) carved from a static
+ * device array of FSE_NOALLOC_MAX_BYTES that each GPU the library runs on holds
+ * until the process ends.  Calls no hipMalloc/hipFree or other allocating
+ * routine.  Arguments as fse_plan_create (params, batch, stream), fse_set_points
+ * (n points x, validate) and fse_eval (src_a, src_b, u), all device pointers in
+ * the dtype; u is overwritten.  An evaluation whose workspace exceeds the
+ * array returns FSE_EINVAL before any device work (fse_last_error names the
+ * bytes it needs).  Every call on one GPU uses that GPU's one array and leaves
+ * its contents there: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Each call reruns the
+ * FP64 precompute and synchronises `stream` (table upload and precompute).
+ */
+#define FSE_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+fse_status_t fse_eval_noalloc(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t *params,
+                              int32_t batch, int64_t n, const void *x, const void *src_a,
+                              const void *src_b, void *u, int32_t validate, void *stream);
+
 /* Device bytes held by the plan.  Synchronises nothing. */
 fse_status_t fse_plan_workspace(const fse_plan_t *plan, size_t *bytes);
 

@@ -1034,6 +1034,39 @@ template <typename T> fse_status_t freespace_solve_t(fse_plan* p, int ncomp, con
     return FSE_OK;
 }
 
+// Device scratch of the no-allocation entry point: one array per GPU, loaded
+// with the library's code object and held until the process ends.  Host code
+// never uses the array's name as an address: it takes each device's address
+// once from hipGetSymbolAddress and passes that.
+__device__ __align__(256) unsigned char scratch[FSE_NOALLOC_MAX_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of the current device's scratch array (looked up on first use).
+fse_status_t scratch_ptr(void** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) { set_err("device %d beyond the supported %d", dev, MAX_DEVICES); return FSE_EINVAL; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* q = nullptr;
+        HIPCHK(hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)));
+        if (!q) { set_err("hipGetSymbolAddress returned a null scratch address"); return FSE_EHIP; }
+        g_scratch_ptr[dev] = q;
+    }
+    *out = g_scratch_ptr[dev];
+    return FSE_OK;
+}
+
+template <typename T>
+fse_status_t eval_noalloc_t(fse_plan* p, int64_t n, const T* x, const T* a, const T* b, T* u, int validate) {
+    TRY(plan_init<T>(p));
+    TRY(set_points_t<T>(p, n, x, validate));
+    return eval_t<T>(p, a, b, u, nullptr, true);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1213,6 +1246,33 @@ fse_status_t fse_plan_workspace(const fse_plan_t* plan, size_t* bytes) {
     if (!plan || !bytes) { set_err("null argument"); return FSE_EINVAL; }
     *bytes = plan->bytes;
     return FSE_OK;
+}
+
+fse_status_t fse_eval_noalloc(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t* params, int32_t batch,
+                              int64_t n, const void* x, const void* src_a, const void* src_b, void* u,
+                              int32_t validate, void* stream) {
+    if (!x || !src_a || !u) { set_err("null argument"); return FSE_EINVAL; }
+    if (kernel == FSE_STRESSLET && !src_b) { set_err("stresslet needs the normals (src_b)"); return FSE_EINVAL; }
+    fse_geometry_t geo;
+    TRY(check_plan_args(kernel, dtype, params, batch, n, &geo));
+    fse_plan p;  // host object only; every device buffer is carved from the scratch array
+    setup_plan(&p, kernel, dtype, params, geo, batch, n, stream);
+    size_t need = 0;
+    TRY(dtype == FSE_F32 ? plan_bytes<float>(&p, &need) : plan_bytes<double>(&p, &need));
+    if (need > FSE_NOALLOC_MAX_BYTES) {
+        set_err("this evaluation needs %zu bytes of device workspace, above the %zu-byte static scratch of "
+                "fse_eval_noalloc (use a plan)", need, (size_t)FSE_NOALLOC_MAX_BYTES);
+        return FSE_EINVAL;
+    }
+    void* base = nullptr;
+    TRY(scratch_ptr(&base));
+    p.arena = (char*)base;
+    p.arena_cap = FSE_NOALLOC_MAX_BYTES;
+    return dtype == FSE_F32
+               ? eval_noalloc_t<float>(&p, n, (const float*)x, (const float*)src_a, (const float*)src_b, (float*)u,
+                                       validate)
+               : eval_noalloc_t<double>(&p, n, (const double*)x, (const double*)src_a, (const double*)src_b,
+                                        (double*)u, validate);
 }
 
 fse_status_t fse_freespace_solve(int32_t family, fse_dtype_t dtype, int32_t M, double h, int32_t ncomp, const void* f,

@@ -23,9 +23,10 @@ STATUS = {0: "FSE_OK", 1: "FSE_EINVAL", 2: "FSE_ERANGE", 3: "FSE_ENOMEM", 4: "FS
 EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set_stream",
            "fse_set_points", "fse_eval", "fse_eval_parts", "fse_eval_adjoint", "fse_plan_multiplier",
            "fse_plan_workspace", "fse_plan_grid", "fse_plan_set_timing", "fse_plan_timings",
-           "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error",
+           "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error", "fse_eval_noalloc",
            "fse_error_estimates", "fse_choose_params", "fse_bounding_box", "fse_set_targets", "fse_eval_targets",
            "fse_eval_adjoint_stresslet", "fse_freespace_solve")
+NOALLOC_MAX_BYTES = 64 << 20  # FSE_NOALLOC_MAX_BYTES
 NSTAGES = 12
 
 
@@ -84,6 +85,8 @@ def lib():
             L.fse_plan_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
             L.fse_stage_name.argtypes = [i32]
             L.fse_stage_name.restype = ctypes.c_char_p
+            L.fse_eval_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params), i32, i64, vp, vp, vp,
+                                           vp, i32, vp]
             dp = ctypes.POINTER(ctypes.c_double)
             L.fse_error_estimates.argtypes = [ctypes.c_int, ctypes.POINTER(Params), ctypes.c_double, dp, dp]
             L.fse_choose_params.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, ctypes.c_double, ctypes.c_double,
@@ -364,6 +367,23 @@ def bounding_box(x):
     L = ctypes.c_double()
     _check(lib().fse_bounding_box(DTYPES[dtype], x.shape[0], _ptr(x), _stream_ptr(), lo, ctypes.byref(L)))
     return tuple(lo), L.value
+
+
+def eval_noalloc(kernel, dtype, params: Params, x, a, b=None, out=None, batch=1, validate=False):
+    """fse_eval_noalloc: one evaluation with no device allocation inside the library
+    (workspace from its static per-GPU scratch array).  `out` may be preallocated."""
+    torch = _torch()
+    td = torch.float32 if dtype == "f32" else torch.float64
+    n = x.shape[0]
+    shape = (int(batch), n, 3)
+    x = x.to(td).contiguous()
+    a = a.to(td).contiguous().reshape(shape)
+    b = None if b is None else b.to(td).contiguous().reshape(shape)
+    if out is None:
+        out = torch.empty(shape, dtype=td, device=x.device)
+    _check(lib().fse_eval_noalloc(_kid(kernel), DTYPES[dtype], ctypes.byref(params), int(batch), n, _ptr(x),
+                                  _ptr(a), _ptr(b), _ptr(out), 1 if validate else 0, _stream_ptr()))
+    return out
 
 
 def _autograd():
