@@ -335,8 +335,9 @@ def main():
 
     head = results.get("f32") or next(iter(results.values()))
     head_form = "f32" if "f32" in results else forms[0]
-    # dominant kernel and its roofline
-    dom_name, dom = max(head["stages"].items(), key=lambda kv: kv[1]["ms_per_step"])
+    # dominant kernel (of the stages with an algorithmic work figure) and its roofline
+    dom_name, dom = max(((k, v) for k, v in head["stages"].items() if v["GBs"] is not None or v["TFLOPs"] is not None),
+                        key=lambda kv: kv[1]["ms_per_step"])
     peak_alu = PEAK["f32_TFLOPs"] if head_form == "f32" else PEAK["f64_TFLOPs"]
     tr = stage_traffic(head_form, dom_name)
     tr = round(tr) if tr is not None else None
@@ -373,7 +374,8 @@ def main():
 
     if "batched" in results:
         br = results["batched"]
-        bd, bdom = max(br["stages"].items(), key=lambda kv: kv[1]["ms_per_step"])
+        bd, bdom = max(((k, v) for k, v in br["stages"].items() if v["GBs"] is not None or v["TFLOPs"] is not None),
+                       key=lambda kv: kv[1]["ms_per_step"])
         if bdom["TFLOPs"] is not None:
             line["forms"]["batched"]["roofline"] = dict(kernel=bd, bound="mfma" if ("f32", bd) in MFMA_STAGES else "alu",
                                                         achieved=round(bdom["TFLOPs"], 2), peak=PEAK["f32_TFLOPs"],

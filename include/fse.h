@@ -304,6 +304,39 @@ fse_status_t fse_eval_noalloc(fse_kernel_t kernel, fse_dtype_t dtype, const fse_
                               int32_t batch, int64_t n, const void *x, const void *src_a,
                               const void *src_b, void *u, int32_t validate, void *stream);
 
+/*
+ * Launch shapes of a plan (runtime knobs of this implementation, not of the
+ * method): the side of the point bins, in grid nodes, that spreading and the
+ * quadrature work in (tiles); the real-space hit-queue depths per thread of the
+ * value and the gradient pass; the most waves (64 targets each) a real-space
+ * work item takes.  Plans start at the defaults; fse_plan_autotune times the
+ * candidates on the plan's own workload and keeps the fastest.
+ */
+typedef struct {
+    int32_t bin_side;         /* 4..8                                           */
+    int32_t real_queue;       /* 16..96, a multiple of 8                        */
+    int32_t real_queue_grad;  /* 16..96, a multiple of 8                        */
+    int32_t real_waves;       /* 1..4                                           */
+} fse_tuning_t;
+
+fse_status_t fse_plan_get_tuning(const fse_plan_t *plan, fse_tuning_t *out);
+
+/* Apply a tuning (FSE_EINVAL outside the ranges above).  The points and any
+ * targets must be set again afterwards (FSE_ESTATE otherwise). */
+fse_status_t fse_plan_set_tuning(fse_plan_t *plan, const fse_tuning_t *tuning);
+
+/*
+ * Autotune the plan on its workload: for the n points x and sources (src_a,
+ * src_b as fse_eval) and, when w != NULL (stokeslet and rotlet), the adjoint
+ * weights, time `repeats` runs of fse_set_points + fse_eval (+ fse_eval_adjoint)
+ * with HIP events for each candidate of each knob in turn (bin side, real-space
+ * waves, then the two queue depths), keep the fastest, and leave the plan with
+ * it and the points set.  *best (may be NULL) receives the tuning.  Allocates
+ * temporary outputs and synchronises the stream.
+ */
+fse_status_t fse_plan_autotune(fse_plan_t *plan, int64_t n, const void *x, const void *src_a, const void *src_b,
+                               const void *w, int32_t repeats, fse_tuning_t *best);
+
 /* Device bytes held by the plan.  Synchronises nothing. */
 fse_status_t fse_plan_workspace(const fse_plan_t *plan, size_t *bytes);
 

@@ -46,6 +46,7 @@ void set_err(const char* fmt, ...) {
 constexpr double PI = 3.14159265358979323846;
 constexpr int MAX_MT = 540;  // n = 2 Mt <= 1080 keeps every FFT pass within 160 KB of LDS
 constexpr int MAX_CELLS_PER_SIDE = 128;
+constexpr int MIN_BIN_SIDE = 4, MAX_BIN_SIDE = 8;  // the range a tuning may set
 
 bool smooth7(int n) {
     if (n <= 0) return false;
@@ -273,6 +274,8 @@ struct fse_plan {
     void* sort_tmp;
     size_t sort_bytes = 0;
     int bits_s = 1, bits_r = 1;
+    int64_t ntiles_max = 0;  // tiles at the smallest bin side a tuning may set
+    int real_waves = 4;      // tuning: most waves per real-space work item
     void *coff, *coff_s, *x_r;
     int *cnt_s, *start_s, *cnt_r, *start_r, *work_r, *scan_tmp, *flag;
     int real_S = 256;
@@ -392,19 +395,23 @@ template <typename T> fse_status_t allocate(fse_plan* p) {
     TRY(p->alloc((T**)&p->coff_s, 3 * nm));
     TRY(p->alloc((T**)&p->x_r, 3 * nm));
     p->ntiles3 = (int64_t)p->gg.nt * p->gg.nt * p->gg.nt;
+    {
+        const int64_t ntm = (p->gg.Mt + MIN_BIN_SIDE - 1) / MIN_BIN_SIDE;
+        p->ntiles_max = ntm * ntm * ntm;
+    }
     p->ncells3 = (int64_t)p->cg.ncell * p->cg.ncell * p->cg.ncell;
-    TRY(p->alloc(&p->cnt_s, p->ntiles3 + 1));
-    TRY(p->alloc(&p->start_s, p->ntiles3 + 1));
+    TRY(p->alloc(&p->cnt_s, p->ntiles_max + 1));
+    TRY(p->alloc(&p->start_s, p->ntiles_max + 1));
     TRY(p->alloc(&p->cnt_r, p->ncells3 + 1));
     TRY(p->alloc(&p->start_r, p->ncells3 + 1));
     TRY(p->alloc(&p->work_r, p->ncells3 + 1));
-    const size_t st = scan_tmp_ints(p->ntiles3 + 1) > scan_tmp_ints(p->ncells3 + 1)
-                          ? scan_tmp_ints(p->ntiles3 + 1) : scan_tmp_ints(p->ncells3 + 1);
+    const size_t st = scan_tmp_ints(p->ntiles_max + 1) > scan_tmp_ints(p->ncells3 + 1)
+                          ? scan_tmp_ints(p->ntiles_max + 1) : scan_tmp_ints(p->ncells3 + 1);
     TRY(p->alloc(&p->scan_tmp, st));
     p->bits_s = key_bits(p->ntiles3);
     p->bits_r = key_bits(p->ncells3);
     {
-        const size_t b1 = sort_tmp_bytes(nm, p->bits_s), b2 = sort_tmp_bytes(nm, p->bits_r);
+        const size_t b1 = sort_tmp_bytes(nm, key_bits(p->ntiles_max)), b2 = sort_tmp_bytes(nm, p->bits_r);
         if (b1 == 0 || b2 == 0) { set_err("sort workspace query failed"); return FSE_EHIP; }
         p->sort_bytes = b1 > b2 ? b1 : b2;
         TRY(p->alloc((char**)&p->sort_tmp, p->sort_bytes));
@@ -580,7 +587,7 @@ template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T*
         launch_scan_exclusive(p->cnt_s, p->start_s, p->ntiles3 + 1, p->scan_tmp, st);
         launch_scan_exclusive(p->cnt_r, p->start_r, p->ncells3 + 1, p->scan_tmp, st);
         // real-space work items: slices of up to real_S targets of one cell
-        p->real_S = (int)real_threads(n, p->ncells3);
+        p->real_S = (int)real_threads(n, p->ncells3, p->real_waves);
         launch_cell_slices(p->cnt_r, p->ncells3, p->real_S, st);
         launch_scan_exclusive(p->cnt_r, p->work_r, p->ncells3 + 1, p->scan_tmp, st);
         launch_scatter<T>(x, n, p->perm_s, p->perm_r, p->bpack, (const T*)p->coff, p->bpack_s, (T*)p->coff_s,
@@ -632,12 +639,12 @@ template <typename T> fse_status_t reserve_targets(fse_plan* p, int64_t nt) {
     TRY(talloc(p, (T**)&t.coff, 3 * nt));
     TRY(talloc(p, (T**)&t.coff_s, 3 * nt));
     TRY(talloc(p, (T**)&t.x_r, 3 * nt));
-    TRY(talloc(p, &t.cnt_s, p->ntiles3 + 1));
-    TRY(talloc(p, &t.start_s, p->ntiles3 + 1));
+    TRY(talloc(p, &t.cnt_s, p->ntiles_max + 1));
+    TRY(talloc(p, &t.start_s, p->ntiles_max + 1));
     TRY(talloc(p, &t.cnt_r, p->ncells3 + 1));
     TRY(talloc(p, &t.start_r, p->ncells3 + 1));
     TRY(talloc(p, &t.work_r, p->ncells3 + 1));
-    const size_t b1 = sort_tmp_bytes(nt, p->bits_s), b2 = sort_tmp_bytes(nt, p->bits_r);
+    const size_t b1 = sort_tmp_bytes(nt, key_bits(p->ntiles_max)), b2 = sort_tmp_bytes(nt, p->bits_r);
     if (b1 == 0 || b2 == 0) { set_err("sort workspace query failed"); return FSE_EHIP; }
     t.sort_bytes = b1 > b2 ? b1 : b2;
     TRY(talloc(p, (char**)&t.sort_tmp, t.sort_bytes));
@@ -662,7 +669,7 @@ template <typename T> fse_status_t set_targets_t(fse_plan* p, int64_t nt, const 
         HIPCHK(launch_sort_pairs(t.sort_tmp, t.sort_bytes, t.key_r, t.key_tmp, t.idx, t.perm_r, nt, p->bits_r, st));
         launch_scan_exclusive(t.cnt_s, t.start_s, p->ntiles3 + 1, p->scan_tmp, st);
         launch_scan_exclusive(t.cnt_r, t.start_r, p->ncells3 + 1, p->scan_tmp, st);
-        t.real_S = (int)real_threads(nt, p->ncells3);
+        t.real_S = (int)real_threads(nt, p->ncells3, p->real_waves);
         launch_cell_slices(t.cnt_r, p->ncells3, t.real_S, st);
         launch_scan_exclusive(t.cnt_r, t.work_r, p->ncells3 + 1, p->scan_tmp, st);
         launch_scatter<T>(y, nt, t.perm_s, t.perm_r, t.bpack, (const T*)t.coff, t.bpack_s, (T*)t.coff_s,
@@ -968,6 +975,8 @@ void setup_plan(fse_plan* p, fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
     cg.cell = geo.cell;
     cg.rc2 = params->rc * params->rc;
     cg.periodic = params->periodic != 0;
+    cg.qcap = default_qcap(dtype == FSE_F32 ? 4 : 8, false);
+    cg.qcap_grad = default_qcap(dtype == FSE_F32 ? 4 : 8, true);
     FftGeo& fg = p->fg;
     fg.n = geo.n_fft;
     fg.ns = 0;
@@ -1032,6 +1041,116 @@ template <typename T> fse_status_t freespace_solve_t(fse_plan* p, int ncomp, con
     HIPCHK(hipMemcpyAsync(u, p->phi, ncomp * M3 * sizeof(T), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipStreamSynchronize(st));  // the workspace is freed on return
     return FSE_OK;
+}
+
+// Launch-shape tuning (runtime knobs): bin side (tiles of spreading and
+// quadrature), real-space queue depths and waves per work item.
+fse_status_t apply_tuning(fse_plan* p, const fse_tuning_t& t) {
+    if (t.bin_side < MIN_BIN_SIDE || t.bin_side > MAX_BIN_SIDE || t.real_waves < 1 || t.real_waves > 4) {
+        set_err("tuning: bin_side in [%d, %d], real_waves in [1, 4]", MIN_BIN_SIDE, MAX_BIN_SIDE);
+        return FSE_EINVAL;
+    }
+    for (int q : {t.real_queue, t.real_queue_grad})
+        if (q < 16 || q > 96 || q % 8) { set_err("tuning: queue depths in [16, 96], multiples of 8"); return FSE_EINVAL; }
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->gg.TS = t.bin_side;
+    p->gg.nt = (p->gg.Mt + t.bin_side - 1) / t.bin_side;
+    p->ntiles3 = (int64_t)p->gg.nt * p->gg.nt * p->gg.nt;
+    p->bits_s = key_bits(p->ntiles3);
+    p->cg.qcap = t.real_queue;
+    p->cg.qcap_grad = t.real_queue_grad;
+    p->real_waves = t.real_waves;
+    p->n = 0;  // the points' bins and work items follow the tuning: set them again
+    p->forward_valid = false;
+    p->free_targets();
+    return FSE_OK;
+}
+
+fse_tuning_t current_tuning(const fse_plan* p) {
+    fse_tuning_t t;
+    t.bin_side = p->gg.TS;
+    t.real_queue = p->cg.qcap;
+    t.real_queue_grad = p->cg.qcap_grad;
+    t.real_waves = p->real_waves;
+    return t;
+}
+
+// One timed workload run (set_points + eval [+ adjoint]), in milliseconds.
+template <typename T>
+fse_status_t time_workload(fse_plan* p, int64_t n, const T* x, const T* a, const T* b, const T* w, T* u, T* ds,
+                           T* dx, int repeats, float* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    fse_status_t rc = FSE_OK;
+    for (int r = -1; r < repeats && rc == FSE_OK; ++r) {  // r = -1: warm-up
+        if (r == 0) (void)hipEventRecord(e0, p->stream);
+        rc = set_points_t<T>(p, n, x, 0);
+        if (rc == FSE_OK) rc = eval_t<T>(p, a, b, u, nullptr, true);
+        if (rc == FSE_OK && w) rc = adjoint_t<T>(p, a, w, ds, dx, 0);
+    }
+    if (rc == FSE_OK) {
+        (void)hipEventRecord(e1, p->stream);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess) rc = FSE_EHIP;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+template <typename T>
+fse_status_t autotune_t(fse_plan* p, int64_t n, const T* x, const T* a, const T* b, const T* w, int repeats,
+                        fse_tuning_t* best_out) {
+    const int64_t vec = (int64_t)p->batch * n * 3;
+    T *u = nullptr, *ds = nullptr, *dx = nullptr;
+    auto release = [&]() {
+        if (u) (void)hipFree(u);
+        if (ds) (void)hipFree(ds);
+        if (dx) (void)hipFree(dx);
+    };
+    if (hipMalloc(&u, vec * sizeof(T)) != hipSuccess ||
+        (w && (hipMalloc(&ds, vec * sizeof(T)) != hipSuccess || hipMalloc(&dx, n * 3 * sizeof(T)) != hipSuccess))) {
+        release();
+        set_err("autotune: out of device memory");
+        return FSE_ENOMEM;
+    }
+    fse_tuning_t best = current_tuning(p);
+    float best_ms = 0.f;
+    fse_status_t rc = apply_tuning(p, best);
+    if (rc == FSE_OK) rc = time_workload<T>(p, n, x, a, b, w, u, ds, dx, repeats, &best_ms);
+    const bool f32 = sizeof(T) == 4;
+    // each knob in turn, the others held at the best so far
+    for (int knob = 0; knob < 4 && rc == FSE_OK; ++knob) {
+        std::vector<int> cand;
+        if (knob == 0) cand = {5, 6, 7, 8};
+        else if (knob == 1) cand = {1, 2, 3, 4};
+        else if (knob == 2) cand = f32 ? std::vector<int>{24, 32, 48} : std::vector<int>{32, 48, 64};
+        else cand = {32, 48, 64};
+        for (int v : cand) {
+            fse_tuning_t t = best;
+            int* field = knob == 0 ? &t.bin_side : knob == 1 ? &t.real_waves : knob == 2 ? &t.real_queue
+                                                                                          : &t.real_queue_grad;
+            if (*field == v) continue;
+            *field = v;
+            float ms = 0.f;
+            rc = apply_tuning(p, t);
+            if (rc == FSE_OK) rc = time_workload<T>(p, n, x, a, b, w, u, ds, dx, repeats, &ms);
+            if (rc != FSE_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+    }
+    if (rc == FSE_OK) rc = apply_tuning(p, best);
+    if (rc == FSE_OK) rc = set_points_t<T>(p, n, x, 0);
+    if (rc == FSE_OK) {
+        hipError_t e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) { set_err("autotune: %s", hipGetErrorString(e)); rc = FSE_EHIP; }
+    }
+    release();
+    if (rc == FSE_OK && best_out) *best_out = best;
+    return rc;
 }
 
 // Device scratch of the no-allocation entry point: one array per GPU, loaded
@@ -1240,6 +1359,34 @@ fse_status_t fse_plan_timings(fse_plan_t* plan, double* ms, int64_t* launches) {
 
 const char* fse_stage_name(int32_t stage) {
     return (stage >= 0 && stage < FSE_NSTAGES) ? STAGE_NAMES[stage] : "unknown";
+}
+
+fse_status_t fse_plan_get_tuning(const fse_plan_t* plan, fse_tuning_t* out) {
+    if (!plan || !out) { set_err("null argument"); return FSE_EINVAL; }
+    *out = current_tuning(plan);
+    return FSE_OK;
+}
+
+fse_status_t fse_plan_set_tuning(fse_plan_t* plan, const fse_tuning_t* t) {
+    if (!plan || !t) { set_err("null argument"); return FSE_EINVAL; }
+    return apply_tuning(plan, *t);
+}
+
+fse_status_t fse_plan_autotune(fse_plan_t* plan, int64_t n, const void* x, const void* a, const void* b,
+                               const void* w, int32_t repeats, fse_tuning_t* best) {
+    if (!plan || !x || !a) { set_err("null argument"); return FSE_EINVAL; }
+    if (n < 2 || n > plan->nmax) { set_err("n=%lld outside [2, nmax]", (long long)n); return FSE_EINVAL; }
+    if (plan->kernel == FSE_STRESSLET && !b) { set_err("stresslet needs the normals (src_b)"); return FSE_EINVAL; }
+    if (w && (plan->kernel == FSE_STRESSLET || plan->periodic)) {
+        set_err("autotune: the adjoint is timed for free-space stokeslet and rotlet plans only");
+        return FSE_EINVAL;
+    }
+    if (repeats < 1) repeats = 1;
+    return plan->dtype == FSE_F32
+               ? autotune_t<float>(plan, n, (const float*)x, (const float*)a, (const float*)b, (const float*)w,
+                                   repeats, best)
+               : autotune_t<double>(plan, n, (const double*)x, (const double*)a, (const double*)b, (const double*)w,
+                                    repeats, best);
 }
 
 fse_status_t fse_plan_workspace(const fse_plan_t* plan, size_t* bytes) {

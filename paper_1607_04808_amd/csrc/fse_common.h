@@ -124,6 +124,8 @@ struct CellGeo {
     double cell;     // cell side (>= rc)
     double rc2;      // rc^2
     int periodic;    // 1: the cells wrap with period L (triply periodic sums)
+    int qcap;        // real-space hit-queue entries per thread: value pass
+    int qcap_grad;   // and gradient pass (>= 16; tuned per plan)
 };
 
 constexpr int MAX_RADICES = 12;
@@ -182,7 +184,9 @@ void launch_scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStre
 // cnt[c] <- ceil(cnt[c] / S) for c < ncells, cnt[ncells] <- 0
 void launch_cell_slices(int* cnt, int64_t ncells, int S, hipStream_t st);
 // threads (= targets) per real-space work item for n points in ncells cells
-unsigned real_threads(int64_t n, int64_t ncells);
+// (at most max_waves waves, 1..4)
+int default_qcap(int elem_bytes, bool grad);
+unsigned real_threads(int64_t n, int64_t ncells, int max_waves = 4);
 size_t scan_tmp_ints(int64_t n);
 
 // window starts/offsets, tile and cell keys, per-key counts (cnt_s, cnt_r

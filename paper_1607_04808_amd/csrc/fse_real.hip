@@ -115,6 +115,7 @@ __device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, flo
 #endif
 template <typename T, bool GRAD>
 constexpr int qcap() { return sizeof(T) == 4 ? (GRAD ? FSE_QCAP32G : FSE_QCAP32) : 48; }
+
 // 1 when the sign bit of v is set (v < 0 or v = -0), else 0
 __device__ __forceinline__ unsigned sign_bit(float v) { return __float_as_uint(v) >> 31; }
 __device__ __forceinline__ unsigned sign_bit(double v) {
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
         const int QROW = queue_row(nthr);
         const int qsh = QROW == 64 ? 7 : QROW == 128 ? 8 : 9;  // log2 of a row in bytes
         unsigned short* const q0 = qd + tid;
-        unsigned short* const qlim = q0 + (qcap<T, GRAD>() - 8) * QROW;
+        unsigned short* const qlim = q0 + ((GRAD ? cg.qcap_grad : cg.qcap) - 8) * QROW;
         unsigned short* qp = q0;
         // widened test threshold folded into the target term: a hit is a negative sign
         const T Atc = At - rc2t;
@@ -675,10 +676,15 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
 // Threads per work item (= targets per slice of a cell): the whole waves that
 // hold a cell of mean occupancy, at most 256; fuller cells are cut into several
 // work items, so no wave of a workgroup sits idle for the typical cell.
-unsigned real_threads(int64_t n, int64_t ncells) {
+// the plan's queue depths start at these defaults and may be tuned (fse_plan_autotune)
+int default_qcap(int elem_bytes, bool grad) {
+    return elem_bytes == 4 ? (grad ? qcap<float, true>() : qcap<float, false>()) : qcap<double, false>();
+}
+
+unsigned real_threads(int64_t n, int64_t ncells, int max_waves) {
     const double mean = (double)n / (double)ncells;
     const int waves = (int)std::ceil(mean / 64.0);
-    return 64u * (unsigned)std::min(4, std::max(1, waves));
+    return 64u * (unsigned)std::min(std::max(1, std::min(4, max_waves)), std::max(1, waves));
 }
 
 template <typename T>
@@ -690,7 +696,7 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned thr = (unsigned)p.t_real_S;
     // at most ceil(nt / S) + ncells work items; the surplus workgroups return at once
     const unsigned items = (unsigned)((p.t_n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)qcap<T, false>() * queue_row((int)thr) * sizeof(unsigned short);
+    const size_t qbytes = (size_t)c.qcap * queue_row((int)thr) * sizeof(unsigned short);
     dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
     hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p, src_a_r, src_b_r,        \
@@ -711,7 +717,7 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.real_S;
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)qcap<T, true>() * queue_row((int)thr) * sizeof(unsigned short);
+    const size_t qbytes = (size_t)c.qcap_grad * queue_row((int)thr) * sizeof(unsigned short);
     // batch members in groups of 4 per pass; each pass adds to dx (and dsrc)
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
@@ -740,7 +746,7 @@ void launch_real_tadj(const CellGeo& c, const PointsDev<T>& p, const T* q_r, con
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.t_real_S;
     const unsigned items = (unsigned)((p.t_n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)qcap<T, false>() * queue_row((int)thr) * sizeof(unsigned short);
+    const size_t qbytes = (size_t)c.qcap * queue_row((int)thr) * sizeof(unsigned short);
     // one batch member per workgroup row (six accumulators per member)
     hipLaunchKernelGGL((k_real<T, KTADJ, 1, false>), dim3(items, batch), dim3(thr), qbytes, st, c, p, q_r, n_r,
                        w_r, batch, (T)xi, (T)0, dq, 1, dn);

@@ -25,7 +25,8 @@ EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set
            "fse_plan_workspace", "fse_plan_grid", "fse_plan_set_timing", "fse_plan_timings",
            "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error", "fse_eval_noalloc",
            "fse_error_estimates", "fse_choose_params", "fse_bounding_box", "fse_set_targets", "fse_eval_targets",
-           "fse_eval_adjoint_stresslet", "fse_freespace_solve")
+           "fse_eval_adjoint_stresslet", "fse_freespace_solve",
+           "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_plan_autotune")
 NOALLOC_MAX_BYTES = 64 << 20  # FSE_NOALLOC_MAX_BYTES
 NSTAGES = 12
 
@@ -41,6 +42,14 @@ class Params(ctypes.Structure):
                 ("P", ctypes.c_int32), ("box_lo", ctypes.c_double * 3), ("L", ctypes.c_double),
                 ("deltaL_rule", ctypes.c_int32), ("Mt", ctypes.c_int32), ("C", ctypes.c_double),
                 ("periodic", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("bin_side", ctypes.c_int32), ("real_queue", ctypes.c_int32), ("real_queue_grad", ctypes.c_int32),
+                ("real_waves", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class GeometryC(ctypes.Structure):
@@ -75,6 +84,9 @@ def lib():
             L.fse_eval_parts.argtypes = [vp, vp, vp, vp, vp]
             L.fse_eval_adjoint.argtypes = [vp, vp, vp, vp, vp, i32]
             L.fse_eval_adjoint_stresslet.argtypes = [vp, vp, vp, vp, vp, vp]
+            L.fse_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+            L.fse_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+            L.fse_plan_autotune.argtypes = [vp, i64, vp, vp, vp, vp, i32, ctypes.POINTER(Tuning)]
             L.fse_freespace_solve.argtypes = [i32, ctypes.c_int, i32, ctypes.c_double, i32, vp, vp, vp]
             L.fse_set_targets.argtypes = [vp, i64, vp, i32]
             L.fse_eval_targets.argtypes = [vp, vp, vp, vp, vp]
@@ -172,7 +184,7 @@ def _ptr(t):
 class Plan:
     """An FSE plan on the current HIP device (see fse_plan_create)."""
 
-    def __init__(self, kernel, dtype, params: Params, batch=1, nmax=2):
+    def __init__(self, kernel, dtype, params: Params, batch=1, nmax=2, tuned=True):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("libfse needs a HIP device")
@@ -190,6 +202,10 @@ class Plan:
         self.geometry = Geometry.from_c(g)
         self.n = 0
         self.generation = 0
+        if tuned:
+            t = tuning_for(self.kernel, dtype, self.batch, params.P, self.geometry.Mt, self.nmax)
+            if t is not None:
+                self.set_tuning(t)
 
     def close(self):
         if self._h:
@@ -319,6 +335,33 @@ class Plan:
         _check(lib().fse_plan_timings(self._h, ms, cnt))
         return {lib().fse_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(NSTAGES)}
 
+    def tuning(self):
+        t = Tuning()
+        _check(lib().fse_plan_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, t):
+        """Apply a tuning dict (fse_plan_set_tuning); points must be set again."""
+        tt = Tuning(**{k: int(t[k]) for k, _ in Tuning._fields_})
+        _check(lib().fse_plan_set_tuning(self._h, ctypes.byref(tt)))
+        self.generation += 1
+
+    def autotune(self, x, a, b=None, w=None, repeats=3):
+        """fse_plan_autotune on this workload; leaves the points set; returns the tuning."""
+        x = self._prep(x, (x.shape[0], 3))
+        n = x.shape[0]
+        self.n = n
+        a = self._prep(a, self._src_shape())
+        b = None if b is None else self._prep(b, self._src_shape())
+        w = None if w is None else self._prep(w, self._src_shape())
+        self._sync_stream()
+        t = Tuning()
+        _check(lib().fse_plan_autotune(self._h, n, _ptr(x), _ptr(a), _ptr(b), _ptr(w), int(repeats),
+                                       ctypes.byref(t)))
+        self._x = x
+        self.generation += 1
+        return t.as_dict()
+
     def workspace_bytes(self):
         b = ctypes.c_size_t()
         _check(lib().fse_plan_workspace(self._h, ctypes.byref(b)))
@@ -384,6 +427,33 @@ def eval_noalloc(kernel, dtype, params: Params, x, a, b=None, out=None, batch=1,
     _check(lib().fse_eval_noalloc(_kid(kernel), DTYPES[dtype], ctypes.byref(params), int(batch), n, _ptr(x),
                                   _ptr(a), _ptr(b), _ptr(out), 1 if validate else 0, _stream_ptr()))
     return out
+
+
+TUNING_PATH = os.path.join(_HERE, "tuning.json")
+_TUNING = None
+
+
+def tuning_for(kernel, dtype, batch, P, Mt, n):
+    """The autotuner's entry for the closest recorded workload (same kernel, dtype,
+    batch and P; grid size and point count within a factor of 2), or None."""
+    global _TUNING
+    if _TUNING is None:
+        try:
+            import json
+            with open(TUNING_PATH) as fh:
+                _TUNING = json.load(fh).get("entries", [])
+        except (OSError, ValueError):
+            _TUNING = []
+    import math
+    best, dist = None, None
+    for e in _TUNING:
+        if (e["kernel"], e["dtype"], e["batch"], e["P"]) != (kernel, dtype, batch, P):
+            continue
+        d = abs(math.log(e["Mt"] / Mt)) + abs(math.log(e["n"] / max(n, 2)))
+        if abs(math.log(e["Mt"] / Mt)) <= math.log(2) and abs(math.log(e["n"] / max(n, 2))) <= math.log(2) \
+                and (dist is None or d < dist):
+            best, dist = e["tuning"], d
+    return best
 
 
 def _autograd():

@@ -175,3 +175,36 @@ def test_fp32_adjoint_matches_oracle(kernel):
     ef = relmax(df.cpu().numpy()[0], se.evaluate(kernel, x64, w64, g=g)["u"])
     print(kernel, "FP32 dL/dx %.2e dL/df %.2e" % (ex, ef))
     assert ex < 2e-6 and ef < 2e-6
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tuning_changes_shapes_not_results(dtype):
+    """Every bin side, queue depth and wave count gives the same sums (FP64 to
+    rounding; FP32 within its rounding), and autotune leaves a working plan."""
+    n = 4000
+    prm = F.make_params(9.0, 0.35, 22, 12, L=1.0)
+    x, f, w = W.uniform_cube(n, 390), W.normal_strengths(n, 391), W.normal_strengths(n, 392)
+    plan = F.Plan("stokeslet", dtype, prm, nmax=n, tuned=False)
+    try:
+        xt, ft, wt = _t(x, dtype), _t(f, dtype), _t(w, dtype)
+        plan.set_points(xt)
+        u0 = plan.eval(ft).double().cpu().numpy()
+        d0 = plan.adjoint(ft, wt)[1].double().cpu().numpy()
+        tol = 1e-12 if dtype == "f64" else 2e-6
+        for t in ({"bin_side": 5, "real_queue": 24, "real_queue_grad": 32, "real_waves": 1},
+                  {"bin_side": 8, "real_queue": 64, "real_queue_grad": 64, "real_waves": 2},
+                  {"bin_side": 6, "real_queue": 48, "real_queue_grad": 48, "real_waves": 4}):
+            plan.set_tuning(t)
+            with pytest.raises(F.FseError):
+                plan.eval(ft)  # the points must be set again
+            plan.set_points(xt)
+            assert plan.tuning() == t
+            assert relmax(plan.eval(ft).double().cpu().numpy(), u0) < tol
+            assert relmax(plan.adjoint(ft, wt)[1].double().cpu().numpy(), d0) < tol
+        best = plan.autotune(xt, ft, None, wt, repeats=1)
+        assert plan.tuning() == best
+        assert relmax(plan.eval(ft).double().cpu().numpy(), u0) < tol
+        with pytest.raises(F.FseError):
+            plan.set_tuning(dict(best, bin_side=3))
+    finally:
+        plan.close()
