@@ -233,7 +233,7 @@ const char *fse_stage_name(int32_t stage);
  * of spacing h (nodes j h, j = 0..M-1, and f negligible at the faces) and u
  * returned at the same nodes.  Spectrally accurate for smooth f (Table 1's
  * closed forms, e.g. H * gamma_E = erf(xi r)/r).  f, u: ncomp device fields of
- * M^3 in the dtype, x fastest; 2M must factor into 2,3,5,7 (M <= 540).
+ * M^3 in the dtype, x fastest; 2M must factor into 2,3,5,7 (M <= 1024).
  * Allocates its workspace, runs on `stream` and synchronises it.
  */
 fse_status_t fse_freespace_solve(int32_t family, fse_dtype_t dtype, int32_t M, double h, int32_t ncomp,
@@ -309,14 +309,19 @@ fse_status_t fse_eval_noalloc(fse_kernel_t kernel, fse_dtype_t dtype, const fse_
  * method): the side of the point bins, in grid nodes, that spreading and the
  * quadrature work in (tiles); the real-space hit-queue depths per thread of the
  * value and the gradient pass; the most waves (64 targets each) a real-space
- * work item takes.  Plans start at the defaults; fse_plan_autotune times the
- * candidates on the plan's own workload and keeps the fastest.
+ * work item takes; the most FFT lines (rows) one workgroup transforms.  Plans
+ * start at the defaults; fse_plan_autotune times the candidates on the plan's
+ * own workload and keeps the fastest.  No knob changes the sums' arithmetic.
  */
 typedef struct {
     int32_t bin_side;         /* 4..8                                           */
     int32_t real_queue;       /* 16..96, a multiple of 8                        */
     int32_t real_queue_grad;  /* 16..96, a multiple of 8                        */
     int32_t real_waves;       /* 1..4                                           */
+    int32_t fft_lines;        /* 0: each pass's default (16 or 8 FP32, 4 or 2   */
+                              /* FP64, fewer where the lines exceed LDS);       */
+                              /* 1, 2, 4, 8 or 16: at most that many per        */
+                              /* workgroup, and the z-pass one column at a time */
 } fse_tuning_t;
 
 fse_status_t fse_plan_get_tuning(const fse_plan_t *plan, fse_tuning_t *out);

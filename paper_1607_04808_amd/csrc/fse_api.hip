@@ -44,7 +44,10 @@ void set_err(const char* fmt, ...) {
     } while (0)
 
 constexpr double PI = 3.14159265358979323846;
-constexpr int MAX_MT = 540;  // n = 2 Mt <= 1080 keeps every FFT pass within 160 KB of LDS
+// Mt <= 1024: window starts are packed in 10 bits per direction, and n = 2 Mt <= 2048
+// keeps one line set of every FFT pass within 160 KB of LDS (fft_fits checks the
+// six-component stresslet z-pass, whose FP64 lines stop at n = 1364)
+constexpr int MAX_MT = 1024;
 constexpr int MAX_CELLS_PER_SIDE = 128;
 constexpr int MIN_BIN_SIDE = 4, MAX_BIN_SIDE = 8;  // the range a tuning may set
 
@@ -115,7 +118,11 @@ fse_status_t compute_geometry(fse_kernel_t kernel, const fse_params_t* p, fse_ge
         if (!(p->rc <= 0.5 * p->L)) { set_err("periodic: rc must be <= L/2"); return FSE_EINVAL; }
         if (p->P > p->M) { set_err("periodic: P must be <= M"); return FSE_EINVAL; }
         if (!smooth7(2 * p->M)) { set_err("periodic: 2*M=%d does not factor into 2,3,5,7", 2 * p->M); return FSE_EINVAL; }
-        if (p->M > MAX_MT) { set_err("grid size M=%d above the supported %d", p->M, MAX_MT); return FSE_EINVAL; }
+        // the extended grid's last window start is M - 1 (even P) or M (odd P)
+        if (p->M + (p->P & 1) > MAX_MT) {
+            set_err("grid size M=%d above the supported %d (%d for odd P)", p->M, MAX_MT, MAX_MT - 1);
+            return FSE_EINVAL;
+        }
         const double h = p->L / p->M, d = h * p->P, m = C * sqrt(PI * p->P);
         g->Mt = p->M;
         g->n_fft = 2 * p->M;
@@ -931,6 +938,12 @@ fse_status_t check_plan_args(fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
         set_err("eta = %.3f >= 1: the FP32 form needs eta < 1 (smaller xi h P, or larger M)", geo->eta);
         return FSE_EINVAL;
     }
+    if (!fft_fits((int)kernel, dtype == FSE_F32 ? 4 : 8, geo->Mt)) {
+        set_err("Mt=%d: the %s %s transforms of length %d do not fit in LDS (largest Mt for this kernel and dtype: "
+                "%d)", geo->Mt, kernel == FSE_STRESSLET ? "six-component" : "three-component",
+                dtype == FSE_F32 ? "FP32" : "FP64", 2 * geo->Mt, fft_max_mt((int)kernel, dtype == FSE_F32 ? 4 : 8));
+        return FSE_EINVAL;
+    }
     return FSE_OK;
 }
 
@@ -980,6 +993,7 @@ void setup_plan(fse_plan* p, fse_kernel_t kernel, fse_dtype_t dtype, const fse_p
     FftGeo& fg = p->fg;
     fg.n = geo.n_fft;
     fg.ns = 0;
+    fg.lines_cap = 0;
     int L = fg.n;
     for (int s = 0; s < 8 && geo.radices[s]; ++s) {
         fg.rad[s] = geo.radices[s];
@@ -1052,6 +1066,10 @@ fse_status_t apply_tuning(fse_plan* p, const fse_tuning_t& t) {
     }
     for (int q : {t.real_queue, t.real_queue_grad})
         if (q < 16 || q > 96 || q % 8) { set_err("tuning: queue depths in [16, 96], multiples of 8"); return FSE_EINVAL; }
+    if (t.fft_lines < 0 || t.fft_lines > 16 || (t.fft_lines & (t.fft_lines - 1))) {
+        set_err("tuning: fft_lines 0 (default) or 1, 2, 4, 8, 16");
+        return FSE_EINVAL;
+    }
     HIPCHK(hipStreamSynchronize(p->stream));
     p->gg.TS = t.bin_side;
     p->gg.nt = (p->gg.Mt + t.bin_side - 1) / t.bin_side;
@@ -1060,6 +1078,7 @@ fse_status_t apply_tuning(fse_plan* p, const fse_tuning_t& t) {
     p->cg.qcap = t.real_queue;
     p->cg.qcap_grad = t.real_queue_grad;
     p->real_waves = t.real_waves;
+    p->fg.lines_cap = t.fft_lines;
     p->n = 0;  // the points' bins and work items follow the tuning: set them again
     p->forward_valid = false;
     p->free_targets();
@@ -1072,6 +1091,7 @@ fse_tuning_t current_tuning(const fse_plan* p) {
     t.real_queue = p->cg.qcap;
     t.real_queue_grad = p->cg.qcap_grad;
     t.real_waves = p->real_waves;
+    t.fft_lines = p->fg.lines_cap;
     return t;
 }
 
@@ -1120,16 +1140,17 @@ fse_status_t autotune_t(fse_plan* p, int64_t n, const T* x, const T* a, const T*
     if (rc == FSE_OK) rc = time_workload<T>(p, n, x, a, b, w, u, ds, dx, repeats, &best_ms);
     const bool f32 = sizeof(T) == 4;
     // each knob in turn, the others held at the best so far
-    for (int knob = 0; knob < 4 && rc == FSE_OK; ++knob) {
+    for (int knob = 0; knob < 5 && rc == FSE_OK; ++knob) {
         std::vector<int> cand;
         if (knob == 0) cand = {5, 6, 7, 8};
         else if (knob == 1) cand = {1, 2, 3, 4};
         else if (knob == 2) cand = f32 ? std::vector<int>{24, 32, 48} : std::vector<int>{32, 48, 64};
-        else cand = {32, 48, 64};
+        else if (knob == 3) cand = {32, 48, 64};
+        else cand = f32 ? std::vector<int>{0, 8, 4} : std::vector<int>{0, 2, 1};
         for (int v : cand) {
             fse_tuning_t t = best;
             int* field = knob == 0 ? &t.bin_side : knob == 1 ? &t.real_waves : knob == 2 ? &t.real_queue
-                                                                                          : &t.real_queue_grad;
+                                                   : knob == 3 ? &t.real_queue_grad : &t.fft_lines;
             if (*field == v) continue;
             *field = v;
             float ms = 0.f;

@@ -137,6 +137,7 @@ struct FftGeo {
     int pair[MAX_RADICES];    // 1: stages s and s+1 run as one register-resident pass
     int sy, sz;               // padded line strides (elements) of the y- and z-lines of the
                               // intermediate spectra, multiples of 128 bytes
+    int lines_cap;            // 0, or the most lines (rows) per workgroup of a pass (tuning)
 };
 
 // Stage pairs that run fused (both radices' butterflies of one element group
@@ -241,6 +242,11 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
 template <typename T>
 void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f, const T* phi_w,
                         const T* f_s, const T* w_s, int batch, T* dsrc, T* dx, hipStream_t st);
+
+// Grid sides the FFT passes take: whether every pass fits in LDS at Mt, and the
+// largest Mt <= 1024 that does for a kernel (FSE_STRESSLET: six grid components)
+bool fft_fits(int kernel, int elem_bytes, int Mt);
+int fft_max_mt(int kernel, int elem_bytes);
 
 template <typename T>
 void launch_fft_forward(const FftGeo& fg, const GridGeo& g, const T* grid, void* A, void* B,

@@ -800,7 +800,80 @@ template <typename K> void set_lds(K kern, size_t bytes) {
     done.emplace_back((const void*)kern, bytes);
 }
 
+// LDS of each pass (bytes) for `lines` complex lines of length n: the twiddle
+// table, the lines and the digit-reversal table (the z-pass adds its sigma rows,
+// the x-inverse pass its ROWS half spectra).
+constexpr size_t LDS_BYTES = 160 * 1024;
+template <typename T> size_t lds_lines(int n, int lines) {
+    return sizeof(C2<T>) * (size_t)n * (size_t)(1 + lines) + sizeof(int) * (size_t)n;
+}
+template <typename T> size_t lds_xinv(int n, int Mt, int rows) {
+    return sizeof(C2<T>) * ((size_t)n * (size_t)(1 + rows / 2) + (size_t)rows * (Mt + 1)) + sizeof(int) * (size_t)n;
+}
+template <typename T> size_t lds_z(int n, int Mt, int lines, int sigrows) {
+    return lds_lines<T>(n, lines) + 16 + sizeof(T) * (size_t)sigrows * (Mt + 1);
+}
+// The largest count, halving from dflt down to lo, that is at most cap (when
+// cap > 0) and whose LDS fits (lo when none does: fft_fits has ruled that out).
+template <typename F> int fit_count(int dflt, int lo, int cap, F need) {
+    for (int c = dflt; c > lo; c /= 2)
+        if ((cap <= 0 || c <= cap) && need(c) <= LDS_BYTES) return c;
+    return lo;
+}
+
+template <typename T, int R>
+void launch_x(const FftGeo& fg, int Mt, const T* grid, C2<T>* A, int ncomp, const C2<T>* tw, const int* revinv,
+              hipStream_t st) {
+    const size_t sh = lds_lines<T>(fg.n, R / 2);
+    set_lds(k_fft_x<T, R>, sh);
+    hipLaunchKernelGGL((k_fft_x<T, R>), dim3((Mt + R - 1) / R, Mt, ncomp), dim3(256), sh, st, fg, Mt, grid, A, tw,
+                       revinv);
+}
+template <typename T, int LZ>
+void launch_y(const FftGeo& fg, int Mt, const C2<T>* A, C2<T>* B, int ncomp, const C2<T>* tw, const int* revinv,
+              hipStream_t st) {
+    const size_t sh = lds_lines<T>(fg.n, LZ);
+    set_lds(k_fft_y<T, LZ>, sh);
+    hipLaunchKernelGGL((k_fft_y<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, ncomp), dim3(256), sh, st, fg, Mt, A, B,
+                       tw, revinv);
+}
+template <typename T, int LZ>
+void launch_yinv(const FftGeo& fg, int Mt, int c_in, int batch, const C2<T>* B, C2<T>* A, const C2<T>* tw,
+                 const int* revinv, hipStream_t st) {
+    const size_t sh = lds_lines<T>(fg.n, LZ);
+    set_lds(k_fft_yinv<T, LZ>, sh);
+    hipLaunchKernelGGL((k_fft_yinv<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, 3 * batch), dim3(256), sh, st, fg, Mt,
+                       c_in, B, A, tw, revinv);
+}
+template <typename T, int R>
+void launch_xinv(const FftGeo& fg, int Mt, int c_in, int batch, const C2<T>* A, T* field, const C2<T>* tw,
+                 const int* revinv, hipStream_t st) {
+    const size_t sh = lds_xinv<T>(fg.n, Mt, R);
+    set_lds(k_fft_xinv<T, R>, sh);
+    hipLaunchKernelGGL((k_fft_xinv<T, R>), dim3((Mt + R - 1) / R, Mt, 3 * batch), dim3(256), sh, st, fg, Mt, c_in,
+                       A, field, tw, revinv);
+}
+
 }  // namespace
+
+// Whether every pass of the transforms fits in LDS at grid side Mt (n = 2 Mt),
+// with its smallest line count; the launchers below take the largest count that fits.
+bool fft_fits(int kernel, int elem_bytes, int Mt) {
+    const int n = 2 * Mt;
+    const int cin = kernel == FSE_STRESSLET ? 6 : 3;
+    auto ok = [&](auto tag) {
+        using T = decltype(tag);
+        return lds_lines<T>(n, 1) <= LDS_BYTES && lds_xinv<T>(n, Mt, 2) <= LDS_BYTES &&
+               lds_z<T>(n, Mt, cin, 1) <= LDS_BYTES;
+    };
+    return elem_bytes == 4 ? ok(0.0f) : ok(0.0);
+}
+
+int fft_max_mt(int kernel, int elem_bytes) {
+    int Mt = 1024;
+    while (Mt > 1 && !fft_fits(kernel, elem_bytes, Mt)) --Mt;
+    return Mt;
+}
 
 template <typename T>
 void launch_fft_forward(const FftGeo& fg, const GridGeo& g, const T* grid, void* Av, void* Bv, int ncomp,
@@ -808,20 +881,27 @@ void launch_fft_forward(const FftGeo& fg, const GridGeo& g, const T* grid, void*
     using V = C2<T>;
     (void)rev;
     const int Mt = g.Mt, n = fg.n;
-    constexpr int R = xrows<T>(), LZ = ylines<T>();
     V* A = (V*)Av;
     V* B = (V*)Bv;
+    const V* twv = (const V*)tw;
     if (passes & 1) {
-        size_t shx = sizeof(V) * (size_t)n * (1 + R / 2) + sizeof(int) * n;
-        set_lds(k_fft_x<T, R>, shx);
-        hipLaunchKernelGGL((k_fft_x<T, R>), dim3((Mt + R - 1) / R, Mt, ncomp), dim3(256), shx, st, fg,
-                           Mt, grid, A, (const V*)tw, revinv);
+        // rows per workgroup: the measured best where it fits, fewer on long lines
+        const int R = fit_count(xrows<T>(), 2, fg.lines_cap, [&](int r) { return lds_lines<T>(n, r / 2); });
+        switch (R) {
+            case 16: if constexpr (xrows<T>() >= 16) launch_x<T, 16>(fg, Mt, grid, A, ncomp, twv, revinv, st); break;
+            case 8: if constexpr (xrows<T>() >= 8) launch_x<T, 8>(fg, Mt, grid, A, ncomp, twv, revinv, st); break;
+            case 4: if constexpr (xrows<T>() >= 4) launch_x<T, 4>(fg, Mt, grid, A, ncomp, twv, revinv, st); break;
+            default: launch_x<T, 2>(fg, Mt, grid, A, ncomp, twv, revinv, st); break;
+        }
     }
     if (passes & 2) {
-        size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
-        set_lds(k_fft_y<T, LZ>, shy);
-        hipLaunchKernelGGL((k_fft_y<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, ncomp), dim3(256), shy,
-                           st, fg, Mt, (const V*)A, B, (const V*)tw, revinv);
+        const int LZ = fit_count(ylines<T>(), 1, fg.lines_cap, [&](int l) { return lds_lines<T>(n, l); });
+        switch (LZ) {
+            case 8: if constexpr (ylines<T>() >= 8) launch_y<T, 8>(fg, Mt, A, B, ncomp, twv, revinv, st); break;
+            case 4: if constexpr (ylines<T>() >= 4) launch_y<T, 4>(fg, Mt, A, B, ncomp, twv, revinv, st); break;
+            case 2: if constexpr (ylines<T>() >= 2) launch_y<T, 2>(fg, Mt, A, B, ncomp, twv, revinv, st); break;
+            default: launch_y<T, 1>(fg, Mt, A, B, ncomp, twv, revinv, st); break;
+        }
     }
 }
 
@@ -836,7 +916,7 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
     constexpr int ZC = 4;  // ky columns per workgroup
     dim3 grd((n + ZC - 1) / ZC, Mt + 1, batch);
     // LDS: twiddles, CIN lines, index table, sigma row
-    size_t sh = sizeof(V) * (size_t)n * (1 + c_in) + sizeof(int) * n + 16 + sizeof(T) * (size_t)(Mt + 1);
+    const size_t sh = lds_z<T>(n, Mt, c_in, 1);
     const int need = (c_in * Mt + 127) / 128;  // column elements per thread
     // the prefetch registers cost the FP32 kernel a third of its occupancy (the
     // LDS allows eight blocks per CU there), a net loss; FP64 is LDS-limited to
@@ -861,7 +941,8 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
     } while (0)
     // FP32 three-component kernels: FSE_ZB32 columns (3 FSE_ZB32 lines) transformed
     // together by FSE_ZBT32 threads, FSE_ZBG32 such groups per workgroup (measured
-    // at Mt = 250: 1.05 ms against 1.15 ms one column at a time)
+    // at Mt = 250: 1.05 ms against 1.15 ms one column at a time), where their
+    // lines fit in LDS
 #ifndef FSE_ZB32
 #define FSE_ZB32 3
 #endif
@@ -869,13 +950,13 @@ void launch_fft_zscale(const FftGeo& fg, const GridGeo& g, int kernel, void* Bv,
 #define FSE_ZBT32 256
 #endif
     if constexpr (sizeof(T) == 4 && FSE_ZB32 > 1) {
-        if (kernel == FSE_STOKESLET || kernel == FSE_ROTLET) {
+        constexpr int ZB = FSE_ZB32;
+        const size_t shb = lds_z<T>(n, Mt, 3 * ZB, ZB);
+        if ((kernel == FSE_STOKESLET || kernel == FSE_ROTLET) && shb <= LDS_BYTES && fg.lines_cap == 0) {
 #ifndef FSE_ZBG32
 #define FSE_ZBG32 2
 #endif
-            constexpr int ZB = FSE_ZB32, ZCB = FSE_ZBG32 * FSE_ZB32;
-            const size_t shb =
-                sizeof(V) * (size_t)n * (1 + 3 * ZB) + sizeof(int) * n + 16 + sizeof(T) * (size_t)ZB * (Mt + 1);
+            constexpr int ZCB = FSE_ZBG32 * FSE_ZB32;
             const dim3 grdb((n + ZCB - 1) / ZCB, Mt + 1, batch);
 #define ZBLAUNCH(K)                                                                                          \
     do {                                                                                                     \
@@ -905,20 +986,25 @@ void launch_fft_inverse(const FftGeo& fg, const GridGeo& g, void* Bv, void* Av, 
     using V = C2<T>;
     (void)rev;
     const int Mt = g.Mt, n = fg.n;
-    constexpr int R = xinvrows<T>(), LZ = yinvlines<T>();
     V* A = (V*)Av;
     V* B = (V*)Bv;
+    const V* twv = (const V*)tw;
     if (passes & 1) {
-        size_t shy = sizeof(V) * (size_t)n * (1 + LZ) + sizeof(int) * n;
-        set_lds(k_fft_yinv<T, LZ>, shy);
-        hipLaunchKernelGGL((k_fft_yinv<T, LZ>), dim3((Mt + LZ - 1) / LZ, Mt + 1, 3 * batch), dim3(256),
-                           shy, st, fg, Mt, c_in, (const V*)B, A, (const V*)tw, revinv);
+        const int LZ = fit_count(yinvlines<T>(), 1, fg.lines_cap, [&](int l) { return lds_lines<T>(n, l); });
+        switch (LZ) {
+            case 8: if constexpr (yinvlines<T>() >= 8) launch_yinv<T, 8>(fg, Mt, c_in, batch, B, A, twv, revinv, st); break;
+            case 4: if constexpr (yinvlines<T>() >= 4) launch_yinv<T, 4>(fg, Mt, c_in, batch, B, A, twv, revinv, st); break;
+            case 2: if constexpr (yinvlines<T>() >= 2) launch_yinv<T, 2>(fg, Mt, c_in, batch, B, A, twv, revinv, st); break;
+            default: launch_yinv<T, 1>(fg, Mt, c_in, batch, B, A, twv, revinv, st); break;
+        }
     }
     if (passes & 2) {
-        size_t shx = sizeof(V) * ((size_t)n * (1 + R / 2) + (size_t)R * (Mt + 1)) + sizeof(int) * n;
-        set_lds(k_fft_xinv<T, R>, shx);
-        hipLaunchKernelGGL((k_fft_xinv<T, R>), dim3((Mt + R - 1) / R, Mt, 3 * batch), dim3(256), shx, st,
-                           fg, Mt, c_in, (const V*)A, field, (const V*)tw, revinv);
+        const int R = fit_count(xinvrows<T>(), 2, fg.lines_cap, [&](int r) { return lds_xinv<T>(n, Mt, r); });
+        switch (R) {
+            case 8: if constexpr (xinvrows<T>() >= 8) launch_xinv<T, 8>(fg, Mt, c_in, batch, A, field, twv, revinv, st); break;
+            case 4: if constexpr (xinvrows<T>() >= 4) launch_xinv<T, 4>(fg, Mt, c_in, batch, A, field, twv, revinv, st); break;
+            default: launch_xinv<T, 2>(fg, Mt, c_in, batch, A, field, twv, revinv, st); break;
+        }
     }
 }
 

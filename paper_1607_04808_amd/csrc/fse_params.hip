@@ -177,6 +177,7 @@ fse_status_t fse_choose_params(fse_kernel_t kernel, fse_dtype_t dtype, int64_t n
     const CostModel cm = dtype == FSE_F32 ? COST_F32 : COST_F64;
     const double rho = (double)n / (L * L * L);
     const int cin = kernel == FSE_STRESSLET ? 6 : 3;  // grid components spread
+    const int mt_max = fft_max_mt((int)kernel, dtype == FSE_F32 ? 4 : 8);
     bool found = false;
     double best = 0;
     fse_params_t bp{};
@@ -200,7 +201,7 @@ fse_status_t fse_choose_params(fse_kernel_t kernel, fse_dtype_t dtype, int64_t n
         const double eta_max = dtype == FSE_F32 ? 0.7 : 0.95;
         const int Meta = (int)ceil(xi * L * P / (m * sqrt(eta_max)));
         int M = 0, Mt = 0;
-        for (int Mc = std::max(4, Meta); Mc <= 1100; ++Mc) {
+        for (int Mc = std::max(4, Meta); Mc <= mt_max; ++Mc) {
             const double h = L / Mc;
             const double eta = (xi * h * P / m) * (xi * h * P / m);
             const double dL = std::max(h * P, sqrt(2.0 * (1.0 - eta) * m * m) / xi);
@@ -212,7 +213,7 @@ fse_status_t fse_choose_params(fse_kernel_t kernel, fse_dtype_t dtype, int64_t n
                 break;
             }
         }
-        if (M == 0 || Mt > 540) continue;
+        if (M == 0 || Mt > mt_max) continue;
         const double pairs = (double)n * rho * 4.0 / 3.0 * PI * rc * rc * rc;
         const double nf = 2.0 * Mt;
         // transforms: cin components forward, 3 back, in each of the two chains
@@ -229,7 +230,7 @@ fse_status_t fse_choose_params(fse_kernel_t kernel, fse_dtype_t dtype, int64_t n
         }
     }
     if (!found) {
-        set_error("no parameters meet rel_tol %.1e within the grid limit (Mt <= 540)", rel_tol);
+        set_error("no parameters meet rel_tol %.1e within the grid limit (Mt <= %d)", rel_tol, mt_max);
         return FSE_EINVAL;
     }
     for (int d = 0; d < 3; ++d) bp.box_lo[d] = box_lo[d];

@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_side", ctypes.c_int32), ("real_queue", ctypes.c_int32), ("real_queue_grad", ctypes.c_int32),
-                ("real_waves", ctypes.c_int32)]
+                ("real_waves", ctypes.c_int32), ("fft_lines", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -341,8 +341,10 @@ class Plan:
         return t.as_dict()
 
     def set_tuning(self, t):
-        """Apply a tuning dict (fse_plan_set_tuning); points must be set again."""
-        tt = Tuning(**{k: int(t[k]) for k, _ in Tuning._fields_})
+        """Apply a tuning dict (fse_plan_set_tuning); points must be set again.
+        Knobs the dict leaves out keep their current values."""
+        cur = self.tuning()
+        tt = Tuning(**{k: int(t.get(k, cur[k])) for k, _ in Tuning._fields_})
         _check(lib().fse_plan_set_tuning(self._h, ctypes.byref(tt)))
         self.generation += 1
 

@@ -62,7 +62,7 @@ def test_geometry_rejects_bad_parameters():
             F.geometry("stokeslet", F.make_params(**kw))
         assert e.value.status == 1
     with pytest.raises(F.FseError):
-        F.geometry("stokeslet", F.make_params(xi=5.0, rc=0.3, M=800, P=8))  # grid too large
+        F.geometry("stokeslet", F.make_params(xi=5.0, rc=0.3, M=1020, P=8))  # Mt = 1028 > 1024
 
 
 def test_forced_grid_size_and_padding():

@@ -191,9 +191,9 @@ def test_tuning_changes_shapes_not_results(dtype):
         u0 = plan.eval(ft).double().cpu().numpy()
         d0 = plan.adjoint(ft, wt)[1].double().cpu().numpy()
         tol = 1e-12 if dtype == "f64" else 2e-6
-        for t in ({"bin_side": 5, "real_queue": 24, "real_queue_grad": 32, "real_waves": 1},
-                  {"bin_side": 8, "real_queue": 64, "real_queue_grad": 64, "real_waves": 2},
-                  {"bin_side": 6, "real_queue": 48, "real_queue_grad": 48, "real_waves": 4}):
+        for t in ({"bin_side": 5, "real_queue": 24, "real_queue_grad": 32, "real_waves": 1, "fft_lines": 1},
+                  {"bin_side": 8, "real_queue": 64, "real_queue_grad": 64, "real_waves": 2, "fft_lines": 4},
+                  {"bin_side": 6, "real_queue": 48, "real_queue_grad": 48, "real_waves": 4, "fft_lines": 0}):
             plan.set_tuning(t)
             with pytest.raises(F.FseError):
                 plan.eval(ft)  # the points must be set again
@@ -206,5 +206,37 @@ def test_tuning_changes_shapes_not_results(dtype):
         assert relmax(plan.eval(ft).double().cpu().numpy(), u0) < tol
         with pytest.raises(F.FseError):
             plan.set_tuning(dict(best, bin_side=3))
+        with pytest.raises(F.FseError):
+            plan.set_tuning(dict(best, fft_lines=3))
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fft_line_counts_agree(kernel, dtype):
+    """Each FFT pass transforms its lines one by one, whatever the number of lines
+    a workgroup holds, and the z-pass multiplies each wavevector alike, one column
+    or three at a time: every line count (the variants that long lines fall back
+    to) gives the default's field to within a few units of rounding."""
+    n = 3000
+    prm = F.make_params(9.0, 0.35, 22, 12, L=1.0)
+    x = W.uniform_cube(n, 395)
+    f = W.normal_strengths(n, 396)
+    nrm = W.normal_strengths(n, 397) if kernel == "stresslet" else None
+    plan = F.Plan(kernel, dtype, prm, nmax=n, tuned=False)
+    try:
+        xt, ft = _t(x, dtype), _t(f, dtype)
+        bt = None if nrm is None else _t(nrm, dtype)
+        plan.set_points(xt)
+        u0 = plan.eval_parts(ft, bt)[1].double().cpu().numpy()
+        worst = 0.0
+        for lines in (16, 8, 4, 2, 1):
+            plan.set_tuning({"fft_lines": lines})
+            plan.set_points(xt)
+            u = plan.eval_parts(ft, bt)[1].double().cpu().numpy()
+            worst = max(worst, relmax(u, u0))
+        print(kernel, dtype, "largest change of u^F over line counts %.1e" % worst)
+        assert worst < (1e-14 if dtype == "f64" else 1e-6)
     finally:
         plan.close()
