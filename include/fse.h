@@ -210,6 +210,25 @@ fse_status_t fse_plan_multiplier(fse_plan_t *plan, double *out);
  * the quadrature reads (step 4).  Synchronises. */
 fse_status_t fse_plan_grid(fse_plan_t *plan, int32_t which, double *out);
 
+/* Copy, for tests, the binning of the points last set (fse_set_points) to host
+ * memory.  Any array pointer may be NULL; n is the point count, nbins the bins
+ * per side of the spreading grid (written first, so a call with NULL arrays
+ * gives the sizes) and ncell the geometry's cells per side:
+ *   perm_s[n]     the point (index into x) at each position of the spread order:
+ *                 points ordered by bin (bins of bin_side^3 grid nodes, x
+ *                 fastest), in input order within a bin;
+ *   bpack_s[n]    its window start b = floor(t - P/2 + 1), t = (x - x0)/h, per
+ *                 direction (Section 5.1's support of eq. Hx), packed
+ *                 bx | by << 10 | bz << 20;
+ *   coff_s[3n]    its window-centre offset t - b - (P - 1)/2 per direction, as the
+ *                 quadrature and spreading use it (the plan's dtype, widened);
+ *   tile_start[nbins^3 + 1]   first spread-order position of each bin;
+ *   perm_r[n], cell_start[ncell^3 + 1]   the same order and offsets for the
+ *                 real-space cells (side >= r_c, Section 6).
+ * FSE_ESTATE before fse_set_points.  Synchronises. */
+fse_status_t fse_plan_bins(fse_plan_t *plan, int32_t *nbins, int32_t *perm_s, int32_t *bpack_s, double *coff_s,
+                           int32_t *tile_start, int32_t *perm_r, int32_t *cell_start);
+
 /*
  * Per-stage timing with HIP events recorded on the plan's stream around each
  * kernel launch group.  Stages (index: name): 0 bin, 1 permute, 2 spread,

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -403,7 +404,10 @@ template <typename T> fse_status_t allocate(fse_plan* p) {
     TRY(p->alloc((T**)&p->x_r, 3 * nm));
     p->ntiles3 = (int64_t)p->gg.nt * p->gg.nt * p->gg.nt;
     {
-        const int64_t ntm = (p->gg.Mt + MIN_BIN_SIDE - 1) / MIN_BIN_SIDE;
+        // the most bins any bin side this plan may take gives: the smallest a tuning
+        // may set, or the default where the LDS bound makes that smaller (large P)
+        const int side = std::min(MIN_BIN_SIDE, p->gg.TS);
+        const int64_t ntm = (p->gg.Mt + side - 1) / side;
         p->ntiles_max = ntm * ntm * ntm;
     }
     p->ncells3 = (int64_t)p->cg.ncell * p->cg.ncell * p->cg.ncell;
@@ -1350,6 +1354,34 @@ fse_status_t fse_plan_grid(fse_plan_t* plan, int32_t which, double* out) {
         std::vector<float> tmp(cnt);
         HIPCHK(hipMemcpy(tmp.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
         for (size_t i = 0; i < cnt; ++i) out[i] = tmp[i];
+    }
+    return FSE_OK;
+}
+
+fse_status_t fse_plan_bins(fse_plan_t* plan, int32_t* nbins, int32_t* perm_s, int32_t* bpack_s, double* coff_s,
+                           int32_t* tile_start, int32_t* perm_r, int32_t* cell_start) {
+    if (!plan) { set_err("null plan"); return FSE_EINVAL; }
+    if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
+    if (nbins) *nbins = plan->gg.nt;
+    const size_t n = (size_t)plan->n;
+    HIPCHK(hipStreamSynchronize(plan->stream));
+    auto get = [&](void* dst, const void* src, size_t bytes) -> fse_status_t {
+        if (dst) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+        return FSE_OK;
+    };
+    TRY(get(perm_s, plan->perm_s, n * sizeof(int)));
+    TRY(get(bpack_s, plan->bpack_s, n * sizeof(int)));
+    TRY(get(tile_start, plan->start_s, (size_t)(plan->ntiles3 + 1) * sizeof(int)));
+    TRY(get(perm_r, plan->perm_r, n * sizeof(int)));
+    TRY(get(cell_start, plan->start_r, (size_t)(plan->ncells3 + 1) * sizeof(int)));
+    if (coff_s) {
+        if (plan->dtype == FSE_F64) {
+            TRY(get(coff_s, plan->coff_s, 3 * n * sizeof(double)));
+        } else {
+            std::vector<float> tmp(3 * n);
+            TRY(get(tmp.data(), plan->coff_s, 3 * n * sizeof(float)));
+            for (size_t i = 0; i < 3 * n; ++i) coff_s[i] = tmp[i];
+        }
     }
     return FSE_OK;
 }

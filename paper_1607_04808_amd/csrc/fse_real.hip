@@ -16,6 +16,7 @@
 // range in cell order, so each chunk is a coalesced read), hits queued per
 // thread and evaluated wave-wide.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <type_traits>
 
@@ -115,12 +116,39 @@ __device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, flo
 #endif
 template <typename T, bool GRAD>
 constexpr int qcap() { return sizeof(T) == 4 ? (GRAD ? FSE_QCAP32G : FSE_QCAP32) : 48; }
+// source slots per chunk, and the chunk buffers a pass keeps: two (queued hits may
+// outlive their chunk) for single FP64 passes, measured 6 % faster there; FP32
+// pairs cost too few instructions to pay for the queue moves (value pass 12 %
+// slower), and batched passes hold four times the values per chunk
+template <typename T> constexpr int real_chunk() { return sizeof(T) == 4 ? FSE_REAL_CH32 : FSE_REAL_CH64; }
+template <typename T, int NB> constexpr int real_nbuf() { return NB == 1 && sizeof(T) == 8 ? 2 : 1; }
+// queue entries: buffer slot indices, 16 bits (one-byte entries, which would fit
+// the FP32 passes' 128 slots, measured 6 % slower in the FP32 value pass)
+using QE = unsigned short;
 
 // 1 when the sign bit of v is set (v < 0 or v = -0), else 0
 __device__ __forceinline__ unsigned sign_bit(float v) { return __float_as_uint(v) >> 31; }
 __device__ __forceinline__ unsigned sign_bit(double v) {
     return (unsigned)((unsigned long long)__double_as_longlong(v) >> 63);
 }
+// Wave-wide max (MAX) or min of an int, the same in every lane: an inclusive
+// scan within each row of 16 lanes by DPP row shifts, then the row totals
+// carried across rows by DPP row broadcasts, read from the last lane.  Lanes a
+// DPP source does not reach take the identity.  No LDS traffic.
+template <bool MAX> __device__ __forceinline__ int wave_reduce(int v) {
+    constexpr int id = MAX ? INT_MIN : INT_MAX;
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce<true>(v); }
+__device__ __forceinline__ int wave_min(int v) { return wave_reduce<false>(v); }
+
 // queue row stride: the workgroup size rounded up to a power of two, so that a
 // hit advances the queue pointer by a shift of the hit bit
 __host__ __device__ inline int queue_row(int nthr) { return nthr <= 64 ? 64 : nthr <= 128 ? 128 : 256; }
@@ -162,12 +190,18 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
     constexpr int NS = TADJ ? 3 : ((KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3);  // staged values per source
     constexpr int NO = TADJ ? 6 : 3;  // accumulated values per target and batch member
     // source slots per LDS chunk
-    constexpr int CH = sizeof(T) == 4 ? FSE_REAL_CH32 : FSE_REAL_CH64;
+    constexpr int CH = real_chunk<T>();
     static_assert(CH % 8 == 0, "candidates are tested in groups of 8");
-    __shared__ Pos4<T> xs[CH];  // source positions
-    __shared__ Pos4<T> xq[CH];  // test form: -2 (x - o), |x - o|^2 about the cell corner o
-    __shared__ T ss[NB][NS][CH];
-    extern __shared__ unsigned short qd[];  // hit queues: qcap rows of blockDim.x entries
+    // CARRY: queued hits may outlive their chunk by one chunk, so a chunk's end
+    // evaluates only as many entries as keep every lane busy (plus what must go);
+    // the chunks' positions and values alternate between two buffers.
+    constexpr int NBUF = real_nbuf<T, NB>();
+    constexpr bool CARRY = NBUF == 2;
+    __shared__ Pos4<T> xs[NBUF * CH];  // source positions
+    __shared__ Pos4<T> xq[CH];         // test form: -2 (x - o), |x - o|^2 about the cell corner o
+    __shared__ T ss[NB][NS][NBUF * CH];
+    extern __shared__ __align__(16) unsigned char qd_raw[];
+    QE* const qd = (QE*)qd_raw;  // hit queues: qcap (+ 8 with CARRY) rows of queue_row(blockDim.x) entries
     const int tid = threadIdx.x;
     const int nc = cg.ncell;
     const int nthr = blockDim.x;
@@ -278,10 +312,13 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
         double gs0 = 0, gs1 = 0, gs2 = 0;
         // this thread's hit queue: column tid of qd, QROW entries per row
         const int QROW = queue_row(nthr);
-        const int qsh = QROW == 64 ? 7 : QROW == 128 ? 8 : 9;  // log2 of a row in bytes
-        unsigned short* const q0 = qd + tid;
-        unsigned short* const qlim = q0 + ((GRAD ? cg.qcap_grad : cg.qcap) - 8) * QROW;
-        unsigned short* qp = q0;
+        const int qlog = QROW == 64 ? 6 : QROW == 128 ? 7 : 8;  // log2 of a row in entries
+        const int qsh = qlog + 1;                               // and in bytes
+        QE* const q0 = qd + tid;
+        const int qcap = GRAD ? cg.qcap_grad : cg.qcap;
+        QE* const qlim = q0 + (qcap - 8) * QROW;
+        QE* qp = q0;
+        int old = 0;  // CARRY: entries at the front of the queue from the previous chunk
         // widened test threshold folded into the target term: a hit is a negative sign
         const T Atc = At - rc2t;
         const bool wave_active = __any(act);
@@ -458,18 +495,50 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                 }
             }
         };
-        auto flush = [&]() {
-            const int qn = (int)(qp - q0) >> (qsh - 1);
-            int qmax = qn;
-#pragma unroll
-            for (int d = 32; d > 0; d >>= 1) qmax = max(qmax, __shfl_xor(qmax, d));
-            qmax = __builtin_amdgcn_readfirstlane(qmax);
-            for (int e = 0; e < qmax; ++e) {
+        // Evaluate the first E entries of every lane's queue (E the same for the
+        // whole wave; a lane with fewer entries idles for the rest).  mode 2 (the
+        // work item's last chunk, or no CARRY): E = the longest queue, all of it.
+        // mode 0 (a queue near full inside a chunk) and mode 1 (a chunk's end):
+        // E = the shortest queue, so every lane is busy, but at least what leaves
+        // each queue at most qcap - 16 entries and, at a chunk's end, at least the
+        // entries of the previous chunk, whose buffer the next chunk overwrites.
+        // The entries left move to the front of the queue, in order.
+        auto flush = [&](int mode) {
+            const int qn = (int)(qp - q0) >> qlog;
+            const int qmax = wave_max(qn);
+            int E = qmax;
+            if (CARRY && mode != 2) {
+                // (lanes without a target have empty queues and do not count)
+                E = max(wave_min(act ? qn : 1 << 20), qmax - (qcap - 16));
+                if (mode == 1) E = max(E, wave_max(old));
+            }
+            for (int e = 0; e < E; ++e) {
                 const bool on = e < qn;
                 const int kk = q0[e * QROW];
                 eval(on ? kk : 0, on);
             }
-            qp = q0;
+            if constexpr (CARRY) {
+                const int rest = max(qn - E, 0);
+                // move rows [E, qmax) to [0, qmax - E), eight at a time, in every lane:
+                // rows past a lane's own entries carry stale values that are never
+                // read as entries (the queue has 8 spare rows for the last group).  A
+                // group reads before it writes, and reads only rows above every row
+                // written so far.
+                if (E > 0) {
+                    const QE* src = q0 + E * QROW;
+                    for (int k = 0; k < qmax - E; k += 8) {
+                        QE v[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) v[u] = src[(k + u) * QROW];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) q0[(k + u) * QROW] = v[u];
+                    }
+                }
+                qp = q0 + rest * QROW;
+                old = mode == 1 ? rest : max(old - E, 0);
+            } else {
+                qp = q0;
+            }
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -496,6 +565,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
         const int nr = nb_n - nq * nch;
         int cur = nb_s, rem = 0;
         for (int c = 0; c < nch; ++c) {
+            const int base = CARRY ? (c & 1) * CH : 0;  // this chunk's buffer
             __syncthreads();
             if (tid < 32) {
                 int cnt = 0, base = 0;
@@ -568,22 +638,22 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                 }
                 if (keep) {
                     const int slot = off + __popcll(m & ((1ull << (tid & 63)) - 1ull));
-                    xs[slot] = ps;
+                    xs[base + slot] = ps;
                     xq[slot] = pq;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         if (b0 + b < batch) {
                             const T* ap = (TADJ ? w_r : a_r) + ((int64_t)(b0 + b) * n + src) * 3;
 #pragma unroll
-                            for (int d = 0; d < 3; ++d) ss[b][d][slot] = ap[d];
+                            for (int d = 0; d < 3; ++d) ss[b][d][base + slot] = ap[d];
                             if constexpr (NS == 6) {
                                 const T* bp = (GRAD ? w_r : b_r) + ((int64_t)(b0 + b) * n + src) * 3;
 #pragma unroll
-                                for (int d = 0; d < 3; ++d) ss[b][3 + d][slot] = bp[d];
+                                for (int d = 0; d < 3; ++d) ss[b][3 + d][base + slot] = bp[d];
                             }
                         } else {
 #pragma unroll
-                            for (int d = 0; d < NS; ++d) ss[b][d][slot] = (T)0;
+                            for (int d = 0; d < NS; ++d) ss[b][d][base + slot] = (T)0;
                         }
                     }
                 }
@@ -602,23 +672,23 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
             // candidates in groups of 8 (padding slots are far away); the self pair
             // and coincident points (r^2 = 0) are queued and skipped when evaluated
             const int cnt8 = (kept + 7) & ~7;
-            // slot indices two to a register (low, high half), advanced by 8 per group
+            // buffer slot indices two to a register (low, high half), advanced by 8 per group
             unsigned kp[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) kp[v] = (2u * v) | ((2u * v + 1u) << 16);
+            for (int v = 0; v < 4; ++v) kp[v] = (unsigned)(base + 2 * v) | ((unsigned)(base + 2 * v + 1) << 16);
             for (int k8 = 0; k8 < cnt8; k8 += 8) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const Pos4<T> pq = xq[k8 + u];
                     const T d = fma(xl0, pq.x, fma(xl1, pq.y, fma(xl2, pq.z, Atc + pq.pad)));
-                    *qp = (unsigned short)((u & 1) ? (kp[u >> 1] >> 16) : kp[u >> 1]);
-                    qp = (unsigned short*)((char*)qp + (sign_bit(d) << qsh));
+                    *qp = (QE)((u & 1) ? (kp[u >> 1] >> 16) : kp[u >> 1]);
+                    qp = (QE*)((char*)qp + (sign_bit(d) << qsh));
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) kp[v] += 0x00080008u;
-                if (__any(qp > qlim)) flush();
+                if (__any(qp > qlim)) flush(0);
             }
-            flush();
+            flush(c == nch - 1 ? 2 : 1);
         }
         if (act) {
             const int64_t i = perm_r[j];
@@ -681,6 +751,14 @@ int default_qcap(int elem_bytes, bool grad) {
     return elem_bytes == 4 ? (grad ? qcap<float, true>() : qcap<float, false>()) : qcap<double, false>();
 }
 
+// dynamic LDS of a pass's hit queues: qcap rows of queue_row(thr) entries, and 8
+// spare rows for the queue moves of two-buffer passes (the FP32 passes keep their
+// LDS within what eight workgroups per CU hold)
+template <typename T> size_t queue_bytes(int qcap, unsigned thr, int NB) {
+    const int spare = (NB == 1 ? real_nbuf<T, 1>() : real_nbuf<T, 4>()) == 2 ? 8 : 0;
+    return (size_t)(qcap + spare) * queue_row((int)thr) * sizeof(QE);
+}
+
 unsigned real_threads(int64_t n, int64_t ncells, int max_waves) {
     const double mean = (double)n / (double)ncells;
     const int waves = (int)std::ceil(mean / 64.0);
@@ -696,7 +774,7 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     const unsigned thr = (unsigned)p.t_real_S;
     // at most ceil(nt / S) + ncells work items; the surplus workgroups return at once
     const unsigned items = (unsigned)((p.t_n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)c.qcap * queue_row((int)thr) * sizeof(unsigned short);
+    const size_t qbytes = queue_bytes<T>(c.qcap, thr, NBc);
     dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
     hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p, src_a_r, src_b_r,        \
@@ -717,10 +795,10 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.real_S;
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)c.qcap_grad * queue_row((int)thr) * sizeof(unsigned short);
     // batch members in groups of 4 per pass; each pass adds to dx (and dsrc)
     for (int b0 = 0; b0 < batch; b0 += 4) {
         const int nb = batch - b0 < 4 ? batch - b0 : 4;
+        const size_t qbytes = queue_bytes<T>(c.qcap_grad, thr, nb == 1 ? 1 : 4);
         const T* f = f_r + (int64_t)b0 * p.n * 3;
         const T* w = w_r + (int64_t)b0 * p.n * 3;
         T* ds = dsrc ? dsrc + (int64_t)b0 * p.n * 3 : nullptr;
@@ -746,7 +824,7 @@ void launch_real_tadj(const CellGeo& c, const PointsDev<T>& p, const T* q_r, con
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.t_real_S;
     const unsigned items = (unsigned)((p.t_n + thr - 1) / thr + ncells);
-    const size_t qbytes = (size_t)c.qcap * queue_row((int)thr) * sizeof(unsigned short);
+    const size_t qbytes = queue_bytes<T>(c.qcap, thr, 1);
     // one batch member per workgroup row (six accumulators per member)
     hipLaunchKernelGGL((k_real<T, KTADJ, 1, false>), dim3(items, batch), dim3(thr), qbytes, st, c, p, q_r, n_r,
                        w_r, batch, (T)xi, (T)0, dq, 1, dn);

@@ -26,7 +26,7 @@ EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set
            "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error", "fse_eval_noalloc",
            "fse_error_estimates", "fse_choose_params", "fse_bounding_box", "fse_set_targets", "fse_eval_targets",
            "fse_eval_adjoint_stresslet", "fse_freespace_solve",
-           "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_plan_autotune")
+           "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_plan_autotune", "fse_plan_bins")
 NOALLOC_MAX_BYTES = 64 << 20  # FSE_NOALLOC_MAX_BYTES
 NSTAGES = 12
 
@@ -93,6 +93,7 @@ def lib():
             L.fse_plan_multiplier.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
             L.fse_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
             L.fse_plan_grid.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
+            L.fse_plan_bins.argtypes = [vp, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp]
             L.fse_plan_set_timing.argtypes = [vp, i32]
             L.fse_plan_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
             L.fse_stage_name.argtypes = [i32]
@@ -323,6 +324,21 @@ class Plan:
         nc = (6 if self.kernel == "stresslet" else 3) if which == 0 else 3
         out = np.empty((self.batch, nc, Mt, Mt, Mt), dtype=np.float64)
         _check(lib().fse_plan_grid(self._h, int(which), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def bins(self):
+        """Host copies of the binning of the points last set (fse_plan_bins): a dict
+        with nbins, perm_s, bpack_s, coff_s (n, 3), tile_start, perm_r, cell_start."""
+        nb = ctypes.c_int32(0)
+        self._sync_stream()
+        _check(lib().fse_plan_bins(self._h, ctypes.byref(nb), None, None, None, None, None, None))
+        n, nc = self.n, self.geometry.ncell
+        out = dict(nbins=nb.value, perm_s=np.empty(n, np.int32), bpack_s=np.empty(n, np.int32),
+                   coff_s=np.empty((n, 3), np.float64), tile_start=np.empty(nb.value ** 3 + 1, np.int32),
+                   perm_r=np.empty(n, np.int32), cell_start=np.empty(nc ** 3 + 1, np.int32))
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().fse_plan_bins(self._h, ctypes.byref(nb), p(out["perm_s"]), p(out["bpack_s"]), p(out["coff_s"]),
+                                   p(out["tile_start"]), p(out["perm_r"]), p(out["cell_start"])))
         return out
 
     def set_timing(self, on=True):
