@@ -210,6 +210,17 @@ fse_status_t fse_plan_multiplier(fse_plan_t *plan, double *out);
  * the quadrature reads (step 4).  Synchronises. */
 fse_status_t fse_plan_grid(fse_plan_t *plan, int32_t which, double *out);
 
+/* The process-wide cache of the mollified transform (Section 4.3): plans with the
+ * grid side Mt and kernel family (biharmonic: stokeslet, stresslet; harmonic:
+ * rotlet) of an earlier plan on the same device reuse its transform, scaled by
+ * (h / h0)^4 or (h / h0)^2 for their grid spacing h (the truncated transform is
+ * homogeneous in k and R = sqrt(3) Mt h), and skip the precompute's FFT
+ * contractions.  Entries are device memory held until the process ends, 2 GiB in
+ * all at most; the no-allocation entry point neither reads nor adds them.  Reports
+ * the lookups that found an entry (hits) or computed it (misses), the bytes held
+ * and the entries.  Any pointer may be NULL. */
+fse_status_t fse_precompute_cache_stats(int64_t *hits, int64_t *misses, size_t *bytes, int32_t *entries);
+
 /* Copy, for tests, the binning of the points last set (fse_set_points) to host
  * memory.  Any array pointer may be NULL; n is the point count, nbins the bins
  * per side of the spreading grid (written first, so a call with NULL arrays

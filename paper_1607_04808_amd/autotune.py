@@ -25,8 +25,11 @@ from . import fse as F  # noqa: E402
 
 L_UNIT = 1.0 + 2.0 ** -20
 
-# name: (kernel, dtype, n, batch, (xi, rc, M, P), deltaL_rule, positions, adjoint)
+# name: (kernel, dtype, n, batch, (xi, rc, M, P), deltaL_rule, positions, adjoint); parameters
+# None: chosen for a 1e-6 tolerance (fse_choose_params, bounding-cube box); "blobs": the
+# 64-blob cloud in its bounding cube with xi = 165, r_c = 3.93 / xi, M = 3.15 xi L
 WORKLOADS = {
+    "c1_f64": ("stokeslet", "f64", 1000, 1, None, 1, "cube", True),
     "headline_f32": ("stokeslet", "f32", 1_000_000, 1, (75.0, 0.0476, 236, 12), 0, "cube", True),
     "headline_f64": ("stokeslet", "f64", 1_000_000, 1, (80.0, 0.06075, 304, 20), 0, "cube", True),
     "batched16_f32": ("stokeslet", "f32", 1_000_000, 16, (75.0, 0.0476, 236, 12), 0, "cube", True),
@@ -35,6 +38,7 @@ WORKLOADS = {
     "c2_f64": ("stokeslet", "f64", 100_000, 1, (40.0, 0.1215, 153, 20), 0, "cube", True),
     "c3_f32": ("stresslet", "f32", 200_000, 1, (30.0, 0.14, 240, 14), 1, "sphere", False),
     "c3_f64": ("stresslet", "f64", 200_000, 1, (40.0, 0.11, 300, 14), 1, "sphere", False),
+    "c5_blobs4m_f32": ("stokeslet", "f32", 4_000_000, 1, "blobs", 0, "blobs", True),
 }
 
 
@@ -43,6 +47,12 @@ def _inputs(name, kernel, n, batch, positions):
     if positions == "sphere":
         x, nrm = W.sphere_surface(n, seed)
         lo, L = (-L_UNIT,) * 3, 2.0 * L_UNIT
+    elif positions == "blobs":
+        import numpy as np
+        x, nrm = W.gaussian_blobs(n, seed), None
+        xs = np.asarray(x, np.float32).astype(np.float64)
+        lo = tuple(float(v) for v in xs.min(axis=0))
+        L = float((xs.max(axis=0) - xs.min(axis=0)).max()) * L_UNIT + 1e-6
     else:
         x, nrm = W.uniform_cube(n, seed), None
         lo, L = (0.0, 0.0, 0.0), L_UNIT
@@ -62,7 +72,14 @@ def tune(name, repeats=3):
     td = torch.float32 if dtype == "f32" else torch.float64
     x, a, b, w, lo, L = _inputs(name, kernel, n, batch, positions)
     t = lambda v: None if v is None else torch.tensor(np.asarray(v), dtype=td, device="cuda:0")
-    params = F.make_params(*prm, box_lo=lo, L=L, deltaL_rule=rule)
+    if prm is None:
+        params = F.plan_for(kernel, t(x), t(a), t(b), tol=1e-6).params
+        prm = (params.xi, params.rc, params.M, params.P)
+    else:
+        if prm == "blobs":
+            xi = 165.0
+            prm = (xi, 3.93 / xi, int(math.ceil(3.15 * xi * L)), 12)
+        params = F.make_params(*prm, box_lo=lo, L=L, deltaL_rule=rule)
     plan = F.Plan(kernel, dtype, params, batch=batch, nmax=n, tuned=False)
     try:
         default = plan.tuning()
@@ -84,7 +101,7 @@ def tune(name, repeats=3):
         ms_default = run(repeats)
         best = plan.autotune(xt, at, bt, wt, repeats=repeats)
         ms_tuned = run(repeats)
-        return dict(name=name, kernel=kernel, dtype=dtype, batch=batch, P=prm[3], Mt=plan.geometry.Mt, n=n,
+        return dict(name=name, kernel=kernel, dtype=dtype, batch=batch, P=int(prm[3]), Mt=plan.geometry.Mt, n=n,
                     tuning=best, default=default, ms_default=round(ms_default, 3), ms_tuned=round(ms_tuned, 3))
     finally:
         plan.close()

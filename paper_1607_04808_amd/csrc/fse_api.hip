@@ -472,6 +472,25 @@ template <typename T> fse_status_t upload_fft_tables(fse_plan* p) {
 
 // Section 4.3 precompute, FP64, then fold in the scalar factors.  Its four
 // temporaries come from hipMalloc (freed at the end), or from the plan's arena.
+// Process-wide cache of the mollified transform Bt (the FP64 octant, Section 4.3),
+// one entry per (device, Mt, kernel family).  Bt depends on the grid spacing h only
+// through a factor: the truncated transform is homogeneous in (k, R), k = 2 pi kbar /
+// (Mg h) and R = sqrt(3) Mt h, so Bt(h) = (h / h0)^p Bt(h0) with p = 4 for the
+// biharmonic kernel (eq. BhatR) and 2 for the harmonic one (eq. HhatR).  Entries
+// are written once, never changed or freed (device memory held until the process
+// ends), up to BT_CACHE_MAX bytes in all; plans that find their entry skip the
+// fill and the six contractions.  The no-allocation entry point does not use it.
+struct BtEntry {
+    int dev, Mt, family;
+    double h0;
+    const double* buf;
+};
+constexpr size_t BT_CACHE_MAX = (size_t)2 << 30;
+std::mutex bt_mu;
+std::vector<BtEntry> bt_cache;
+size_t bt_bytes = 0;
+int64_t bt_hits = 0, bt_misses = 0;
+
 template <typename T> fse_status_t precompute(fse_plan* p) {
     if (p->periodic) {
         if (p->dry) return FSE_OK;
@@ -491,6 +510,40 @@ template <typename T> fse_status_t precompute(fse_plan* p) {
     const int64_t big = (int64_t)H * H * H > (int64_t)Mp * H * H ? (int64_t)H * H * H : (int64_t)Mp * H * H;
     double *t0 = nullptr, *t1 = nullptr, *c1 = nullptr, *c2 = nullptr;
     const bool carve = p->arena || p->dry;
+    const double a = p->geo.alpha;
+    const double nn = (double)p->geo.n_fft;
+    // the Gaussian normalisations (alpha/pi)^{3/2} of spreading and quadrature, the
+    // quadrature weight h^3 and the inverse transform's 1/n^3 (the transform Bt
+    // already carries the convolution's h^3: the solver's plain convolution is 1/n^3)
+    const double norm = p->solver ? 1.0 / (nn * nn * nn) : pow(a / PI, 3.0) * pow(p->geo.h, 3.0) / (nn * nn * nn);
+    const int fin_kernel = p->solver ? KSCALAR : (int)p->kernel;
+    const double hpow = p->family == 0 ? 4.0 : 2.0;  // Bt's degree of homogeneity in h
+    int dev = -1;
+    if (!carve) {
+        HIPCHK(hipGetDevice(&dev));
+        const double* hit = nullptr;
+        double h0 = 0.0;
+        {
+            std::lock_guard<std::mutex> lk(bt_mu);
+            for (const BtEntry& e : bt_cache)
+                if (e.dev == dev && e.Mt == Mt && e.family == p->family) {
+                    hit = e.buf;
+                    h0 = e.h0;
+                }
+            if (hit) ++bt_hits; else ++bt_misses;
+        }
+        if (hit) {
+            launch_pre_finalize<T>(hit, Mt, PI / p->geo.Lt, p->prm.xi, p->geo.eta, fin_kernel,
+                                   norm * pow(p->geo.h / h0, hpow), p->sig64, (T*)p->sig, p->stream);
+            hipError_t e = hipGetLastError();
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) {
+                set_err("precompute failed: %s", hipGetErrorString(e));
+                return FSE_EHIP;
+            }
+            return FSE_OK;
+        }
+    }
     auto cleanup = [&]() {
         if (carve) return;
         if (t0) (void)hipFree(t0);
@@ -542,19 +595,47 @@ template <typename T> fse_status_t precompute(fse_plan* p) {
     launch_pre_contract(t1, t0, c2, Mp, Mp, (int64_t)Mp * Mp, st);
     launch_pre_contract(t0, t1, c2, Mp, Mp, (int64_t)Mp * Mp, st);
     launch_pre_contract(t1, t0, c2, Mp, Mp, (int64_t)Mp * Mp, st); // [k1][k2][k3]: mollified transform
-    const double a = p->geo.alpha;
-    const double nn = (double)p->geo.n_fft;
-    // the Gaussian normalisations (alpha/pi)^{3/2} of spreading and quadrature, the
-    // quadrature weight h^3 and the inverse transform's 1/n^3 (the transform Bt
-    // already carries the convolution's h^3: the solver's plain convolution is 1/n^3)
-    const double norm = p->solver ? 1.0 / (nn * nn * nn) : pow(a / PI, 3.0) * pow(p->geo.h, 3.0) / (nn * nn * nn);
-    launch_pre_finalize<T>(t0, Mt, PI / p->geo.Lt, p->prm.xi, p->geo.eta, p->solver ? KSCALAR : (int)p->kernel,
-                           norm, p->sig64, (T*)p->sig, st);
+    // a copy of Bt for the cache, when it has room (published after the stream sync)
+    const size_t bt_size = (size_t)Mp * Mp * Mp * sizeof(double);
+    double* keep = nullptr;
+    if (!carve) {
+        bool room;
+        {
+            std::lock_guard<std::mutex> lk(bt_mu);
+            room = bt_bytes + bt_size <= BT_CACHE_MAX;
+        }
+        if (room && hipMalloc(&keep, bt_size) == hipSuccess) {
+            if (hipMemcpyAsync(keep, t0, bt_size, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(keep);
+                keep = nullptr;
+            }
+        } else {
+            (void)hipGetLastError();  // a failed cache allocation is not an error of the plan
+            keep = nullptr;
+        }
+    }
+    launch_pre_finalize<T>(t0, Mt, PI / p->geo.Lt, p->prm.xi, p->geo.eta, fin_kernel, norm, p->sig64, (T*)p->sig,
+                           st);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         set_err("precompute failed: %s", hipGetErrorString(e));
         rc = FSE_EHIP;
+    }
+    if (keep) {
+        bool stored = false;
+        if (rc == FSE_OK) {
+            std::lock_guard<std::mutex> lk(bt_mu);
+            bool dup = false;
+            for (const BtEntry& en : bt_cache) dup = dup || (en.dev == dev && en.Mt == Mt && en.family == p->family);
+            if (!dup && bt_bytes + bt_size <= BT_CACHE_MAX) {
+                bt_cache.push_back(BtEntry{dev, Mt, p->family, p->geo.h, keep});
+                bt_bytes += bt_size;
+                stored = true;
+            }
+        }
+        if (!stored) (void)hipFree(keep);
     }
     cleanup();
     return rc;
@@ -1355,6 +1436,15 @@ fse_status_t fse_plan_grid(fse_plan_t* plan, int32_t which, double* out) {
         HIPCHK(hipMemcpy(tmp.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
         for (size_t i = 0; i < cnt; ++i) out[i] = tmp[i];
     }
+    return FSE_OK;
+}
+
+fse_status_t fse_precompute_cache_stats(int64_t* hits, int64_t* misses, size_t* bytes, int32_t* entries) {
+    std::lock_guard<std::mutex> lk(bt_mu);
+    if (hits) *hits = bt_hits;
+    if (misses) *misses = bt_misses;
+    if (bytes) *bytes = bt_bytes;
+    if (entries) *entries = (int32_t)bt_cache.size();
     return FSE_OK;
 }
 

@@ -26,7 +26,8 @@ EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set
            "fse_stage_name", "fse_plan_destroy", "fse_status_string", "fse_last_error", "fse_eval_noalloc",
            "fse_error_estimates", "fse_choose_params", "fse_bounding_box", "fse_set_targets", "fse_eval_targets",
            "fse_eval_adjoint_stresslet", "fse_freespace_solve",
-           "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_plan_autotune", "fse_plan_bins")
+           "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_plan_autotune", "fse_plan_bins",
+           "fse_precompute_cache_stats")
 NOALLOC_MAX_BYTES = 64 << 20  # FSE_NOALLOC_MAX_BYTES
 NSTAGES = 12
 
@@ -94,6 +95,8 @@ def lib():
             L.fse_plan_workspace.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
             L.fse_plan_grid.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double)]
             L.fse_plan_bins.argtypes = [vp, ctypes.POINTER(i32), vp, vp, vp, vp, vp, vp]
+            L.fse_precompute_cache_stats.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                                     ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(i32)]
             L.fse_plan_set_timing.argtypes = [vp, i32]
             L.fse_plan_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
             L.fse_stage_name.argtypes = [i32]
@@ -445,6 +448,13 @@ def eval_noalloc(kernel, dtype, params: Params, x, a, b=None, out=None, batch=1,
     _check(lib().fse_eval_noalloc(_kid(kernel), DTYPES[dtype], ctypes.byref(params), int(batch), n, _ptr(x),
                                   _ptr(a), _ptr(b), _ptr(out), 1 if validate else 0, _stream_ptr()))
     return out
+
+
+def precompute_cache_stats():
+    """fse_precompute_cache_stats: dict of hits, misses, bytes and entries."""
+    h, m, b, e = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int32()
+    _check(lib().fse_precompute_cache_stats(ctypes.byref(h), ctypes.byref(m), ctypes.byref(b), ctypes.byref(e)))
+    return dict(hits=h.value, misses=m.value, bytes=b.value, entries=e.value)
 
 
 TUNING_PATH = os.path.join(_HERE, "tuning.json")

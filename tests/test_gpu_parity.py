@@ -91,6 +91,43 @@ def test_multiplier_matches_mollified_kernel(kernel, Mt):
     plan.close()
 
 
+def _multiplier_ref(kernel, plan, params):
+    g = _oracle_geo(plan, params)
+    Kt = se.mollified_kernel(se.kernel_family(kernel), g)
+    Mp = g.Mt + 1
+    kb = np.arange(Mp)
+    k2 = (math.pi / g.Lt) ** 2 * (kb[:, None, None] ** 2 + kb[None, :, None] ** 2 + kb[None, None, :] ** 2)
+    E = np.exp(-(1 - g.eta) * k2 / (4 * g.xi ** 2))
+    fac = {"stokeslet": -(1 + k2 / (4 * g.xi ** 2)) * E, "stresslet": (1 + k2 / (4 * g.xi ** 2)) * E,
+           "rotlet": E}[kernel]
+    return fac * Kt[:Mp, :Mp, :Mp] * (g.alpha / math.pi) ** 3 * g.h ** 3 / g.n ** 3
+
+
+def test_precompute_cache_scales_the_transform():
+    """Plans with the grid side and kernel family of an earlier plan reuse its
+    mollified transform, scaled for their own grid spacing ((h/h0)^4 biharmonic,
+    (h/h0)^2 harmonic): each multiplier still matches the oracle's, computed afresh
+    for its own geometry, and the second plan of each family is a cache hit."""
+    for fam in (["stokeslet", "stresslet", "stokeslet"], ["rotlet", "rotlet"]):
+        for i, (kernel, L) in enumerate(zip(fam, (1.0, 2.5, 0.7))):
+            before = F.precompute_cache_stats()
+            params = F.make_params(6.0 / L, 0.4 * L, 16, 8, L=L, Mt=27)  # Mt 27: no other test's grid
+            plan = _plan(kernel, "f64", params, 16)
+            try:
+                assert plan.geometry.Mt == 27
+                sig = plan.multiplier()
+                ref = _multiplier_ref(kernel, plan, params)
+            finally:
+                plan.close()
+            after = F.precompute_cache_stats()
+            assert after["hits"] + after["misses"] == before["hits"] + before["misses"] + 1
+            if i > 0:
+                assert after["hits"] == before["hits"] + 1, (kernel, L)
+            e = relmax(sig, ref)
+            print(kernel, "L", L, "multiplier error %.1e" % e, after)
+            assert e < 1e-11
+
+
 @pytest.mark.parametrize("kernel", ["stokeslet", "stresslet", "rotlet"])
 def test_stage_grids(kernel):
     """Stage by stage: the spread grid (step 1) and the scaled inverse-transformed
