@@ -216,7 +216,7 @@ fse_status_t fse_plan_grid(fse_plan_t *plan, int32_t which, double *out);
  * (h / h0)^4 or (h / h0)^2 for their grid spacing h (the truncated transform is
  * homogeneous in k and R = sqrt(3) Mt h), and skip the precompute's FFT
  * contractions.  Entries are device memory held until the process ends, 2 GiB in
- * all at most; the no-allocation entry point neither reads nor adds them.  Reports
+ * all at most; the no-allocation entry point reads them but adds none.  Reports
  * the lookups that found an entry (hits) or computed it (misses), the bytes held
  * and the entries.  Any pointer may be NULL. */
 fse_status_t fse_precompute_cache_stats(int64_t *hits, int64_t *misses, size_t *bytes, int32_t *entries);
@@ -327,7 +327,9 @@ fse_status_t fse_bounding_box(fse_dtype_t dtype, int64_t n, const void *x, void 
  * bytes it needs).  Every call on one GPU uses that GPU's one array and leaves
  * its contents there: calls that overlap on one GPU (other streams, other
  * threads) race and must be serialised by the caller.  Each call reruns the
- * FP64 precompute and synchronises `stream` (table upload and precompute).
+ * FP64 precompute, or scales a transform that an earlier plan on this GPU left in
+ * the precompute cache (fse_precompute_cache_stats), and synchronises `stream`
+ * (table upload and precompute).
  */
 #define FSE_NOALLOC_MAX_BYTES ((size_t)64 << 20)
 fse_status_t fse_eval_noalloc(fse_kernel_t kernel, fse_dtype_t dtype, const fse_params_t *params,

@@ -479,7 +479,8 @@ template <typename T> fse_status_t upload_fft_tables(fse_plan* p) {
 // biharmonic kernel (eq. BhatR) and 2 for the harmonic one (eq. HhatR).  Entries
 // are written once, never changed or freed (device memory held until the process
 // ends), up to BT_CACHE_MAX bytes in all; plans that find their entry skip the
-// fill and the six contractions.  The no-allocation entry point does not use it.
+// fill and the six contractions.  The no-allocation entry point reads entries but
+// adds none (an entry costs an allocation).
 struct BtEntry {
     int dev, Mt, family;
     double h0;
@@ -519,7 +520,8 @@ template <typename T> fse_status_t precompute(fse_plan* p) {
     const int fin_kernel = p->solver ? KSCALAR : (int)p->kernel;
     const double hpow = p->family == 0 ? 4.0 : 2.0;  // Bt's degree of homogeneity in h
     int dev = -1;
-    if (!carve) {
+    if (!p->dry) {
+        // plans look up and add entries; the no-allocation entry point only looks up
         HIPCHK(hipGetDevice(&dev));
         const double* hit = nullptr;
         double h0 = 0.0;
