@@ -661,6 +661,30 @@ __global__ __launch_bounds__(128) void k_fft_z(FftGeo fg, int Mt, int zc, C2<T>*
     }
 }
 
+// XCD-grouped block order.  Workgroups go to the 8 XCDs (each with its own L2) in
+// turn by linear block id, so the G neighbouring blocks that read parts of the
+// same 128-byte lines (a pass that moves fewer lines per workgroup than a cache
+// line holds) would each fetch those lines into a different L2.  Within every run
+// of 8 G linear ids, id j * 8 + x (XCD x, j < G) takes logical block x * G + j:
+// the G neighbours run on one XCD at about the same time.  Ids past the last full
+// run keep their place.  Returns the logical (x, y, z) block.
+template <int G> __device__ __forceinline__ void xcd_blocks(int& bx, int& by, int& bz) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int total = gx * gy * (int)gridDim.z;
+    int p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    if (G > 1 && p < total / (8 * G) * (8 * G)) {
+        const int o = p % (8 * G);
+        p = p - o + (o % 8) * G + o / 8;
+    }
+    bx = p % gx;
+    by = (p / gx) % gy;
+    bz = p / (gx * gy);
+}
+// neighbouring blocks of a pass whose workgroups move L lines of V elements
+template <typename V> constexpr int xcd_group(int L) {
+    return (int)sizeof(V) * L >= 128 ? 1 : 128 / ((int)sizeof(V) * L);
+}
+
 // ---------------------------------------------------------------------------
 // y-pass inverse: LZ lines (consecutive z) at fixed (c, kx); keep y < Mt
 // ---------------------------------------------------------------------------
@@ -676,8 +700,12 @@ __global__ __launch_bounds__(256) void k_fft_yinv(FftGeo fg, int Mt, int c_in,
     V* buf = tw + n;
     int* revinv = (int*)(buf + LZ * n);
     load_tables(tw, revinv, twg, revinvg, n);
-    const int z0 = blockIdx.x * LZ, kx = blockIdx.y;
-    const int bm = blockIdx.z / 3, c = blockIdx.z % 3;
+    // blocks in XCD-grouped order: FP64 (LZ = 2, four blocks per line) 4.11 -> 3.00 ms
+    // per step, FP32 (two per line) 0.688 -> 0.678 ms
+    int bx, by, bz;
+    xcd_blocks<xcd_group<V>(LZ)>(bx, by, bz);
+    const int z0 = bx * LZ, kx = by;
+    const int bm = bz / 3, c = bz % 3;
     const int64_t bc = (int64_t)bm * c_in + c;
     const int SY = fg.sy, SZ = fg.sz;
     const V* src = B + (bc * (Mt + 1) + kx) * n * SZ;
@@ -718,6 +746,7 @@ __global__ __launch_bounds__(256) void k_fft_xinv(FftGeo fg, int Mt, int c_in,
     V* H = buf + (ROWS / 2) * n;
     int* revinv = (int*)(H + ROWS * Mp);
     load_tables(tw, revinv, twg, revinvg, n);
+    // (the XCD-grouped order measured 1-2 % slower here, in both precisions)
     const int y0 = blockIdx.x * ROWS, z = blockIdx.y;
     const int bm = blockIdx.z / 3, c = blockIdx.z % 3;
     const int64_t bc = (int64_t)bm * c_in + c, fc = (int64_t)bm * 3 + c;

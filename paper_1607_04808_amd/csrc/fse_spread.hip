@@ -591,7 +591,18 @@ __global__ __launch_bounds__(64 * NW) void k_gather_col(GridGeo g, int KX, int s
     const int ncx = (nb + KX - 1) / KX;
     // work item: column (x fastest) then z-segment; surplus items return
     const int nwork = ncx * ncx * ((nb + segb - 1) / segb);
-    const int w = (int)blockIdx.x;
+    // work items in XCD-grouped order in FP64: each run of 32 block ids puts four
+    // neighbouring columns (which stage largely the same planes) on one XCD's L2
+    // (FP64 value and gradient passes 2.4 % faster; FP32 1-3 % slower, so it keeps
+    // the plain order)
+    int w = (int)blockIdx.x;
+    if constexpr (sizeof(T) == 8) {
+        constexpr int G = 4;
+        if (w < (int)gridDim.x / (8 * G) * (8 * G)) {
+            const int o = w % (8 * G);
+            w = w - o + (o % 8) * G + o / 8;
+        }
+    }
     if (w >= nwork) return;
     const int col = w % (ncx * ncx), seg = w / (ncx * ncx);
     const int cx = col % ncx, cy = col / ncx;
