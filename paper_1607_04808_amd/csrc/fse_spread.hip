@@ -105,6 +105,7 @@ __device__ __forceinline__ void chunk_factors(const GridGeo& g, int cnt, int lox
                                               T (*s_w)[32 + TZ], T (*s_c)[3], const int* s_bp) {
     const int P = g.P;
     const T gk = gauss_coef<T>(g.ahh);
+    const T g2 = sizeof(T) == 8 ? gauss<T>((T)2 * gk) : (T)0;  // exp(2 gk), FP64 recurrence
     const T half = (T)(0.5 * (P - 1));
     for (int q = threadIdx.x; q < cnt * 3; q += 256) {
         const int k = small_div(q, 3), d = q - 3 * k;
@@ -117,28 +118,34 @@ __device__ __forceinline__ void chunk_factors(const GridGeo& g, int cnt, int lox
         // at the magnitude of P / 2 for every node)
         const T sc = s_c[k][d], k0 = half - (T)i0;
         T* dst = &s_w[k][16 * d];
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int o = 0; o < 16; ++o) {
-            if (o >= TZ && d == 2) break;
-            const T e = sc + (k0 - (T)o);
-            const T w = gauss<T>(gk * e * e);
-            dst[o] = (unsigned)(i0 + o) < (unsigned)P ? w : (T)0;  // 0 <= i0 + o < P
+            for (int o = 0; o < 16; ++o) {
+                if (o >= TZ && d == 2) break;
+                const T e = sc + (k0 - (T)o);
+                const T w = gauss<T>(gk * e * e);
+                dst[o] = (unsigned)(i0 + o) < (unsigned)P ? w : (T)0;  // 0 <= i0 + o < P
+            }
+        } else {
+            // FP64: two exponentials per point and direction, the rest by the
+            // recurrence of fast Gaussian gridding: with e(o) = e(o - 1) - 1,
+            // g(o + 1) = g(o) r(o), r(o) = exp(gk (1 - 2 e(o))), r(o + 1) = r(o) exp(2 gk),
+            // started at the window's first node inside the core (inside the window
+            // |e| <= P/2, so nothing underflows; 2 o + 2 roundings, ~4e-15 relative)
+            const int os = i0 < 0 ? -i0 : 0;
+            const T es = sc + (k0 - (T)os);
+            T w = gauss<T>(gk * es * es);
+            T r = gauss<T>(gk * ((T)1 - (T)2 * es));
+#pragma unroll
+            for (int o = 0; o < 16; ++o) {
+                if (o >= TZ && d == 2) break;
+                dst[o] = (unsigned)(i0 + o) < (unsigned)P ? w : (T)0;  // 0 <= i0 + o < P
+                const bool adv = o >= os;
+                w = adv ? w * r : w;
+                r = adv ? r * g2 : r;
+            }
         }
     }
-}
-
-// Load, stage and factor the chunk of points [base, min(j1, base + CH)).
-template <typename T, int NC, int TZ, int CH>
-__device__ __forceinline__ int stage_chunk(const GridGeo& g, int lox, int loy, int loz, int base, int j1,
-                                           int bm, int64_t n, const int* __restrict__ bpack_s,
-                                           const T* __restrict__ coff_s, const T* __restrict__ src_s,
-                                           T (*s_w)[32 + TZ], T (*s_c)[3], T (*s_v)[NC], int* s_bp,
-                                           int* s_wc) {
-    ChunkPoint<T, NC> pt;
-    load_point<T, NC, CH>(pt, base, j1, bm, n, bpack_s, coff_s, src_s);
-    const int cnt = stage_points<T, NC, TZ>(pt, g.P, lox, loy, loz, s_c, s_v, s_bp, s_wc);
-    chunk_factors<T, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
-    return cnt;
 }
 
 // Output-stationary spreading.  The workgroup (256 threads) owns a 16 x 16 x TZ
@@ -190,68 +197,87 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     const int bx0 = max(0, lox - P + 1) / TB, bx1 = min(Mt - P, lox + 15) / TB;
     const int by0 = max(0, loy - P + 1) / TB, by1 = min(Mt - P, loy + 15) / TB;
     const int bz0 = max(0, loz - P + 1) / TB, bz1 = min(Mt - P, loz + TZ - 1) / TB;
-    for (int sz = bz0; sz <= bz1; ++sz)
-        for (int sy = by0; sy <= by1; ++sy) {
-            const int row = (sz * nb + sy) * nb;
-            const int j0 = tile_start[row + bx0], j1 = tile_start[row + bx1 + 1];
-            for (int base = j0; base < j1; base += CH) {
-                const int cnt = stage_chunk<T, NC, TZ, CH>(g, lox, loy, loz, base, j1, bm, n, bpack_s, coff_s,
-                                                           src_s, s_w, s_c, s_v, s_bp, s_wc);
-                // this wave's list: the staged points whose window reaches its 8 x 8 tile
-                int nl = 0;
-                for (int k0 = 0; k0 < cnt; k0 += 64) {
-                    const int k = k0 + lane;
-                    bool hit = false;
-                    unsigned zm = 0;  // groups of 4 core z-nodes the window meets
-                    if (k < cnt) {
-                        const int bp = s_bp[k];
-                        const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
-                        hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
-                                by + P <= loy + wy0);
-                        const int zlo = max(bz, loz) - loz, zhi = min(bz + P, loz + TZ) - loz;
-#pragma unroll
-                        for (int z4 = 0; z4 < TZ; z4 += 4)
-                            if (z4 < zhi && z4 + 4 > zlo) zm |= 1u << (z4 / 4);
-                    }
-                    const unsigned long long m = __ballot(hit);
-                    if (hit)
-                        s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)(k | (zm << 8));
-                    nl += __popcll(m);
-                }
-                __syncthreads();
-                // list entries come 64 at a time, one per lane, and are read from the
-                // lanes as the wave visits them (no LDS round trip per visit)
-                for (int l0 = 0; l0 < nl; l0 += 64) {
-                  const int mine = l0 + lane < nl ? (int)s_list[wid][l0 + lane] : 0;
-                  const int cl = min(64, nl - l0);
-                  for (int li = 0; li < cl; ++li) {
-                    const int ent = __builtin_amdgcn_readlane(mine, li);
-                    const int k = ent & 255;
-                    const unsigned zm = (unsigned)ent >> 8;
-                    const T wxy = s_w[k][tx] * s_w[k][16 + ty];
-                    T v[NC];
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) v[c] = s_v[k][c];
-                    T wz[TZ];
-#pragma unroll
-                    for (int z = 0; z < TZ; ++z) wz[z] = s_w[k][32 + z];
-                    // z in groups of 4 that meet the window (the factors are zero outside it)
-#pragma unroll
-                    for (int z4 = 0; z4 < TZ; z4 += 4) {
-                        if (zm & (1u << (z4 / 4))) {
-#pragma unroll
-                            for (int z = z4; z < z4 + 4; ++z) {
-                                const T w = wxy * wz[z];
-#pragma unroll
-                                for (int c = 0; c < NC; ++c) acc[z][c] += w * v[c];
-                            }
-                        }
-                    }
-                  }
-                }
-                __syncthreads();
-            }
+    // The chunks run as one sequence over the bin rows (sz, sy), row r = (sz - bz0)
+    // nry + sy - by0, each row's range cut into chunks of CH; the next chunk's range
+    // and points are loaded while the current one is processed (as in k_spread_mfma)
+    const int nry = by1 - by0 + 1, nrows = (nry > 0 && bz1 >= bz0) ? (bz1 - bz0 + 1) * nry : 0;
+    auto find_row = [&](int r, int& jb, int& je) {
+        for (; r < nrows; ++r) {
+            const int rz = r / nry;
+            const int row = ((bz0 + rz) * nb + by0 + (r - rz * nry)) * nb;
+            jb = tile_start[row + bx0];
+            je = tile_start[row + bx1 + 1];
+            if (jb < je) break;
         }
+        return r;
+    };
+    int r = 0, base = 0, end = 0;
+    r = find_row(0, base, end);
+    ChunkPoint<T, NC> pt;
+    if (r < nrows) load_point<T, NC, CH>(pt, base, end, bm, n, bpack_s, coff_s, src_s);
+    while (r < nrows) {
+        const int cnt = stage_points<T, NC, TZ>(pt, P, lox, loy, loz, s_c, s_v, s_bp, s_wc);
+        int nr = r, nbase = base + CH, nend = end;
+        if (nbase >= end) nr = find_row(r + 1, nbase, nend);
+        if (nr < nrows) load_point<T, NC, CH>(pt, nbase, nend, bm, n, bpack_s, coff_s, src_s);
+        chunk_factors<T, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
+        // this wave's list: the staged points whose window reaches its 8 x 8 tile
+        int nl = 0;
+        for (int k0 = 0; k0 < cnt; k0 += 64) {
+            const int k = k0 + lane;
+            bool hit = false;
+            unsigned zm = 0;  // groups of 4 core z-nodes the window meets
+            if (k < cnt) {
+                const int bp = s_bp[k];
+                const int bx = bp & 1023, by = (bp >> 10) & 1023, bz = bp >> 20;
+                hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
+                        by + P <= loy + wy0);
+                const int zlo = max(bz, loz) - loz, zhi = min(bz + P, loz + TZ) - loz;
+#pragma unroll
+                for (int z4 = 0; z4 < TZ; z4 += 4)
+                    if (z4 < zhi && z4 + 4 > zlo) zm |= 1u << (z4 / 4);
+            }
+            const unsigned long long m = __ballot(hit);
+            if (hit)
+                s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)(k | (zm << 8));
+            nl += __popcll(m);
+        }
+        __syncthreads();
+        // list entries come 64 at a time, one per lane, and are read from the
+        // lanes as the wave visits them (no LDS round trip per visit)
+        for (int l0 = 0; l0 < nl; l0 += 64) {
+          const int mine = l0 + lane < nl ? (int)s_list[wid][l0 + lane] : 0;
+          const int cl = min(64, nl - l0);
+          for (int li = 0; li < cl; ++li) {
+            const int ent = __builtin_amdgcn_readlane(mine, li);
+            const int k = ent & 255;
+            const unsigned zm = (unsigned)ent >> 8;
+            const T wxy = s_w[k][tx] * s_w[k][16 + ty];
+            T v[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c] = s_v[k][c];
+            T wz[TZ];
+#pragma unroll
+            for (int z = 0; z < TZ; ++z) wz[z] = s_w[k][32 + z];
+            // z in groups of 4 that meet the window (the factors are zero outside it)
+#pragma unroll
+            for (int z4 = 0; z4 < TZ; z4 += 4) {
+                if (zm & (1u << (z4 / 4))) {
+#pragma unroll
+                    for (int z = z4; z < z4 + 4; ++z) {
+                        const T w = wxy * wz[z];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) acc[z][c] += w * v[c];
+                    }
+                }
+            }
+          }
+        }
+        __syncthreads();
+        r = nr;
+        base = nbase;
+        end = nend;
+    }
     if (gx < Mt && gy < Mt) {
         const int64_t M3 = (int64_t)Mt * Mt * Mt;
 #pragma unroll
