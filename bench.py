@@ -49,8 +49,10 @@ def cube_pair_cdf(r):
     return 4 * math.pi / 3 * r ** 3 - 1.5 * math.pi * r ** 4 + 1.6 * r ** 5 - r ** 6 / 6
 
 
-def stage_work(stage, geo, n, P, dtype, pairs, c_in=3, batch=1):
-    """Algorithmic (bytes, flops) of one launch group of a stage."""
+def stage_work(stage, geo, n, P, dtype, pairs, c_in=3, batch=1, fused=False):
+    """Algorithmic (bytes, flops) of one launch group of a stage.  fused: the stage
+    groups of fse_eval_with_adjoint (one spread of both source sets; the forward
+    quadrature inside gather_grad; the forward real-space pairs inside real_grad)."""
     s = 4 if dtype == "f32" else 8
     Mt, nf = geo.Mt, geo.n_fft
     Mp = Mt + 1
@@ -68,15 +70,17 @@ def stage_work(stage, geo, n, P, dtype, pairs, c_in=3, batch=1):
         return batch * 3 * (Mp * Mt * Mt * 2 * s + M3 * s), None
     if stage == "spread":
         # per point and window node: 1 weight product + c_in multiply-adds
+        if fused:
+            return 2 * nc * M3 * s + n * 7 * s, n * P ** 3 * (1 + 2 * 2 * c_in) * batch
         return nc * M3 * s + n * 4 * s, n * P ** 3 * (1 + 2 * c_in) * batch
     if stage == "gather":
         return batch * 3 * M3 * s + n * 4 * s, n * P ** 3 * (2 + 2 * 3) * batch
     if stage == "gather_grad":
-        return 2 * batch * 3 * M3 * s, n * P ** 3 * batch * (2 + 12 + 6 + 6 + 6)
+        return 2 * batch * 3 * M3 * s, n * P ** 3 * batch * (2 + 12 + 6 + 6 + 6 + (8 if fused else 0))
     if stage in ("real", "real_grad"):
         # per interacting pair: r^2 (5), sqrt+div (2), exp (1), erfc (1), coefficients and
         # the 3x3 application (~25): counted as 34 flops; gradients about twice that
-        per = 34 if stage == "real" else 70
+        per = 34 if stage == "real" else (104 if fused else 70)
         return None, pairs * per * batch
     return None, None
 
@@ -84,11 +88,11 @@ def stage_work(stage, geo, n, P, dtype, pairs, c_in=3, batch=1):
 # Kernels behind each timed stage (FP32 / FP64 template names as rocprofv3 lists them)
 # and the sources that define them, for the counter-based HBM traffic.
 STAGE_KERNELS = {
-    "real": (["k_real<{T}, 0, 1, false, false>"], "fse_real.hip"),
-    "real_grad": (["k_real<{T}, 0, 1, true, true>"], "fse_real.hip"),
-    "spread": (["k_spread<{T}, 3,", "k_spread_mfma<3,"], "fse_spread.hip"),
+    "real": (["k_real<{T}, 0, 1, false, false,"], "fse_real.hip"),
+    "real_grad": (["k_real<{T}, 0, 1, true, true,"], "fse_real.hip"),
+    "spread": (["k_spread<{T}, 3,", "k_spread_mfma<3,", "k_spread<{T}, 6,", "k_spread_mfma<6,"], "fse_spread.hip"),
     "gather": (["k_gather_col<{T}, 0, "], "fse_spread.hip"),
-    "gather_grad": (["k_gather_col<{T}, 1, ", "k_gather_col<{T}, 2, "], "fse_spread.hip"),
+    "gather_grad": (["k_gather_col<{T}, 1, ", "k_gather_col<{T}, 2, ", "k_gather_col<{T}, 3, "], "fse_spread.hip"),
     "fft_x": (["k_fft_x<{T},"], "fse_fft.hip"),
     "fft_y": (["k_fft_y<{T},"], "fse_fft.hip"),
     "fft_z_scale": (["k_fft_z<{T}, 0, 3,", "k_fft_zb<{T}, 0,"], "fse_fft.hip"),
@@ -255,37 +259,43 @@ def main():
         plan.set_points(x, validate=True)
         geo = plan.geometry
 
-        def step(adjoint=True):
+        # the timed step: binning, then u = K f, dL/df = K w and dL/dx in one call
+        # (fse_eval_with_adjoint); "separate": fse_eval then fse_eval_adjoint reusing
+        # the forward field (as torch.autograd does); "forward": fse_eval alone
+        def step(kind="fused"):
             plan.set_points(x, validate=False)
+            if kind == "fused":
+                return plan.eval_with_adjoint(f, w)
             u = plan.eval(f)
-            if adjoint:
+            if kind == "separate":
                 df, dx = plan.adjoint(f, w, recompute=False)
                 return u, df, dx
             return u, None, None
 
+        def timed(kind):
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                out = step(kind)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.steps, out
+
         for _ in range(args.warmup):
             step()
+            step("separate")
         torch.cuda.synchronize()
         plan.timings()
         plan.set_timing(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            u, df, dx = step()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
+        ms, (u, df, dx) = timed("fused")
         stages = plan.timings()
         plan.set_timing(False)
-        # forward-only rate
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            step(adjoint=False)
-        e1.record()
-        torch.cuda.synchronize()
-        ms_fwd = e0.elapsed_time(e1) / args.steps
+        ms_sep, (u_s, df_s, dx_s) = timed("separate")
+        ms_fwd, _ = timed("forward")
+        # the fused and the separate calls agree to rounding
+        agree = max(float((a - b).abs().max() / b.abs().max()) for a, b in ((u, u_s), (df, df_s), (dx, dx_s)))
+        del u_s, df_s, dx_s
         if batched:
             # two members for the sampled error check
             outputs[form] = (u.cpu().numpy()[:2], df.cpu().numpy()[:2], fb[:2], wb[:2])
@@ -316,13 +326,16 @@ def main():
             if cnt == 0:
                 continue
             per = tot / cnt
-            b, fl = stage_work(name, geo, n, prm["P"], dform, pairs / 1.0, batch=nb)
+            b, fl = stage_work(name, geo, n, prm["P"], dform, pairs / 1.0, batch=nb, fused=True)
             # launches per step of this stage (e.g. two spreads per forward+adjoint step)
             stage_tab[name] = dict(ms_per_step=tot / args.steps, ms_per_launch=per, launches=cnt,
                                    GBs=(b / per / 1e6 if b else None),
                                    TFLOPs=(fl / per / 1e9 if fl else None))
         results[form] = dict(params=dict(prm, Mt=geo.Mt, n_fft=geo.n_fft, eta=round(geo.eta, 4), L=L_BOX),
                              ms_per_step=ms, ms_forward=ms_fwd, targets_per_s=n / (ms / 1e3),
+                             ms_per_step_separate_calls=ms_sep,
+                             targets_per_s_separate_calls=n / (ms_sep / 1e3),
+                             fused_vs_separate_max_rel_diff=float("%.2e" % agree),
                              forward_targets_per_s=n / (ms_fwd / 1e3), plan_seconds=t_plan,
                              workspace_GB=plan.workspace_bytes() / 1e9, stages=stage_tab)
         if batched:
@@ -365,9 +378,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "stokeslet sum, N=%d points uniform in [0,1)^3, f and w i.i.d. N(0,1), "
                                "forward + adjoint (dL/df, dL/dx), %s form" % (n, head_form),
-                   "n": n, "kernel": "stokeslet", "params": head["params"]},
+                   "n": n, "kernel": "stokeslet", "params": head["params"],
+                   "step": "fse_set_points + fse_eval_with_adjoint (u, dL/df and dL/dx in one call); "
+                           "forms.*.ms_per_step_separate_calls: fse_eval then fse_eval_adjoint"},
         "roofline": roof,
-        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items() if kk != "stages"}
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) and not kk.endswith("_diff") else vv)
+                      for kk, vv in v.items() if kk != "stages"}
                   for k, v in results.items()},
         "stages": {k: v["stages"] for k, v in results.items()},
     }

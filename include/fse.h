@@ -185,6 +185,22 @@ fse_status_t fse_eval_adjoint(fse_plan_t *plan, const void *src_a, const void *w
                               void *dx, int32_t recompute);
 
 /*
+ * Forward sum and adjoint in one call, for L = sum_m w_m . u(x_m) with w known
+ * beforehand (stokeslet and rotlet plans; Sections 3 and 5 as fse_eval and
+ * fse_eval_adjoint): u = the sum of fse_eval, dsrc = dL/da = K w and dx = dL/dx,
+ * each laid out as there, all three required (device pointers, the plan's dtype).
+ * The two source sets are spread in one pass, the forward quadrature and the first
+ * gradient term share one sweep of the forward field, and (batch 1) one pass over
+ * the real-space pairs adds u^R + self term, the real part of K w and its part of
+ * dL/dx.  The results equal those of fse_eval followed by fse_eval_adjoint to
+ * rounding.  Afterwards the forward field is kept as after fse_eval.
+ * FSE_EUNSUPPORTED for stresslet and periodic plans; FSE_ESTATE before
+ * fse_set_points.
+ */
+fse_status_t fse_eval_with_adjoint(fse_plan_t *plan, const void *src_a, const void *w, void *u, void *dsrc,
+                                   void *dx);
+
+/*
  * Adjoint of fse_eval for the stresslet (eq. def_stresslet), L = sum_m w_m .
  * u(x_m) with u_j(x_m) = sum_{n != m} T_jlm(x_m - x_n) q_l(n) n_m(n): at each
  * point b, D_lm = sum_{a != b} w_j(a) T_jlm(x_a - x_b) (T fully symmetric, so D
@@ -365,10 +381,11 @@ fse_status_t fse_plan_set_tuning(fse_plan_t *plan, const fse_tuning_t *tuning);
 /*
  * Autotune the plan on its workload: for the n points x and sources (src_a,
  * src_b as fse_eval) and, when w != NULL (stokeslet and rotlet), the adjoint
- * weights, time `repeats` runs of fse_set_points + fse_eval (+ fse_eval_adjoint)
- * with HIP events for each candidate of each knob in turn (bin side, real-space
- * waves, then the two queue depths), keep the fastest, and leave the plan with
- * it and the points set.  *best (may be NULL) receives the tuning.  Allocates
+ * weights, time `repeats` runs of fse_set_points + fse_eval (with w:
+ * fse_eval_with_adjoint; periodic plans fse_eval + fse_eval_adjoint) with HIP
+ * events for each candidate of each knob in turn (bin side, real-space waves,
+ * the two queue depths, the FFT line cap), keep the fastest, and leave the plan
+ * with it and the points set.  *best (may be NULL) receives the tuning.  Allocates
  * temporary outputs and synchronises the stream.
  */
 fse_status_t fse_plan_autotune(fse_plan_t *plan, int64_t n, const void *x, const void *src_a, const void *src_b,

@@ -4,8 +4,9 @@ write the table that Plan() loads (tuning.json beside this file).
     python -m paper_1607_04808_amd.autotune [--out PATH] [--repeats R] [--only NAME ...]
 
 Each workload is the seeded synthetic input of a measured configuration; the
-timed unit is one set_points + eval (+ adjoint where the configuration has one)
-on a plan with exactly that configuration's parameters.  Runs on the GPU.
+timed unit is one set_points + eval, or set_points + eval_with_adjoint where the
+configuration has an adjoint, on a plan with exactly that configuration's
+parameters.  Runs on the GPU.
 """
 from __future__ import annotations
 
@@ -90,9 +91,10 @@ def tune(name, repeats=3):
             t0 = time.time()
             for _ in range(reps):
                 plan.set_points(xt, validate=False)
-                plan.eval(at, bt)
                 if adjoint:
-                    plan.adjoint(at, wt, recompute=False)
+                    plan.eval_with_adjoint(at, wt)
+                else:
+                    plan.eval(at, bt)
             torch.cuda.synchronize()
             return (time.time() - t0) / reps * 1e3
 

@@ -810,6 +810,8 @@ template <typename T> PointsDev<T> source_target_points(const fse_plan* p) {
 
 // spread -> FFT -> scale -> IFFT into `field` (periodic: spread onto the
 // extended grid and fold it onto the period first)
+template <typename T> void fft_chain(fse_plan* p, const T* grid, T* field);
+
 template <typename T> void fourier_chain(fse_plan* p, const T* src_s, T* field) {
     hipStream_t st = p->stream;
     PointsDev<T> pd = points<T>(p);
@@ -822,12 +824,21 @@ template <typename T> void fourier_chain(fse_plan* p, const T* src_s, T* field) 
         TimedStage ts(tm, ST_SPREAD, st);
         launch_spread<T>(p->gg, pd, src_s, p->c_in, p->batch, (T*)p->grid, st);
     }
+    fft_chain<T>(p, (const T*)p->grid, field);
+}
+
+// Steps 2-4 of Section 5.2 on a spread grid: forward transforms, the scaling, the
+// inverse transforms into field (which may be the grid itself: the first pass has
+// read all of it before the last one writes).
+template <typename T> void fft_chain(fse_plan* p, const T* grid, T* field) {
+    hipStream_t st = p->stream;
+    Timer& tm = p->timer;
     { TimedStage ts(tm, ST_FFTX, st);
-      launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
-                            p->rev, p->revinv, st, 1); }
+      launch_fft_forward<T>(p->fg, p->gf, grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw, p->rev,
+                            p->revinv, st, 1); }
     { TimedStage ts(tm, ST_FFTY, st);
-      launch_fft_forward<T>(p->fg, p->gf, (const T*)p->grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw,
-                            p->rev, p->revinv, st, 2); }
+      launch_fft_forward<T>(p->fg, p->gf, grid, p->A, p->B, p->batch * p->c_in, (const T*)p->tw, p->rev,
+                            p->revinv, st, 2); }
     { TimedStage ts(tm, ST_FFTZ, st);
       launch_fft_zscale<T>(p->fg, p->gf, (int)p->kernel, p->B, p->c_in, p->batch, (const T*)p->sig,
                            PI / p->geo.Lt, (const T*)p->tw, p->rev, p->revinv, st); }
@@ -949,6 +960,45 @@ fse_status_t adjoint_t(fse_plan* p, const T* f, const T* w, T* dsrc, T* dx, int 
         TimedStage ts(tm, ST_REAL, st);
         launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->adj_r, nullptr, p->batch, p->prm.xi,
                        self_coef(p), dsrc, 1, st);
+    }
+    LAUNCHCHK();
+    return FSE_OK;
+}
+
+// Forward sum and adjoint together, for L = sum_m w_m . u(x_m) with w known: f and
+// w spread in one pass (six components, into the forward grid and phi_w), the two
+// transform chains, the forward quadrature with the first gradient term in one
+// sweep and the second with K w's quadrature, then (one batch member) one pass over
+// the pairs for u^R + self, the real part of K w and dL/dx.
+template <typename T>
+fse_status_t eval_with_adjoint_t(fse_plan* p, const T* f, const T* w, T* u, T* dsrc, T* dx) {
+    hipStream_t st = p->stream;
+    const int64_t n = p->n;
+    const int B = p->batch;
+    PointsDev<T> pd = points<T>(p);
+    Timer& tm = p->timer;
+    {
+        TimedStage ts(tm, ST_PERMUTE, st);
+        launch_permute_sources<T>((int)p->kernel, f, nullptr, n, B, p->perm_s, (T*)p->src_s, st);
+        launch_permute3<T>(f, n, B, p->perm_r, (T*)p->src_ra, st);
+        launch_permute3<T>(w, n, B, p->perm_s, (T*)p->adj_s, st);
+        launch_permute3<T>(w, n, B, p->perm_r, (T*)p->adj_r, st);
+    }
+    { TimedStage ts(tm, ST_SPREAD, st);
+      launch_spread<T>(p->gg, pd, (const T*)p->src_s, 6, B, (T*)p->grid, st, (const T*)p->adj_s, (T*)p->phi_w); }
+    fft_chain<T>(p, (const T*)p->grid, (T*)p->phi);
+    fft_chain<T>(p, (const T*)p->phi_w, (T*)p->phi_w);
+    p->forward_valid = true;
+    { TimedStage ts(tm, ST_GGRAD, st);
+      launch_gather_fused<T>(p->gg, pd, (const T*)p->phi, (const T*)p->phi_w, (const T*)p->src_s,
+                             (const T*)p->adj_s, B, u, dsrc, dx, st); }
+    {
+        TimedStage ts(tm, ST_RGRAD, st);
+        if (B > 1)
+            launch_real<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, nullptr, B, p->prm.xi, self_coef(p), u,
+                           1, st);
+        launch_real_grad<T>((int)p->kernel, p->cg, pd, (const T*)p->src_ra, (const T*)p->adj_r, B, p->prm.xi,
+                            self_coef(p), dx, dsrc, st, B == 1 ? u : nullptr);
     }
     LAUNCHCHK();
     return FSE_OK;
@@ -1193,8 +1243,12 @@ fse_status_t time_workload(fse_plan* p, int64_t n, const T* x, const T* a, const
     for (int r = -1; r < repeats && rc == FSE_OK; ++r) {  // r = -1: warm-up
         if (r == 0) (void)hipEventRecord(e0, p->stream);
         rc = set_points_t<T>(p, n, x, 0);
-        if (rc == FSE_OK) rc = eval_t<T>(p, a, b, u, nullptr, true);
-        if (rc == FSE_OK && w) rc = adjoint_t<T>(p, a, w, ds, dx, 0);
+        if (rc == FSE_OK && w && !p->periodic && p->kernel != FSE_STRESSLET) {
+            rc = eval_with_adjoint_t<T>(p, a, w, u, ds, dx);  // the forward and adjoint in one call
+        } else {
+            if (rc == FSE_OK) rc = eval_t<T>(p, a, b, u, nullptr, true);
+            if (rc == FSE_OK && w) rc = adjoint_t<T>(p, a, w, ds, dx, 0);
+        }
     }
     if (rc == FSE_OK) {
         (void)hipEventRecord(e1, p->stream);
@@ -1403,6 +1457,21 @@ fse_status_t fse_eval_adjoint(fse_plan_t* plan, const void* a, const void* w, vo
                ? adjoint_t<float>(plan, (const float*)a, (const float*)w, (float*)dsrc, (float*)dx, recompute)
                : adjoint_t<double>(plan, (const double*)a, (const double*)w, (double*)dsrc, (double*)dx,
                                    recompute);
+}
+
+fse_status_t fse_eval_with_adjoint(fse_plan_t* plan, const void* a, const void* w, void* u, void* dsrc, void* dx) {
+    if (!plan || !a || !w || !u || !dsrc || !dx) { set_err("null argument"); return FSE_EINVAL; }
+    if (plan->periodic) { set_err("not implemented for the periodic sum"); return FSE_EUNSUPPORTED; }
+    if (plan->kernel == FSE_STRESSLET) {
+        set_err("stokeslet and rotlet plans only (the stresslet adjoint is fse_eval_adjoint_stresslet)");
+        return FSE_EUNSUPPORTED;
+    }
+    if (plan->n == 0) { set_err("fse_set_points must come first"); return FSE_ESTATE; }
+    return plan->dtype == FSE_F32
+               ? eval_with_adjoint_t<float>(plan, (const float*)a, (const float*)w, (float*)u, (float*)dsrc,
+                                            (float*)dx)
+               : eval_with_adjoint_t<double>(plan, (const double*)a, (const double*)w, (double*)u, (double*)dsrc,
+                                             (double*)dx);
 }
 
 fse_status_t fse_eval_adjoint_stresslet(fse_plan_t* plan, const void* q, const void* nrm, const void* w, void* dq,

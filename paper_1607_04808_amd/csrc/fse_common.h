@@ -231,9 +231,11 @@ void launch_unfold(const T* field, int M, int Me, int s, int ncomp, T* ext, hipS
 template <typename T>
 void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, hipStream_t st);
 
+// src2 / grid2 (c_in = 6): two 3-component source sets spread together, the first
+// into grid and the second into grid2 (3 components per batch member each)
 template <typename T>
 void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int c_in, int batch,
-                   T* grid, hipStream_t st);
+                   T* grid, hipStream_t st, const T* src2 = nullptr, T* grid2 = nullptr);
 // bin side (grid points) of the point binning for the element size and P
 int bin_side(int elem_bytes, int P);
 template <typename T>
@@ -242,6 +244,9 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
 template <typename T>
 void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f, const T* phi_w,
                         const T* f_s, const T* w_s, int batch, T* dsrc, T* dx, hipStream_t st);
+template <typename T>
+void launch_gather_fused(const GridGeo& g, const PointsDev<T>& p, const T* phi_f, const T* phi_w,
+                         const T* f_s, const T* w_s, int batch, T* u, T* dsrc, T* dx, hipStream_t st);
 
 // Grid sides the FFT passes take: whether every pass fits in LDS at Mt, and the
 // largest Mt <= 1024 that does for a kernel (FSE_STRESSLET: six grid components)
@@ -269,7 +274,8 @@ template <typename T>
 // dx += real-space gradient; when dsrc is given, also dsrc += the real-space
 // part of K w (with the self term) in the same pass
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
-                      int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st);
+                      int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st,
+                      T* u = nullptr);  // u: with dsrc and batch 1, also u += u^R + self term
 
 // dq += D^R n, dn += D^R q with D^R_lm(t) = sum_s T^R_jlm(x_s - x_t) w_j(s), the
 // real-space part of the stresslet adjoint (q_r, n_r, w_r in real-space order)

@@ -171,11 +171,13 @@ struct __align__(4 * sizeof(T)) Pos4 {
 //   GRAD = true:  out(dx) += sum_b sum_pairs grad_r[w_t . G^R f_s + sgn w_s . G^R f_t]
 //   WVAL (with GRAD): also out2 += sum_pairs G^R w_s + self_coef w_t per batch
 //                 member (the real-space part of dL/df = K w), in the same pass
-template <typename T, int KERNEL, int NB, bool GRAD, bool WVAL = false>
+//   FVAL (with GRAD): also out3 += sum_pairs G^R f_s + self_coef f_t (the forward
+//                 sum u's real-space part and self term), in the same pass
+template <typename T, int KERNEL, int NB, bool GRAD, bool WVAL = false, bool FVAL = false>
 __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const T* __restrict__ a_r,
                                              const T* __restrict__ b_r, const T* __restrict__ w_r,
                                              int batch, T xi, T self_coef, T* out, int accumulate,
-                                             T* out2) {
+                                             T* out2, T* out3) {
     // sources: the cell list of the points; targets: their own cell list (the
     // same one when the targets are the sources; GRAD needs that)
     const int* __restrict__ cell_start = pd.cell_start;
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
     const int* __restrict__ work_start = pd.t_work_start;
     constexpr bool TADJ = KERNEL == KTADJ;  // the stresslet adjoint: sources carry w, targets q and n
     constexpr int NS = TADJ ? 3 : ((KERNEL == FSE_STRESSLET || GRAD) ? 6 : 3);  // staged values per source
-    constexpr int NO = TADJ ? 6 : 3;  // accumulated values per target and batch member
+    constexpr int NO = (TADJ || FVAL) ? 6 : 3;  // accumulated values per target and batch member
     // source slots per LDS chunk
     constexpr int CH = real_chunk<T>();
     static_assert(CH % 8 == 0, "candidates are tested in groups of 8");
@@ -456,12 +458,18 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                         const T wr2 = wn[0] * rv[0] + wn[1] * rv[1] + wn[2] * rv[2];
                         const T fr2 = fp[0] * rv[0] + fp[1] * rv[1] + fp[2] * rv[2];
                         const T rad = (da * (wf1 + sgn * wf2) + dB * (wr1 * fr1 + sgn * wr2 * fr2)) * ir;
+                        const T a_ = ec * ir - c2x * e;
                         if constexpr (WVAL) {
-                            const T a_ = ec * ir - c2x * e;
                             const T bw = Bc * wr2;
                             acc[b][0] += a_ * wn[0] + bw * rv[0];
                             acc[b][1] += a_ * wn[1] + bw * rv[1];
                             acc[b][2] += a_ * wn[2] + bw * rv[2];
+                        }
+                        if constexpr (FVAL) {
+                            const T bf = Bc * fr1;
+                            acc[b][3] += a_ * fn[0] + bf * rv[0];
+                            acc[b][4] += a_ * fn[1] + bf * rv[1];
+                            acc[b][5] += a_ * fn[2] + bf * rv[2];
                         }
                         g0 += rad * rv[0] + Bc * (wp[0] * fr1 + fn[0] * wr1 + sgn * (wn[0] * fr2 + fp[0] * wr2));
                         g1 += rad * rv[1] + Bc * (wp[1] * fr1 + fn[1] * wr1 + sgn * (wn[1] * fr2 + fp[1] * wr2));
@@ -487,6 +495,11 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                             acc[b][0] += psi * (wn[1] * rv[2] - wn[2] * rv[1]);
                             acc[b][1] += psi * (wn[2] * rv[0] - wn[0] * rv[2]);
                             acc[b][2] += psi * (wn[0] * rv[1] - wn[1] * rv[0]);
+                        }
+                        if constexpr (FVAL) {
+                            acc[b][3] += psi * (fn[1] * rv[2] - fn[2] * rv[1]);
+                            acc[b][4] += psi * (fn[2] * rv[0] - fn[0] * rv[2]);
+                            acc[b][5] += psi * (fn[0] * rv[1] - fn[1] * rv[0]);
                         }
                         g0 += rc * rv[0] + psi * cc0;
                         g1 += rc * rv[1] + psi * cc1;
@@ -736,6 +749,16 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                         for (int d = 0; d < 3; ++d) o[d] = (T)((S)o[d] + sum[b][d] + (S)(self_coef * wt[b][d]));
                     }
                 }
+                if constexpr (FVAL) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        if (b0 + b >= batch) break;
+                        T* o = out3 + ((int64_t)(b0 + b) * n + i) * 3;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d)
+                            o[d] = (T)((S)o[d] + sum[b][3 + d] + (S)(self_coef * ft[b][d]));
+                    }
+                }
             }
         }
     }
@@ -778,7 +801,7 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
     dim3 grd(items, (batch + NBc - 1) / NBc);
 #define LAUNCH(K, NB)                                                                                     \
     hipLaunchKernelGGL((k_real<T, K, NB, false>), grd, dim3(thr), qbytes, st, c, p, src_a_r, src_b_r,        \
-                       (const T*)nullptr, batch, (T)xi, (T)self_coef, u, accumulate, (T*)nullptr)
+                       (const T*)nullptr, batch, (T)xi, (T)self_coef, u, accumulate, (T*)nullptr, (T*)nullptr)
     if (kernel == FSE_STOKESLET) {
         if (NBc == 1) LAUNCH(FSE_STOKESLET, 1); else LAUNCH(FSE_STOKESLET, 4);
     } else if (kernel == FSE_ROTLET) {
@@ -791,7 +814,9 @@ void launch_real(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* s
 
 template <typename T>
 void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const T* f_r, const T* w_r,
-                      int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st) {
+                      int batch, double xi, double self_coef, T* dx, T* dsrc, hipStream_t st, T* u) {
+    // u (with dsrc, batch 1 only; ignored otherwise): the forward sum's real part and
+    // self term are added to u in the same pass over the pairs
     const unsigned ncells = (unsigned)c.ncell * c.ncell * c.ncell;
     const unsigned thr = (unsigned)p.real_S;
     const unsigned items = (unsigned)((p.n + thr - 1) / thr + ncells);
@@ -802,12 +827,14 @@ void launch_real_grad(int kernel, const CellGeo& c, const PointsDev<T>& p, const
         const T* f = f_r + (int64_t)b0 * p.n * 3;
         const T* w = w_r + (int64_t)b0 * p.n * 3;
         T* ds = dsrc ? dsrc + (int64_t)b0 * p.n * 3 : nullptr;
-#define LAUNCHG(K, NB, WV)                                                                                \
-        hipLaunchKernelGGL((k_real<T, K, NB, true, WV>), dim3(items), dim3(thr), qbytes, st, c, p, f,          \
-                           (const T*)nullptr, w, nb, (T)xi, (T)self_coef, dx, 1, ds)
+        T* uo = (u && batch == 1) ? u : nullptr;
+#define LAUNCHG(K, NB, WV, FV)                                                                            \
+        hipLaunchKernelGGL((k_real<T, K, NB, true, WV, FV>), dim3(items), dim3(thr), qbytes, st, c, p, f,      \
+                           (const T*)nullptr, w, nb, (T)xi, (T)self_coef, dx, 1, ds, uo)
 #define LAUNCHK(K)                                                                                        \
-        if (ds) { if (nb == 1) LAUNCHG(K, 1, true); else LAUNCHG(K, 4, true); }                           \
-        else { if (nb == 1) LAUNCHG(K, 1, false); else LAUNCHG(K, 4, false); }
+        if (ds && uo && nb == 1) LAUNCHG(K, 1, true, true);                                               \
+        else if (ds) { if (nb == 1) LAUNCHG(K, 1, true, false); else LAUNCHG(K, 4, true, false); }        \
+        else { if (nb == 1) LAUNCHG(K, 1, false, false); else LAUNCHG(K, 4, false, false); }
         if (kernel == FSE_STOKESLET) {
             LAUNCHK(FSE_STOKESLET)
         } else {
@@ -827,7 +854,7 @@ void launch_real_tadj(const CellGeo& c, const PointsDev<T>& p, const T* q_r, con
     const size_t qbytes = queue_bytes<T>(c.qcap, thr, 1);
     // one batch member per workgroup row (six accumulators per member)
     hipLaunchKernelGGL((k_real<T, KTADJ, 1, false>), dim3(items, batch), dim3(thr), qbytes, st, c, p, q_r, n_r,
-                       w_r, batch, (T)xi, (T)0, dq, 1, dn);
+                       w_r, batch, (T)xi, (T)0, dq, 1, dn, (T*)nullptr);
 }
 
 #define INST(T)                                                                                     \
@@ -836,7 +863,7 @@ void launch_real_tadj(const CellGeo& c, const PointsDev<T>& p, const T* q_r, con
     template void launch_real<T>(int, const CellGeo&, const PointsDev<T>&, const T*, const T*, int, \
                                  double, double, T*, int, hipStream_t);                             \
     template void launch_real_grad<T>(int, const CellGeo&, const PointsDev<T>&, const T*, const T*, \
-                                      int, double, double, T*, T*, hipStream_t);
+                                      int, double, double, T*, T*, hipStream_t, T*);
 INST(float)
 INST(double)
 #undef INST

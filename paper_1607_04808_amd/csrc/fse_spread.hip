@@ -48,18 +48,27 @@ template <typename T, int NC> struct ChunkPoint {
 
 // Thread t < CH loads point base + t of the bin range ending at j1 (all of its
 // loads at once: one memory latency).
+// With src2 (NC = 6): components 0-2 from src_s and 3-5 from src2, both 3 per point.
 template <typename T, int NC, int CH>
 __device__ __forceinline__ void load_point(ChunkPoint<T, NC>& pt, int base, int j1, int bm, int64_t n,
                                            const int* __restrict__ bpack_s, const T* __restrict__ coff_s,
-                                           const T* __restrict__ src_s) {
+                                           const T* __restrict__ src_s, const T* __restrict__ src2) {
     pt.bp = -1;
     const int j = base + (int)threadIdx.x;
     if ((int)threadIdx.x < CH && j < j1) {
         pt.bp = bpack_s[j];
 #pragma unroll
         for (int d = 0; d < 3; ++d) pt.cc[d] = coff_s[3 * (int64_t)j + d];
+        if (NC == 6 && src2) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) pt.vv[c] = src_s[((int64_t)bm * n + j) * NC + c];
+            for (int c = 0; c < 3; ++c) {
+                pt.vv[c] = src_s[((int64_t)bm * n + j) * 3 + c];
+                pt.vv[3 + c] = src2[((int64_t)bm * n + j) * 3 + c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pt.vv[c] = src_s[((int64_t)bm * n + j) * NC + c];
+        }
     }
 }
 
@@ -165,7 +174,8 @@ template <typename T, int NC, int TZ, int CH>
 __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict__ tile_start,
                                                const int* __restrict__ bpack_s,
                                                const T* __restrict__ coff_s,
-                                               const T* __restrict__ src_s, int64_t n, T* grid) {
+                                               const T* __restrict__ src_s, int64_t n, T* grid,
+                                               const T* __restrict__ src2, T* grid2) {
     constexpr int NW = 32 + TZ;  // factors per point: x (16), y (16), z (TZ)
     __shared__ __align__(16) T s_w[CH][NW];
     __shared__ T s_c[CH][3];
@@ -214,12 +224,12 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     int r = 0, base = 0, end = 0;
     r = find_row(0, base, end);
     ChunkPoint<T, NC> pt;
-    if (r < nrows) load_point<T, NC, CH>(pt, base, end, bm, n, bpack_s, coff_s, src_s);
+    if (r < nrows) load_point<T, NC, CH>(pt, base, end, bm, n, bpack_s, coff_s, src_s, src2);
     while (r < nrows) {
         const int cnt = stage_points<T, NC, TZ>(pt, P, lox, loy, loz, s_c, s_v, s_bp, s_wc);
         int nr = r, nbase = base + CH, nend = end;
         if (nbase >= end) nr = find_row(r + 1, nbase, nend);
-        if (nr < nrows) load_point<T, NC, CH>(pt, nbase, nend, bm, n, bpack_s, coff_s, src_s);
+        if (nr < nrows) load_point<T, NC, CH>(pt, nbase, nend, bm, n, bpack_s, coff_s, src_s, src2);
         chunk_factors<T, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
         // this wave's list: the staged points whose window reaches its 8 x 8 tile
         int nl = 0;
@@ -286,7 +296,12 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
             if (gz < Mt) {
                 const int64_t o = ((int64_t)gz * Mt + gy) * Mt + gx;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[z][c];
+                for (int c = 0; c < NC; ++c) {
+                    // with grid2: components 0-2 to grid, 3-5 to grid2, 3 per batch member
+                    T* gd = (NC == 6 && grid2) ? (c < 3 ? grid + (int64_t)bm * 3 * M3 : grid2 + ((int64_t)bm * 3 - 3) * M3)
+                                               : grid + (int64_t)bm * NC * M3;
+                    gd[(int64_t)c * M3 + o] = acc[z][c];
+                }
             }
         }
     }
@@ -309,7 +324,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4
                                                     const int* __restrict__ bpack_s,
                                                     const float* __restrict__ coff_s,
                                                     const float* __restrict__ src_s, int64_t n,
-                                                    float* grid) {
+                                                    float* grid, const float* __restrict__ src2,
+                                                    float* grid2) {
     constexpr int TZ = 16;
     __shared__ __align__(16) float s_w[CH][32 + TZ];
     __shared__ float s_c[CH][3];
@@ -357,13 +373,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4
     int r = 0, base = 0, end = 0;
     r = find_row(0, base, end);
     ChunkPoint<float, NC> pt;
-    if (r < nrows) load_point<float, NC, CH>(pt, base, end, bm, n, bpack_s, coff_s, src_s);
+    if (r < nrows) load_point<float, NC, CH>(pt, base, end, bm, n, bpack_s, coff_s, src_s, src2);
     while (r < nrows) {
         const int cnt = stage_points<float, NC, TZ>(pt, P, lox, loy, loz, s_c, s_v, s_bp, s_wc);
         // the next chunk: the rest of this row, else the next non-empty row
         int nr = r, nbase = base + CH, nend = end;
         if (nbase >= end) nr = find_row(r + 1, nbase, nend);
-        if (nr < nrows) load_point<float, NC, CH>(pt, nbase, nend, bm, n, bpack_s, coff_s, src_s);
+        if (nr < nrows) load_point<float, NC, CH>(pt, nbase, nend, bm, n, bpack_s, coff_s, src_s, src2);
         chunk_factors<float, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
         int nl = 0;
         for (int k0 = 0; k0 < cnt; k0 += 64) {
@@ -414,7 +430,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4
             if (gx < Mt && gy < Mt && gz < Mt) {
                 const int64_t o = ((int64_t)gz * Mt + gy) * Mt + gx;
 #pragma unroll
-                for (int c = 0; c < NC; ++c) grid[((int64_t)bm * NC + c) * M3 + o] = acc[c][b][j];
+                for (int c = 0; c < NC; ++c) {
+                    // with grid2: components 0-2 to grid, 3-5 to grid2, 3 per batch member
+                    float* gd = (NC == 6 && grid2) ? (c < 3 ? grid + (int64_t)bm * 3 * M3
+                                                            : grid2 + ((int64_t)bm * 3 - 3) * M3)
+                                                   : grid + (int64_t)bm * NC * M3;
+                    gd[(int64_t)c * M3 + o] = acc[c][b][j];
+                }
             }
         }
     }
@@ -430,6 +452,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4
 //   MODE 1: dx  = sum grad g (p . F), p = the point's vector (the forward
 //           field contracted with w; the first contribution overwrites).
 //   MODE 2: out = sum g F and dx += sum grad g (p . F).
+//   MODE 3 (k_gather_col only): mode 2 whose first contribution overwrites dx,
+//           for the forward value and the first gradient term in one sweep.
 // ---------------------------------------------------------------------------
 constexpr int GW = 4;  // waves per quadrature workgroup
 
@@ -840,7 +864,7 @@ __global__ __launch_bounds__(64 * NW) void k_gather_col(GridGeo g, int KX, int s
                             if (gl == 0 && valid && dx) {
                                 // the first contribution (forward field, first batch member,
                                 // first component pass) overwrites; the same lane adds the rest
-                                const bool first = (MODE == 1 && bm == 0 && cs == 0);
+                                const bool first = ((MODE == 1 || MODE == 3) && bm == 0 && cs == 0);
                                 dx[3 * i] = (first ? (T)0 : dx[3 * i]) + g0;
                                 dx[3 * i + 1] = (first ? (T)0 : dx[3 * i + 1]) + g1;
                                 dx[3 * i + 2] = (first ? (T)0 : dx[3 * i + 2]) + g2;
@@ -1042,17 +1066,17 @@ template <typename K> void allow_lds(K kern, size_t bytes) {
 
 template <typename T>
 void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int c_in, int batch,
-                   T* grid, hipStream_t st) {
+                   T* grid, hipStream_t st, const T* src2, T* grid2) {
     // cores of 16 x 16 x TZ nodes: TZ = 16 (FP32) or 8 (FP64) register accumulators per component
     constexpr int TZ = sizeof(T) == 4 ? 16 : 8;
     const unsigned ncxy = (unsigned)((g.Mt + 15) / 16), ncz = (unsigned)((g.Mt + TZ - 1) / TZ);
     dim3 grd(ncxy * ncxy * ncz, batch);
 #define SPREAD(NC, CHK)                                                                                      \
     hipLaunchKernelGGL((k_spread<T, NC, TZ, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s,     \
-                       p.coff_s, src_s, p.n, grid)
+                       p.coff_s, src_s, p.n, grid, src2, grid2)
 #define SPREAD_MFMA(NC, CHK)                                                                                 \
     hipLaunchKernelGGL((k_spread_mfma<NC, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s, p.coff_s, \
-                       src_s, p.n, grid)
+                       src_s, p.n, grid, src2, grid2)
     if constexpr (sizeof(T) == 4) {
         if (c_in == 3) SPREAD_MFMA(3, 128); else SPREAD_MFMA(6, 128);
     } else {
@@ -1246,6 +1270,41 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
                            p.bpack_s, p.coff_s, phi_f, phi_w, f_s, w_s, p.n, batch, dsrc, dx);
 }
 
+// The forward quadrature and both gradient quadratures of the adjoint: u from phi_f
+// with the first term of dx (w contracted) in one sweep (mode 3), then dsrc from
+// phi_w with the second (f contracted; mode 2).  Without the sweeping kernel (its
+// block exceeds LDS) the separate passes run.
+template <typename T>
+void launch_gather_fused(const GridGeo& g, const PointsDev<T>& p, const T* phi_f, const T* phi_w, const T* f_s,
+                         const T* w_s, int batch, T* u, T* dsrc, T* dx, hipStream_t st) {
+    const ColCfg cc = col_config<T>(g);
+    if (!cc.ncs) {
+        launch_gather<T>(g, p, phi_f, batch, u, st);
+        launch_gather_grad<T>(g, p, phi_f, phi_w, f_s, w_s, batch, dsrc, dx, st);
+        return;
+    }
+    const dim3 grd(cc.ncol * cc.nseg, 1);
+#define GFK(MD, NC, PT, FLD, VEC, OUT)                                                                         \
+    allow_lds(k_gather_col<T, MD, NC, col_gp<T>(), PT>, cc.lds);                                               \
+    hipLaunchKernelGGL((k_gather_col<T, MD, NC, col_gp<T>(), PT>), grd, dim3(64 * CW), cc.lds, st, g, cc.kx,   \
+                       cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, FLD, VEC, p.n,      \
+                       batch, OUT, dx)
+#define GF(NC, PT)                                                                                             \
+    GFK(3, NC, PT, phi_f, w_s, u);                                                                             \
+    GFK(2, NC, PT, phi_w, f_s, dsrc)
+#define GFP(NC)                                                                                                \
+    switch ((g.P + 3) & ~3) {                                                                                  \
+        case 12: GF(NC, 12); break;                                                                            \
+        case 16: GF(NC, 16); break;                                                                            \
+        case 20: GF(NC, 20); break;                                                                            \
+        default: GF(NC, 0); break;                                                                             \
+    }
+    if (cc.ncs == 3) { GFP(3); } else { GFP(1); }
+#undef GFP
+#undef GF
+#undef GFK
+}
+
 // Bin side for the point binning: the largest side <= 7 whose quadrature block
 // still fits in LDS for one component, at least 2.  At the 1e-6 (FP32, P = 12)
 // and 1e-10 (FP64, P = 20) settings, sides 4 to 8 (FP32) and 4 to 7 (FP64)
@@ -1269,11 +1328,13 @@ int bin_side(int elem_bytes, int P) {
 
 #define INST(T)                                                                                      \
     template void launch_spread<T>(const GridGeo&, const PointsDev<T>&, const T*, int, int, T*,      \
-                                   hipStream_t);                                                     \
+                                   hipStream_t, const T*, T*);                                       \
     template void launch_gather<T>(const GridGeo&, const PointsDev<T>&, const T*, int, T*,           \
                                    hipStream_t);                                                     \
     template void launch_gather_grad<T>(const GridGeo&, const PointsDev<T>&, const T*, const T*,     \
-                                        const T*, const T*, int, T*, T*, hipStream_t);
+                                        const T*, const T*, int, T*, T*, hipStream_t);            \
+    template void launch_gather_fused<T>(const GridGeo&, const PointsDev<T>&, const T*, const T*,    \
+                                         const T*, const T*, int, T*, T*, T*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -27,7 +27,7 @@ EXPORTS = ("fse_geometry", "fse_plan_create", "fse_plan_geometry", "fse_plan_set
            "fse_error_estimates", "fse_choose_params", "fse_bounding_box", "fse_set_targets", "fse_eval_targets",
            "fse_eval_adjoint_stresslet", "fse_freespace_solve",
            "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_plan_autotune", "fse_plan_bins",
-           "fse_precompute_cache_stats")
+           "fse_precompute_cache_stats", "fse_eval_with_adjoint")
 NOALLOC_MAX_BYTES = 64 << 20  # FSE_NOALLOC_MAX_BYTES
 NSTAGES = 12
 
@@ -85,6 +85,7 @@ def lib():
             L.fse_eval_parts.argtypes = [vp, vp, vp, vp, vp]
             L.fse_eval_adjoint.argtypes = [vp, vp, vp, vp, vp, i32]
             L.fse_eval_adjoint_stresslet.argtypes = [vp, vp, vp, vp, vp, vp]
+            L.fse_eval_with_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
             L.fse_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
             L.fse_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
             L.fse_plan_autotune.argtypes = [vp, i64, vp, vp, vp, vp, i32, ctypes.POINTER(Tuning)]
@@ -300,6 +301,19 @@ class Plan:
         _check(lib().fse_eval_adjoint(self._h, _ptr(f), _ptr(w), _ptr(df), _ptr(dx), 1 if recompute else 0))
         self.generation += 1
         return df, dx
+
+    def eval_with_adjoint(self, f, w):
+        """(u, dL/df, dL/dx) for L = sum w . u in one call (fse_eval_with_adjoint)."""
+        torch = _torch()
+        f = self._prep(f, self._src_shape())
+        w = self._prep(w, self._src_shape())
+        u = torch.empty(self._src_shape(), dtype=self.tdtype, device=f.device)
+        df = torch.empty_like(u)
+        dx = torch.empty((self.n, 3), dtype=self.tdtype, device=f.device)
+        self._sync_stream()
+        _check(lib().fse_eval_with_adjoint(self._h, _ptr(f), _ptr(w), _ptr(u), _ptr(df), _ptr(dx)))
+        self.generation += 1
+        return u, df, dx
 
     def adjoint_stresslet(self, q, nrm, w):
         """(dL/dq, dL/dn) of L = sum w . u for a stresslet plan (fse_eval_adjoint_stresslet)."""

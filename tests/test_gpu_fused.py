@@ -1,0 +1,97 @@
+"""fse_eval_with_adjoint (the forward sum and the adjoint of L = sum w . u in one
+call: one spreading pass for both source sets, a shared quadrature sweep, one
+real-space pass over the pairs) against fse_eval followed by fse_eval_adjoint on
+the same plan, element by element, and against the oracle's direct sums."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1607_04808_amd as F  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def relmax(u, ref):
+    u = np.asarray(u, np.float64)
+    return float(np.abs(u - ref).max() / np.abs(ref).max())
+
+
+def _t(a, dtype):
+    return torch.tensor(np.asarray(a), dtype=torch.float32 if dtype == "f32" else torch.float64, device=DEV)
+
+
+# the separate calls sum some terms in another order (the gradient quadrature
+# contracts the components first; the forward real-space pass keeps FP32 flush
+# totals where the fused pass keeps FP64 ones), so they agree to rounding
+TOL = {"f64": 1e-12, "f32": 2e-6}
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("batch", [1, 3])
+def test_fused_matches_separate_calls(kernel, dtype, batch):
+    n = 4000
+    prm = F.make_params(9.0, 0.35, 22, 12, L=1.0)
+    x = W.uniform_cube(n, 430)
+    bb = None if batch == 1 else batch
+    f, w = W.normal_strengths(n, 431, bb), W.normal_strengths(n, 432, bb)
+    plan = F.Plan(kernel, dtype, prm, batch=batch, nmax=n, tuned=False)
+    try:
+        xt, ft, wt = _t(x, dtype), _t(f, dtype), _t(w, dtype)
+        plan.set_points(xt)
+        u0 = plan.eval(ft).double().cpu().numpy()
+        df0, dx0 = (a.double().cpu().numpy() for a in plan.adjoint(ft, wt, recompute=False))
+        u1, df1, dx1 = (a.double().cpu().numpy() for a in plan.eval_with_adjoint(ft, wt))
+        # the forward field stays valid: an adjoint without recomputation still agrees
+        df2, dx2 = (a.double().cpu().numpy() for a in plan.adjoint(ft, wt, recompute=False))
+    finally:
+        plan.close()
+    e = (relmax(u1, u0), relmax(df1, df0), relmax(dx1, dx0))
+    print(kernel, dtype, batch, "u %.1e  dL/df %.1e  dL/dx %.1e" % e)
+    assert max(e) < TOL[dtype]
+    assert relmax(df2, df0) < TOL[dtype] and relmax(dx2, dx0) < TOL[dtype]
+
+
+def test_fused_against_direct_sums():
+    n = 3000
+    prm = F.make_params(10.0, 0.5, 40, 20, L=1.0)  # xi r_c = 5, M / xi L = 4: about 1e-10
+    x, f, w = W.uniform_cube(n, 440), W.normal_strengths(n, 441), W.normal_strengths(n, 442)
+    plan = F.Plan("stokeslet", "f64", prm, nmax=n, tuned=False)
+    try:
+        plan.set_points(_t(x, "f64"))
+        u, df, dx = (a.cpu().numpy().reshape(n, 3) for a in plan.eval_with_adjoint(_t(f, "f64"), _t(w, "f64")))
+    finally:
+        plan.close()
+    eu = relmax(u, direct.direct("stokeslet", x, f))
+    ef = relmax(df, direct.direct("stokeslet", x, w))
+    ex = relmax(dx, direct.grad_direct("stokeslet", x, f, w))
+    print("fused vs direct: u %.1e dL/df %.1e dL/dx %.1e" % (eu, ef, ex))
+    assert eu < 1e-8 and ef < 1e-8 and ex < 1e-8
+
+
+def test_fused_rejects_stresslet_and_periodic():
+    n = 200
+    x = _t(W.uniform_cube(n, 450), "f64")
+    f = _t(W.normal_strengths(n, 451), "f64")
+    plan = F.Plan("stresslet", "f64", F.make_params(9.0, 0.35, 22, 12, L=1.0), nmax=n, tuned=False)
+    try:
+        plan.set_points(x)
+        with pytest.raises(F.FseError):
+            plan.eval_with_adjoint(f, f)
+    finally:
+        plan.close()
+    plan = F.Plan("stokeslet", "f64", F.make_params(9.0, 0.3, 24, 8, L=1.0, periodic=1), nmax=n, tuned=False)
+    try:
+        plan.set_points(x)
+        with pytest.raises(F.FseError):
+            plan.eval_with_adjoint(f, f)
+    finally:
+        plan.close()
