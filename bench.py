@@ -87,12 +87,14 @@ def stage_work(stage, geo, n, P, dtype, pairs, c_in=3, batch=1, fused=False):
 
 # Kernels behind each timed stage (FP32 / FP64 template names as rocprofv3 lists them)
 # and the sources that define them, for the counter-based HBM traffic.
+# Timed step: fse_eval_with_adjoint, so the spread stage is the six-component launch,
+# gather_grad the sweeps of modes 3 and 2, and real_grad the pass that also sums u.
 STAGE_KERNELS = {
     "real": (["k_real<{T}, 0, 1, false, false,"], "fse_real.hip"),
-    "real_grad": (["k_real<{T}, 0, 1, true, true,"], "fse_real.hip"),
-    "spread": (["k_spread<{T}, 3,", "k_spread_mfma<3,", "k_spread<{T}, 6,", "k_spread_mfma<6,"], "fse_spread.hip"),
+    "real_grad": (["k_real<{T}, 0, 1, true, true, true>"], "fse_real.hip"),
+    "spread": (["k_spread<{T}, 6,", "k_spread_mfma<6,"], "fse_spread.hip"),
     "gather": (["k_gather_col<{T}, 0, "], "fse_spread.hip"),
-    "gather_grad": (["k_gather_col<{T}, 1, ", "k_gather_col<{T}, 2, ", "k_gather_col<{T}, 3, "], "fse_spread.hip"),
+    "gather_grad": (["k_gather_col<{T}, 3, ", "k_gather_col<{T}, 2, "], "fse_spread.hip"),
     "fft_x": (["k_fft_x<{T},"], "fse_fft.hip"),
     "fft_y": (["k_fft_y<{T},"], "fse_fft.hip"),
     "fft_z_scale": (["k_fft_z<{T}, 0, 3,", "k_fft_zb<{T}, 0,"], "fse_fft.hip"),
