@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int NC, int CH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 3 ? 4 : 3))) void k_spread_mfma(GridGeo g, const int* __restrict__ tile_start,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_spread_mfma(GridGeo g, const int* __restrict__ tile_start,
                                                     const int* __restrict__ bpack_s,
                                                     const float* __restrict__ coff_s,
                                                     const float* __restrict__ src_s, int64_t n,
