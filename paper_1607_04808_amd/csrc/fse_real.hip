@@ -117,11 +117,12 @@ __device__ __forceinline__ void radial<float>(float xi, float xi2, float r2, flo
 template <typename T, bool GRAD>
 constexpr int qcap() { return sizeof(T) == 4 ? (GRAD ? FSE_QCAP32G : FSE_QCAP32) : 48; }
 // source slots per chunk, and the chunk buffers a pass keeps: two (queued hits may
-// outlive their chunk) for single FP64 passes, measured 6 % faster there; FP32
-// pairs cost too few instructions to pay for the queue moves (value pass 12 %
-// slower), and batched passes hold four times the values per chunk
-template <typename T> constexpr int real_chunk() { return sizeof(T) == 4 ? FSE_REAL_CH32 : FSE_REAL_CH64; }
+// outlive their chunk) for single FP64 passes, measured 6 % faster there.  FP32
+// passes keep one: with two, even at the same four waves per SIMD (112-slot chunks,
+// 32-entry queues), the fused gradient pass took 2.23 ms against 2.18 and the value
+// pass 1.56 against 1.36.  Batched passes hold four times the values per chunk.
 template <typename T, int NB> constexpr int real_nbuf() { return NB == 1 && sizeof(T) == 8 ? 2 : 1; }
+template <typename T> constexpr int real_chunk() { return sizeof(T) == 4 ? FSE_REAL_CH32 : FSE_REAL_CH64; }
 // queue entries: buffer slot indices, 16 bits (one-byte entries, which would fit
 // the FP32 passes' 128 slots, measured 6 % slower in the FP32 value pass)
 using QE = unsigned short;
@@ -199,8 +200,9 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
     // the chunks' positions and values alternate between two buffers.
     constexpr int NBUF = real_nbuf<T, NB>();
     constexpr bool CARRY = NBUF == 2;
-    __shared__ Pos4<T> xs[NBUF * CH];  // source positions
-    __shared__ Pos4<T> xq[CH];         // test form: -2 (x - o), |x - o|^2 about the cell corner o
+    // sources in test form about the origin o: -2 (x - o) and |x - o|^2; a pair's
+    // r = (x_t - o) - (x_s - o) comes from it too
+    __shared__ Pos4<T> xq[NBUF * CH];
     __shared__ T ss[NB][NS][NBUF * CH];
     extern __shared__ __align__(16) unsigned char qd_raw[];
     QE* const qd = (QE*)qd_raw;  // hit queues: qcap (+ 8 with CARRY) rows of queue_row(blockDim.x) entries
@@ -222,11 +224,18 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
     const int t0 = tcell_start[cell] + (item - work_start[cell]) * nthr;
     const int t1 = min(tcell_start[cell + 1], t0 + nthr);
     const T rc2 = (T)cg.rc2;
-    // the candidate test uses |xl|^2 + |xs_l|^2 - 2 xl . xs_l in coordinates about
-    // the cell corner, slightly widened (its rounding is ~1e-7 of rc^2 in FP32);
-    // the exact r^2 <= rc^2 decides when a queued pair is evaluated
-    const T rc2t = rc2 * (T)(1.0 + 1.0 / 65536);
-    const T ox = (T)(cg.lo[0] + cx * cg.cell), oy = (T)(cg.lo[1] + cy * cg.cell), oz = (T)(cg.lo[2] + cz * cg.cell);
+    // The origin o of the local coordinates: the cell corner c, or 0 in a direction
+    // where -4 cells < c < 2 cells.  Then every target (in [c, c + cell)) and source
+    // (in [c - cell, c + 2 cell)) is within a factor 2 of o, or o = 0, so x - o is
+    // exact and a pair's (x_t - o) - (x_s - o) rounds to the same r as x_t - x_s.
+    auto origin = [&](double c) { return (T)(c >= 2.0 * cg.cell || c <= -4.0 * cg.cell ? c : 0.0); };
+    const T ox = origin(cg.lo[0] + cx * cg.cell), oy = origin(cg.lo[1] + cy * cg.cell),
+            oz = origin(cg.lo[2] + cz * cg.cell);
+    // the candidate test uses |xl|^2 + |xs_l|^2 - 2 xl . xs_l in these coordinates
+    // (at most 5 cells from o in each direction), widened by 2^-13 cell^2: its FP32
+    // rounding stays below 4e-5 cell^2; the exact r^2 <= rc^2 decides when a queued
+    // pair is evaluated
+    const T rc2t = (T)(cg.rc2 + cg.cell * cg.cell / 8192.0);
     const T xi2 = xi * xi;
     const T c2x = (T)(2.0 * INV_SQRTPI) * xi;       // 2 xi / sqrt(pi)
     const T c4x3 = (T)(4.0 * INV_SQRTPI) * xi * xi2;  // 4 xi^3 / sqrt(pi)
@@ -351,8 +360,8 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
         // queue, the self pair, coincident points, or beyond the cutoff) adds exactly
         // zero (see the two precisions below).
         auto eval = [&](int kk, bool on) {
-            const Pos4<T> ps = xs[kk];
-            const T r0 = xt0 - ps.x, r1 = xt1 - ps.y, r2v = xt2 - ps.z;
+            const Pos4<T> pk = xq[kk];
+            const T r0 = xl0 + (T)0.5 * pk.x, r1 = xl1 + (T)0.5 * pk.y, r2v = xl2 + (T)0.5 * pk.z;
             const T r2q = r0 * r0 + r1 * r1 + r2v * r2v;
             const bool use = on && r2q != (T)0 && r2q <= rc2;
             // FP32: r^2 = 1e30 makes e (and with it ec) exactly zero, and every kernel
@@ -611,7 +620,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
             int kept = 0;
             for (int q0 = 0; q0 < cntc; q0 += nthr) {
                 const int q = q0 + tid;
-                Pos4<T> ps, pq;
+                Pos4<T> pq;
                 bool keep = false;
                 int src = 0;
                 if (q < cntc) {
@@ -620,17 +629,14 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                     for (int st = 16; st > 0; st >>= 1)
                         if (kc + st <= 26 && ch_off[kc + st] <= q) kc += st;
                     const int k = ch_base[kc] + q;
-                    ps.x = x_r[3 * (int64_t)k];
-                    ps.y = x_r[3 * (int64_t)k + 1];
-                    ps.z = x_r[3 * (int64_t)k + 2];
+                    T px = x_r[3 * (int64_t)k], py = x_r[3 * (int64_t)k + 1], pz = x_r[3 * (int64_t)k + 2];
                     if (cg.periodic) {
-                        ps.x += ch_sh[kc][0];
-                        ps.y += ch_sh[kc][1];
-                        ps.z += ch_sh[kc][2];
+                        px += ch_sh[kc][0];
+                        py += ch_sh[kc][1];
+                        pz += ch_sh[kc][2];
                     }
-                    ps.pad = (T)0;
                     src = k;
-                    const T l0 = ps.x - ox, l1 = ps.y - oy, l2 = ps.z - oz;
+                    const T l0 = px - ox, l1 = py - oy, l2 = pz - oz;
                     pq.x = (T)-2 * l0;
                     pq.y = (T)-2 * l1;
                     pq.z = (T)-2 * l2;
@@ -651,8 +657,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                 }
                 if (keep) {
                     const int slot = off + __popcll(m & ((1ull << (tid & 63)) - 1ull));
-                    xs[base + slot] = ps;
-                    xq[slot] = pq;
+                    xq[base + slot] = pq;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         if (b0 + b < batch) {
@@ -678,7 +683,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                 Pos4<T> pf;
                 pf.x = pf.y = pf.z = (T)0;
                 pf.pad = (T)FAR;
-                xq[kept + tid] = pf;
+                xq[base + kept + tid] = pf;
             }
             __syncthreads();
             if (!wave_active) continue;
@@ -692,7 +697,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
             for (int k8 = 0; k8 < cnt8; k8 += 8) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const Pos4<T> pq = xq[k8 + u];
+                    const Pos4<T> pq = xq[base + k8 + u];
                     const T d = fma(xl0, pq.x, fma(xl1, pq.y, fma(xl2, pq.z, Atc + pq.pad)));
                     *qp = (QE)((u & 1) ? (kp[u >> 1] >> 16) : kp[u >> 1]);
                     qp = (QE*)((char*)qp + (sign_bit(d) << qsh));
