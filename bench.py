@@ -37,7 +37,7 @@ MFMA_STAGES = {("f32", "spread")}  # (form, stage) pairs whose kernel is a matri
 # Parameters per form (calibrated against the oracle):
 # FP32 form: 1e-6 relative max-norm; FP64 form: 1e-10.
 FORMS = {
-    "f32": dict(xi=75.0, rc=0.0476, M=236, P=12, Mt=0, tol=1e-6),
+    "f32": dict(xi=75.0, rc=0.0476, M=236, P=11, Mt=0, tol=1e-6),
     "f64": dict(xi=80.0, rc=0.06075, M=304, P=20, Mt=0, tol=1e-10),
 }
 N_DEFAULT = 1_000_000
