@@ -38,7 +38,7 @@ MFMA_STAGES = {("f32", "spread")}  # (form, stage) pairs whose kernel is a matri
 # FP32 form: 1e-6 relative max-norm; FP64 form: 1e-10.
 FORMS = {
     "f32": dict(xi=75.0, rc=0.0476, M=236, P=11, Mt=0, tol=1e-6),
-    "f64": dict(xi=80.0, rc=0.06075, M=304, P=20, Mt=0, tol=1e-10),
+    "f64": dict(xi=80.0, rc=0.06075, M=304, P=18, Mt=0, tol=1e-10),
 }
 N_DEFAULT = 1_000_000
 L_BOX = 1.0 + 2.0 ** -20  # the unit cube, enlarged so FP32-rounded points stay inside

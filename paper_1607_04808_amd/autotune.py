@@ -32,7 +32,7 @@ L_UNIT = 1.0 + 2.0 ** -20
 WORKLOADS = {
     "c1_f64": ("stokeslet", "f64", 1000, 1, None, 1, "cube", True),
     "headline_f32": ("stokeslet", "f32", 1_000_000, 1, (75.0, 0.0476, 236, 11), 0, "cube", True),
-    "headline_f64": ("stokeslet", "f64", 1_000_000, 1, (80.0, 0.06075, 304, 20), 0, "cube", True),
+    "headline_f64": ("stokeslet", "f64", 1_000_000, 1, (80.0, 0.06075, 304, 18), 0, "cube", True),
     "batched16_f32": ("stokeslet", "f32", 1_000_000, 16, (75.0, 0.0476, 236, 11), 0, "cube", True),
     "c4_rotlet16_f32": ("rotlet", "f32", 1_000_000, 16, (80.0, 0.04725, 246, 12), 0, "cube", False),
     "c2_f32": ("stokeslet", "f32", 100_000, 1, (40.0, 0.0945, 124, 12), 0, "cube", True),
