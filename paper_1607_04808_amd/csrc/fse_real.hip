@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
         // widened test threshold folded into the target term: a hit is a negative sign
         const T Atc = At - rc2t;
         const bool wave_active = __any(act);
-        // bounding box of the work item's targets about the cell corner
+        // bounding box of the work item's targets about the origin o
         T bb_lo[3] = {act ? xl0 : (T)FAR, act ? xl1 : (T)FAR, act ? xl2 : (T)FAR};
         T bb_hi[3] = {act ? xl0 : (T)-FAR, act ? xl1 : (T)-FAR, act ? xl2 : (T)-FAR};
 #pragma unroll
