@@ -1078,7 +1078,10 @@ void launch_spread(const GridGeo& g, const PointsDev<T>& p, const T* src_s, int 
     hipLaunchKernelGGL((k_spread_mfma<NC, CHK>), grd, dim3(256), 0, st, g, p.tile_start, p.bpack_s, p.coff_s, \
                        src_s, p.n, grid, src2, grid2)
     if constexpr (sizeof(T) == 4) {
-        if (c_in == 3) SPREAD_MFMA(3, 128); else SPREAD_MFMA(6, 128);
+        // six components stage 160 points per chunk: more work per barrier for the same
+        // four waves per SIMD (f and w of the headline 1.41 -> 1.35 ms; 192 and 224
+        // leave LDS for fewer workgroups and took 1.63 ms)
+        if (c_in == 3) SPREAD_MFMA(3, 128); else SPREAD_MFMA(6, 160);
     } else {
         if (c_in == 3) SPREAD(3, 128); else SPREAD(6, 128);
     }
