@@ -359,7 +359,9 @@ fse_status_t fse_eval_noalloc(fse_kernel_t kernel, fse_dtype_t dtype, const fse_
  * value and the gradient pass; the most waves (64 targets each) a real-space
  * work item takes; the most FFT lines (rows) one workgroup transforms.  Plans
  * start at the defaults; fse_plan_autotune times the candidates on the plan's
- * own workload and keeps the fastest.  No knob changes the sums' arithmetic.
+ * own workload and keeps the fastest.  No knob changes what is summed; the bin
+ * side, queue depths and waves change the order of some sums, so results move by
+ * rounding only (the FFT line count changes nothing: bit-identical fields).
  */
 typedef struct {
     int32_t bin_side;         /* 4..8                                           */
