@@ -669,15 +669,18 @@ template <typename T> fse_status_t set_points_t(fse_plan* p, int64_t n, const T*
         launch_fill_i32(p->cnt_s, p->ntiles3 + 1, 0, st);
         launch_fill_i32(p->cnt_r, p->ncells3 + 1, 0, st);
         launch_fill_i32(p->flag, 1, 0, st);
-        launch_bin<T>(x, n, p->gg, p->cg, p->key_s, p->key_r, p->idx, p->cnt_s, p->cnt_r, p->bpack, (T*)p->coff,
+        launch_bin<T>(x, n, p->gg, p->cg, p->key_s, p->key_r, p->idx, p->bpack, (T*)p->coff,
                       p->flag, st);
         // stable sorts by tile and by cell: perm_s and perm_r list the point indices in order
         if (sort_tmp_bytes(n, p->bits_s) > p->sort_bytes || sort_tmp_bytes(n, p->bits_r) > p->sort_bytes) {
             set_err("sort workspace too small for n=%lld", (long long)n);
             return FSE_EINVAL;
         }
+        // (the counts per tile and cell come from the sorted keys)
         HIPCHK(launch_sort_pairs(p->sort_tmp, p->sort_bytes, p->key_s, p->key_tmp, p->idx, p->perm_s, n, p->bits_s, st));
+        launch_run_counts(p->key_tmp, n, p->cnt_s, st);
         HIPCHK(launch_sort_pairs(p->sort_tmp, p->sort_bytes, p->key_r, p->key_tmp, p->idx, p->perm_r, n, p->bits_r, st));
+        launch_run_counts(p->key_tmp, n, p->cnt_r, st);
         launch_scan_exclusive(p->cnt_s, p->start_s, p->ntiles3 + 1, p->scan_tmp, st);
         launch_scan_exclusive(p->cnt_r, p->start_r, p->ncells3 + 1, p->scan_tmp, st);
         // real-space work items: slices of up to real_S targets of one cell
@@ -757,10 +760,12 @@ template <typename T> fse_status_t set_targets_t(fse_plan* p, int64_t nt, const 
         launch_fill_i32(t.cnt_s, p->ntiles3 + 1, 0, st);
         launch_fill_i32(t.cnt_r, p->ncells3 + 1, 0, st);
         launch_fill_i32(p->flag, 1, 0, st);
-        launch_bin<T>(y, nt, p->gg, p->cg, t.key_s, t.key_r, t.idx, t.cnt_s, t.cnt_r, t.bpack, (T*)t.coff, p->flag,
+        launch_bin<T>(y, nt, p->gg, p->cg, t.key_s, t.key_r, t.idx, t.bpack, (T*)t.coff, p->flag,
                       st);
         HIPCHK(launch_sort_pairs(t.sort_tmp, t.sort_bytes, t.key_s, t.key_tmp, t.idx, t.perm_s, nt, p->bits_s, st));
+        launch_run_counts(t.key_tmp, nt, t.cnt_s, st);
         HIPCHK(launch_sort_pairs(t.sort_tmp, t.sort_bytes, t.key_r, t.key_tmp, t.idx, t.perm_r, nt, p->bits_r, st));
+        launch_run_counts(t.key_tmp, nt, t.cnt_r, st);
         launch_scan_exclusive(t.cnt_s, t.start_s, p->ntiles3 + 1, p->scan_tmp, st);
         launch_scan_exclusive(t.cnt_r, t.start_r, p->ncells3 + 1, p->scan_tmp, st);
         t.real_S = (int)real_threads(nt, p->ncells3, p->real_waves);

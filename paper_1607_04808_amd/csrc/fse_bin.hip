@@ -57,7 +57,7 @@ __global__ void k_scan_add(int* out, int64_t n, const int* offs) {
 
 template <typename T>
 __global__ void k_bin(const T* __restrict__ x, int64_t n, GridGeo g, CellGeo c, int* key_s, int* key_r,
-                      int* idx, int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag) {
+                      int* idx, int* bpack, T* coff, int* flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int b[3], cl[3];
@@ -83,10 +83,24 @@ __global__ void k_bin(const T* __restrict__ x, int64_t n, GridGeo g, CellGeo c, 
     key_s[i] = ks;
     key_r[i] = kr;
     idx[i] = (int)i;
-    // counts only: the order within a tile or cell comes from the stable sort
-    atomicAdd(&cnt_s[ks], 1);
-    atomicAdd(&cnt_r[kr], 1);
     if (bad) atomicOr(flag, 1);
+}
+
+// Counts per key from the sorted keys: the thread at the start of each run of equal
+// keys finds the run's end by binary search and writes its length (cnt holds
+// zeros beforehand; keys without points keep them).  Counting from the sorted
+// keys spares the per-point atomics on a few hundred hot cache lines.
+__global__ void k_run_counts(const int* __restrict__ keys, int64_t n, int* cnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int k = keys[j];
+    if (j > 0 && keys[j - 1] == k) return;
+    int64_t lo = j + 1, hi = n;  // the first index in [j + 1, n] whose key exceeds k
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] > k) hi = mid; else lo = mid + 1;
+    }
+    cnt[k] = (int)(lo - j);
 }
 
 // Gather the per-point data into the two sorted orders (perm_s and perm_r hold
@@ -250,9 +264,14 @@ void launch_scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStre
 
 template <typename T>
 void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* key_r, int* idx,
-                int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, g, c, key_s, key_r, idx, cnt_s,
-                       cnt_r, bpack, coff, flag);
+                int* bpack, T* coff, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin<T>, dim3(nblk(n, 256)), dim3(256), 0, st, x, n, g, c, key_s, key_r, idx, bpack,
+                       coff, flag);
+}
+
+void launch_run_counts(const int* keys_sorted, int64_t n, int* cnt, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_run_counts, dim3(nblk(n, 256)), dim3(256), 0, st, keys_sorted, n, cnt);
 }
 
 int key_bits(int64_t nkeys) {
@@ -314,7 +333,7 @@ void launch_permute3(const T* a, int64_t n, int batch, const int* perm, T* out, 
 
 #define INST(T)                                                                                     \
     template void launch_bin<T>(const T*, int64_t, const GridGeo&, const CellGeo&, int*, int*, int*, int*, \
-                                int*, int*, T*, int*, hipStream_t);                                 \
+                                T*, int*, hipStream_t);                                             \
     template void launch_scatter<T>(const T*, int64_t, const int*, const int*, const int*, const T*,   \
                                     int*, T*, T*, int*, hipStream_t);                               \
     template void launch_permute_sources<T>(int, const T*, const T*, int64_t, int, const int*, T*,  \

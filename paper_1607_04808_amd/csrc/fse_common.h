@@ -194,7 +194,10 @@ size_t scan_tmp_ints(int64_t n);
 // accumulate), idx[i] = i, flag |= 1 for a point outside the box
 template <typename T>
 void launch_bin(const T* x, int64_t n, const GridGeo& g, const CellGeo& c, int* key_s, int* key_r, int* idx,
-                int* cnt_s, int* cnt_r, int* bpack, T* coff, int* flag, hipStream_t st);
+                int* bpack, T* coff, int* flag, hipStream_t st);
+// cnt[k] <- the number of entries equal to k in the ascending keys_sorted[0, n)
+// (cnt zero beforehand)
+void launch_run_counts(const int* keys_sorted, int64_t n, int* cnt, hipStream_t st);
 // bits that hold keys in [0, nkeys)
 int key_bits(int64_t nkeys);
 // device scratch bytes of one launch_sort_pairs over n keys of `bits` bits (0 on failure)
