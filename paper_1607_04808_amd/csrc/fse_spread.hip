@@ -1309,8 +1309,8 @@ void launch_gather_fused(const GridGeo& g, const PointsDev<T>& p, const T* phi_f
 }
 
 // Default bin side for the point binning: the largest side <= 7 whose quadrature
-// block still fits in LDS for one component, at least 2.  At the 1e-6 (FP32, P = 12)
-// and 1e-10 (FP64, P = 20) settings, sides 4 to 8 (FP32) and 4 to 7 (FP64)
+// block still fits in LDS for one component, at least 2.  At 1e-6 (FP32, P = 12) and
+// 1e-10 (FP64, P = 20) settings of the headline workload, sides 4 to 8 (FP32) and 4 to 7 (FP64)
 // measured fastest at 7: larger bins stage fewer ring planes per point, and at
 // 8 the FP32 ring leaves room for one workgroup per CU instead of two.  A plan's
 // tuning may set another side (the autotuned FP64 headline at P = 18 takes 6).

@@ -31,8 +31,8 @@ def _exact(a, dtype):
 
 
 # (dtype, xi, rc, M, P, expected Mt, tolerance).  xi h and xi rc below and above
-# the 1e-6 (FP32, P = 12) and 1e-10 (FP64, P = 20) settings of the headline
-# workload, so that the truncation errors sit well under the tolerance.  In FP32
+# the ratios of the 1e-6 (FP32) and 1e-10 (FP64) headline settings, with P = 12
+# and 20, so that the truncation errors sit well under the tolerance.  In FP32
 # the Fourier part then carries the FP32 rounding of the transforms, which grows
 # with their length: against the oracle's exact Fourier part (direct.fourier_dir)
 # it measured 6.2e-7 at 2 Mt = 1200 and 1.1e-6 at 2048, and 8.2e-7 at 2048 with
