@@ -1,8 +1,9 @@
 """Parity on every code path the ABI admits, element by element against the oracle:
 
 * Gaussian supports that select each quadrature kernel: P = 8 (the generic
-  row walk), P = 24 and 28 in FP64 (the column kernel's widest ring, then the
-  block and global-memory kernels), P = 32 in both precisions;
+  row walk), P = 11 and 18 (the headline forms' widths, padded to 12 and 20),
+  P = 24 and 28 in FP64 (the column kernel's widest ring, then the block and
+  global-memory kernels), P = 32 in both precisions;
 * FFT sizes whose stages run fused in FP32: n = 50 (5 5 | 2) and n = 60 (5 4 | 3);
 * the batched adjoint against single adjoints;
 * the FP32 adjoints (stokeslet and rotlet) against the oracle's discrete gradient.
@@ -47,6 +48,8 @@ def _geo(plan, p):
 # (P, xi, M, Mt, dtypes): eta < 0.7 in every case
 PCASES = [
     (8, 10.0, 20, 0, ("f64", "f32")),
+    (11, 8.5, 20, 0, ("f64", "f32")),   # odd P, the FP32 headline's (x-sums padded to 12)
+    (18, 6.5, 20, 0, ("f64",)),         # the FP64 headline's P (x-sums padded to 20)
     (24, 5.5, 20, 0, ("f64", "f32")),
     (28, 5.0, 20, 0, ("f64",)),
     (32, 4.0, 20, 54, ("f64", "f32")),
