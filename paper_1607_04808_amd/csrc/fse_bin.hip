@@ -4,7 +4,7 @@
 // Section 6).  The sort is a stable LSD radix sort of (key, point index), so
 // within a tile or cell the points keep their input order and every later
 // summation order is the same from run to run.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "fse_common.h"
 
@@ -280,10 +280,17 @@ int key_bits(int64_t nkeys) {
     return b;
 }
 
+// rocPRIM's onesweep LSD radix sort at every size above one block: by default it
+// takes a merge sort up to 2^20 items, five merge levels (ten launches) per sort at
+// 10^6 points.  Both are stable, so the permutations are the same.
+using SortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                              rocprim::default_config, 0>;
+
 size_t sort_tmp_bytes(int64_t n, int bits) {
     size_t b = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const int*)nullptr, (int*)nullptr, (const int*)nullptr,
-                                           (int*)nullptr, (int)n, 0, bits, (hipStream_t)0) != hipSuccess)
+    if (rocprim::radix_sort_pairs<SortConfig>(nullptr, b, (const int*)nullptr, (int*)nullptr, (const int*)nullptr,
+                                              (int*)nullptr, (unsigned int)n, 0u, (unsigned int)bits,
+                                              (hipStream_t)0) != hipSuccess)
         return 0;
     return b;
 }
@@ -291,7 +298,8 @@ size_t sort_tmp_bytes(int64_t n, int bits) {
 hipError_t launch_sort_pairs(void* tmp, size_t tmp_bytes, const int* keys, int* keys_out, const int* vals,
                              int* vals_out, int64_t n, int bits, hipStream_t st) {
     size_t b = tmp_bytes;
-    return hipcub::DeviceRadixSort::SortPairs(tmp, b, keys, keys_out, vals, vals_out, (int)n, 0, bits, st);
+    return rocprim::radix_sort_pairs<SortConfig>(tmp, b, keys, keys_out, vals, vals_out, (unsigned int)n, 0u,
+                                                 (unsigned int)bits, st);
 }
 
 template <typename T>
