@@ -613,6 +613,13 @@ constexpr int CW = 8;  // waves per sweeping workgroup
 #define FSE_CW64V 12
 #endif
 constexpr int CW64V = FSE_CW64V;
+// Window width the sweeping quadrature sums over: P padded to a multiple of 4 (the
+// runtime-width x-sums run in fours), except FP64 P = 17 or 18, which run the
+// unrolled width 18 (16-byte groups of two doubles; the FP64 headline's P = 18
+// then sums 18 terms per row instead of 20).
+template <typename T> __host__ __device__ constexpr int col_p4(int P) {
+    return (sizeof(T) == 8 && (P == 17 || P == 18)) ? 18 : (P + 3) & ~3;
+}
 
 template <typename T, int MODE, int NCS, int GP, int PT, int NW = CW>
 __global__ __launch_bounds__(64 * NW) void k_gather_col(GridGeo g, int KX, int segb, int ES, int PS,
@@ -630,7 +637,7 @@ __global__ __launch_bounds__(64 * NW) void k_gather_col(GridGeo g, int KX, int s
     const int X = KX * TB, E = X + P - 1, E2 = E * E, EZ = TB + P - 1;
     // PT > 0: the padded window width P4 as a compile-time constant (the x sums
     // unrolled with immediate LDS offsets); PT = 0: any P
-    const int P4 = PT > 0 ? PT : (P + 3) & ~3;
+    const int P4 = PT > 0 ? PT : col_p4<T>(P);
     // after the ring: per wave and point, the 1-D factors wx, wy, wz, dwx, dwy, dwz
     // (P4 each, zero beyond P)
     // LDS layout: row stride ES >= E and plane stride PS >= E ES, padded so the
@@ -1121,7 +1128,7 @@ template <typename T> constexpr int col_gp() { return sizeof(T) == 4 ? 4 : 1; }
 
 template <typename T> ColCfg col_config(const GridGeo& g, int waves = CW) {
     ColCfg best{0, 0, 0, 0, 0, 0, 0, 0};
-    const size_t wbytes = (size_t)waves * col_gp<T>() * 6 * ((g.P + 3) & ~3) * sizeof(T);
+    const size_t wbytes = (size_t)waves * col_gp<T>() * 6 * col_p4<T>(g.P) * sizeof(T);
     const size_t limit = 160 * 1024 - wbytes;
     // all components per pass when they fit; one-bin tiles measured as fast as
     // two-bin ones (less LDS, two workgroups per CU)
@@ -1176,9 +1183,10 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
                        cc.kx, cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field,       \
                        (const T*)nullptr, p.n, batch, u, (T*)nullptr)
 #define GCOLP(NC, NWV)                                                                                         \
-    switch ((g.P + 3) & ~3) {                                                                                  \
+    switch (col_p4<T>(g.P)) {                                                                                  \
         case 12: GCOL(NC, 12, NWV); break;                                                                     \
         case 16: GCOL(NC, 16, NWV); break;                                                                     \
+        case 18: if constexpr (sizeof(T) == 8) { GCOL(NC, 18, NWV); } break;                                   \
         case 20: GCOL(NC, 20, NWV); break;                                                                     \
         default: GCOL(NC, 0, NWV); break;                                                                      \
     }
@@ -1238,9 +1246,10 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
                        cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n,    \
                        batch, dsrc, dx)
 #define GCOLGP(NC)                                                                                             \
-    switch ((g.P + 3) & ~3) {                                                                                  \
+    switch (col_p4<T>(g.P)) {                                                                                  \
         case 12: GCOLG(NC, 12); break;                                                                         \
         case 16: GCOLG(NC, 16); break;                                                                         \
+        case 18: if constexpr (sizeof(T) == 8) { GCOLG(NC, 18); } break;                                       \
         case 20: GCOLG(NC, 20); break;                                                                         \
         default: GCOLG(NC, 0); break;                                                                          \
     }
@@ -1296,9 +1305,10 @@ void launch_gather_fused(const GridGeo& g, const PointsDev<T>& p, const T* phi_f
     GFK(3, NC, PT, phi_f, w_s, u);                                                                             \
     GFK(2, NC, PT, phi_w, f_s, dsrc)
 #define GFP(NC)                                                                                                \
-    switch ((g.P + 3) & ~3) {                                                                                  \
+    switch (col_p4<T>(g.P)) {                                                                                  \
         case 12: GF(NC, 12); break;                                                                            \
         case 16: GF(NC, 16); break;                                                                            \
+        case 18: if constexpr (sizeof(T) == 8) { GF(NC, 18); } break;                                          \
         case 20: GF(NC, 20); break;                                                                            \
         default: GF(NC, 0); break;                                                                             \
     }
