@@ -620,6 +620,11 @@ constexpr int CW64V = FSE_CW64V;
 template <typename T> __host__ __device__ constexpr int col_p4(int P) {
     return (sizeof(T) == 8 && (P == 17 || P == 18)) ? 18 : (P + 3) & ~3;
 }
+// Terms of the unrolled x sums: col_p4, except FP32 P = 11 (the FP32 headline's),
+// which sums its 11 terms from rows of 12 factors.
+template <typename T> __host__ __device__ constexpr int col_pt(int P) {
+    return (sizeof(T) == 4 && P == 11) ? 11 : col_p4<T>(P);
+}
 
 template <typename T, int MODE, int NCS, int GP, int PT, int NW = CW>
 __global__ __launch_bounds__(64 * NW) void k_gather_col(GridGeo g, int KX, int segb, int ES, int PS,
@@ -635,9 +640,10 @@ __global__ __launch_bounds__(64 * NW) void k_gather_col(GridGeo g, int KX, int s
     T* sm = (T*)smem_raw;
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
     const int X = KX * TB, E = X + P - 1, E2 = E * E, EZ = TB + P - 1;
-    // PT > 0: the padded window width P4 as a compile-time constant (the x sums
-    // unrolled with immediate LDS offsets); PT = 0: any P
-    const int P4 = PT > 0 ? PT : col_p4<T>(P);
+    // PT > 0: the x sums run over PT terms, unrolled with immediate LDS offsets
+    // (P <= PT; the factors beyond P are zero); PT = 0: any P.  The factor rows are
+    // P4 long either way.
+    const int P4 = PT > 0 ? (sizeof(T) == 8 ? (PT + 1) & ~1 : (PT + 3) & ~3) : col_p4<T>(P);
     // after the ring: per wave and point, the 1-D factors wx, wy, wz, dwx, dwy, dwz
     // (P4 each, zero beyond P)
     // LDS layout: row stride ES >= E and plane stride PS >= E ES, padded so the
@@ -1183,7 +1189,8 @@ void launch_gather(const GridGeo& g, const PointsDev<T>& p, const T* field, int 
                        cc.kx, cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, field,       \
                        (const T*)nullptr, p.n, batch, u, (T*)nullptr)
 #define GCOLP(NC, NWV)                                                                                         \
-    switch (col_p4<T>(g.P)) {                                                                                  \
+    switch (col_pt<T>(g.P)) {                                                                                  \
+        case 11: if constexpr (sizeof(T) == 4) { GCOL(NC, 11, NWV); } break;                                   \
         case 12: GCOL(NC, 12, NWV); break;                                                                     \
         case 16: GCOL(NC, 16, NWV); break;                                                                     \
         case 18: if constexpr (sizeof(T) == 8) { GCOL(NC, 18, NWV); } break;                                   \
@@ -1246,7 +1253,8 @@ void launch_gather_grad(const GridGeo& g, const PointsDev<T>& p, const T* phi_f,
                        cc.segb, cc.es, cc.ps, p.tile_start, p.perm_s, p.bpack_s, p.coff_s, phi_w, f_s, p.n,    \
                        batch, dsrc, dx)
 #define GCOLGP(NC)                                                                                             \
-    switch (col_p4<T>(g.P)) {                                                                                  \
+    switch (col_pt<T>(g.P)) {                                                                                  \
+        case 11: if constexpr (sizeof(T) == 4) { GCOLG(NC, 11); } break;                                       \
         case 12: GCOLG(NC, 12); break;                                                                         \
         case 16: GCOLG(NC, 16); break;                                                                         \
         case 18: if constexpr (sizeof(T) == 8) { GCOLG(NC, 18); } break;                                       \
@@ -1305,7 +1313,8 @@ void launch_gather_fused(const GridGeo& g, const PointsDev<T>& p, const T* phi_f
     GFK(3, NC, PT, phi_f, w_s, u);                                                                             \
     GFK(2, NC, PT, phi_w, f_s, dsrc)
 #define GFP(NC)                                                                                                \
-    switch (col_p4<T>(g.P)) {                                                                                  \
+    switch (col_pt<T>(g.P)) {                                                                                  \
+        case 11: if constexpr (sizeof(T) == 4) { GF(NC, 11); } break;                                          \
         case 12: GF(NC, 12); break;                                                                            \
         case 16: GF(NC, 16); break;                                                                            \
         case 18: if constexpr (sizeof(T) == 8) { GF(NC, 18); } break;                                          \
