@@ -321,6 +321,11 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
         }
         T g0 = 0, g1 = 0, g2 = 0;
         double gs0 = 0, gs1 = 0, gs2 = 0;
+        // stokeslet gradient, one batch member: the terms w_t (B f_s.r) and f_t (B w_s.r)
+        // of every pair share the target's w_t and f_t, so their scalar factors add up
+        // here (h1, h2, flush totals hs1, hs2) and meet w_t, f_t once at the end
+        T h1 = 0, h2 = 0;
+        double hs1 = 0, hs2 = 0;
         // this thread's hit queue: column tid of qd, QROW entries per row
         const int QROW = queue_row(nthr);
         const int qlog = QROW == 64 ? 6 : QROW == 128 ? 7 : 8;  // log2 of a row in entries
@@ -480,9 +485,18 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                             acc[b][4] += a_ * fn[1] + bf * rv[1];
                             acc[b][5] += a_ * fn[2] + bf * rv[2];
                         }
-                        g0 += rad * rv[0] + Bc * (wp[0] * fr1 + fn[0] * wr1 + sgn * (wn[0] * fr2 + fp[0] * wr2));
-                        g1 += rad * rv[1] + Bc * (wp[1] * fr1 + fn[1] * wr1 + sgn * (wn[1] * fr2 + fp[1] * wr2));
-                        g2 += rad * rv[2] + Bc * (wp[2] * fr1 + fn[2] * wr1 + sgn * (wn[2] * fr2 + fp[2] * wr2));
+                        if constexpr (NB == 1) {
+                            const T al = Bc * wr1, be = Bc * fr2;  // sgn = 1 for the stokeslet
+                            g0 += rad * rv[0] + al * fn[0] + be * wn[0];
+                            g1 += rad * rv[1] + al * fn[1] + be * wn[1];
+                            g2 += rad * rv[2] + al * fn[2] + be * wn[2];
+                            h1 += Bc * fr1;
+                            h2 += Bc * wr2;
+                        } else {
+                            g0 += rad * rv[0] + Bc * (wp[0] * fr1 + fn[0] * wr1 + sgn * (wn[0] * fr2 + fp[0] * wr2));
+                            g1 += rad * rv[1] + Bc * (wp[1] * fr1 + fn[1] * wr1 + sgn * (wn[1] * fr2 + fp[1] * wr2));
+                            g2 += rad * rv[2] + Bc * (wp[2] * fr1 + fn[2] * wr1 + sgn * (wn[2] * fr2 + fp[2] * wr2));
+                        }
                     }
                 } else {
                     // w.Omega^R f = psi(r) r.(w x f), psi = rho/r
@@ -570,6 +584,9 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                 }
             if constexpr (GRAD) {
                 gs0 += g0;
+                hs1 += h1;
+                hs2 += h2;
+                h1 = h2 = (T)0;
                 gs1 += g1;
                 gs2 += g2;
                 g0 = g1 = g2 = (T)0;
@@ -742,6 +759,11 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                     }
                 }
             } else {
+                if constexpr (KERNEL == FSE_STOKESLET && NB == 1) {
+                    gs0 += (double)wt[0][0] * hs1 + (double)ft[0][0] * hs2;
+                    gs1 += (double)wt[0][1] * hs1 + (double)ft[0][1] * hs2;
+                    gs2 += (double)wt[0][2] * hs1 + (double)ft[0][2] * hs2;
+                }
                 out[3 * i] = (T)((double)out[3 * i] + gs0);
                 out[3 * i + 1] = (T)((double)out[3 * i + 1] + gs1);
                 out[3 * i + 2] = (T)((double)out[3 * i + 2] + gs2);
