@@ -453,12 +453,15 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
             } else {
                 const T rv[3] = {r0, r1, r2v};
                 if constexpr (KERNEL == FSE_STOKESLET) {
-                    // w.S^R f = a(r) (w.f) + (b(r)/r^2) (w.r)(f.r)
-                    const T b_ = ec * ir + c2x * e;
-                    const T da = -ec * ir * ir - c2x * e * ir + c4x3 * r * e;
-                    const T db = -ec * ir * ir - c2x * e * ir - c4x3 * r * e;
-                    const T Bc = b_ * ir * ir;
-                    const T dB = db * ir * ir - (T)2 * b_ * ir * ir * ir;
+                    // w.S^R f = a(r) (w.f) + (b(r)/r^2) (w.r)(f.r), a = t1 - t2, b = t1 + t2 with
+                    // t1 = erfc/r, t2 = 2 xi e/sqrt(pi): a' = -b/r + t3, b' = -b/r - t3,
+                    // t3 = 4 xi^3 r e/sqrt(pi), and (b/r^2)' = (b' - 2 b/r)/r^2
+                    const T t1 = ec * ir, t2 = c2x * e, t3 = c4x3 * r * e;
+                    const T b_ = t1 + t2, bir = b_ * ir, ir2 = ir * ir;
+                    const T da = t3 - bir;
+                    const T db = -bir - t3;
+                    const T Bc = b_ * ir2;
+                    const T dB = (db - (T)2 * bir) * ir2;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const T fn[3] = {ss[b][0][kk], ss[b][1][kk], ss[b][2][kk]};
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(256) void k_real(CellGeo cg, PointsDev<T> pd, const
                         const T wr2 = wn[0] * rv[0] + wn[1] * rv[1] + wn[2] * rv[2];
                         const T fr2 = fp[0] * rv[0] + fp[1] * rv[1] + fp[2] * rv[2];
                         const T rad = (da * (wf1 + sgn * wf2) + dB * (wr1 * fr1 + sgn * wr2 * fr2)) * ir;
-                        const T a_ = ec * ir - c2x * e;
+                        const T a_ = t1 - t2;
                         if constexpr (WVAL) {
                             const T bw = Bc * wr2;
                             acc[b][0] += a_ * wn[0] + bw * rv[0];
