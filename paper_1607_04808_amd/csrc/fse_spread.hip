@@ -307,16 +307,20 @@ __global__ __launch_bounds__(256) void k_spread(GridGeo g, const int* __restrict
     }
 }
 
-// FP32 spreading on the matrix cores.  Same cores, chunks and per-wave point
-// lists as k_spread (TZ = 16), but a wave's contribution from four listed points
-// k is one product per component c and 16-node xy block:
+// FP32 spreading on the matrix cores.  Same cores and chunks as k_spread
+// (TZ = 16), but a wave's contribution from four listed points k is one product
+// per component c and 16-node xy block:
 //   acc_c[z][xy] += sum_k (wz_k(z) v_k[c]) (wx_k(x) wy_k(y)),
 // a 16 x 4 by 4 x 16 matrix product (v_mfma_f32_16x16x4f32; z rows, points
 // along k, xy nodes as columns).  Lane l supplies A[z = l mod 16][k = l / 16]
 // and B[k = l / 16][xy = l mod 16] and holds D[z = 4 (l / 16) + j][xy = l mod 16],
-// j = 0..3; the four xy blocks of the wave's 8 x 8 tile are its row pairs.
-// Every listed point costs the full 16 z-rows (no z-group skipping) at twice
-// the non-packed FP32 FMA rate of the vector units.
+// j = 0..3.  The wave's 8 x 8 tile is four 4 x 4 blocks (xy = 4 y' + x' within
+// a block), and each block keeps its own list of the staged points whose window
+// meets it, so a point costs products only on the blocks it reaches (2.4 of 4
+// on average at P = 11).  The four lists are walked together, one group of four
+// points from each per step, so every step still issues up to 4 c independent
+// products.  Every listed point costs the full 16 z-rows (no z-group skipping)
+// at twice the non-packed FP32 FMA rate of the vector units.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <int NC, int CH>
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ float s_v[CH][NC];
     __shared__ int s_bp[CH];
     __shared__ int s_wc[4];
-    __shared__ unsigned char s_list[4][CH];  // per wave: the staged points that meet its tile
+    __shared__ unsigned char s_list[4][4][CH];  // per wave and 4 x 4 block: the staged points that meet it
     static_assert(CH <= 256, "list entries are point index bytes");
     const int Mt = g.Mt, P = g.P, TB = g.TS, nb = g.nt;
     const int ncxy = (Mt + 15) / 16;
@@ -343,7 +347,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wx0 = (wid & 1) * 8, wy0 = (wid >> 1) * 8;  // the wave's 8 x 8 tile in the core
     const int kl = lane >> 4, cl = lane & 15;              // operand slot: point kl, row / column cl
-    const int xo = wx0 + (cl & 7), yo = wy0 + (cl >> 3);   // xy node of column cl in block 0
+    const int xo = wx0 + (cl & 3), yo = wy0 + (cl >> 2);   // xy node of column cl in block 0
+    // block b covers x in xo + 4 (b & 1), y in yo + 4 (b >> 1)
 
     f32x4 acc[NC][4];
 #pragma unroll
@@ -381,37 +386,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (nbase >= end) nr = find_row(r + 1, nbase, nend);
         if (nr < nrows) load_point<float, NC, CH>(pt, nbase, nend, bm, n, bpack_s, coff_s, src_s, src2);
         chunk_factors<float, TZ>(g, cnt, lox, loy, loz, s_w, s_c, s_bp);
-        int nl = 0;
+        int nl[4] = {0, 0, 0, 0};
         for (int k0 = 0; k0 < cnt; k0 += 64) {
             const int k = k0 + lane;
-            bool hit = false;
+            bool hx[2] = {false, false}, hy[2] = {false, false};
             if (k < cnt) {
                 const int bp = s_bp[k];
                 const int bx = bp & 1023, by = (bp >> 10) & 1023;
-                hit = !(bx > lox + wx0 + 7 || bx + P <= lox + wx0 || by > loy + wy0 + 7 ||
-                        by + P <= loy + wy0);
-            }
-            const unsigned long long m = __ballot(hit);
-            if (hit) s_list[wid][nl + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)k;
-            nl += __popcll(m);
-        }
-        __syncthreads();
-        // four listed points per step; slots past the list get zero A operands
-        // (their B operands read point 0's factors, which are finite)
-        for (int l0 = 0; l0 < nl; l0 += 4) {
-            const bool ok = l0 + kl < nl;
-            const int k = ok ? (int)s_list[wid][l0 + kl] : 0;
-            const float wz = ok ? s_w[k][32 + cl] : 0.f;
-            const float wx = s_w[k][xo];
-            float a[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a[c] = wz * s_v[k][c];
+                for (int h = 0; h < 2; ++h) {
+                    const int x0 = lox + wx0 + 4 * h, y0 = loy + wy0 + 4 * h;
+                    hx[h] = !(bx > x0 + 3 || bx + P <= x0);
+                    hy[h] = !(by > y0 + 3 || by + P <= y0);
+                }
+            }
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const float bb = wx * s_w[k][16 + yo + 2 * b];
+                const bool hit = hx[b & 1] && hy[b >> 1];
+                const unsigned long long m = __ballot(hit);
+                if (hit) s_list[wid][b][nl[b] + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned char)k;
+                nl[b] += __popcll(m);
+            }
+        }
+        __syncthreads();
+        // step g takes listed points 4 g .. 4 g + 3 of every block whose list
+        // reaches that far; slots past a list get zero A operands (their B
+        // operands read point 0's factors, which are finite)
+        const int ng = (max(max(nl[0], nl[1]), max(nl[2], nl[3])) + 3) >> 2;
+        for (int l0 = 0; l0 < 4 * ng; l0 += 4) {
+            // the four blocks' entries in one LDS round trip (the slot index is
+            // clamped into the list row; entries past a list are not used)
+            int kk[4];
 #pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], bb, acc[c][b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b) kk[b] = s_list[wid][b][min(l0 + kl, CH - 1)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if (l0 < nl[b]) {
+                    const bool ok = l0 + kl < nl[b];
+                    const int k = ok ? kk[b] : 0;
+                    const float wzk = s_w[k][32 + cl];
+                    const float wz = ok ? wzk : 0.f;
+                    const float bb = s_w[k][xo + 4 * (b & 1)] * s_w[k][16 + yo + 4 * (b >> 1)];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        acc[c][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(wz * s_v[k][c], bb, acc[c][b], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
@@ -420,10 +439,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         end = nend;
     }
     const int64_t M3 = (int64_t)Mt * Mt * Mt;
-    const int gx = lox + xo;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int gy = loy + yo + 2 * b;
+        const int gx = lox + xo + 4 * (b & 1), gy = loy + yo + 4 * (b >> 1);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int gz = loz + 4 * kl + j;
