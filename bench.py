@@ -212,7 +212,7 @@ def main():
         FORMS[form][name] = type(FORMS[form][name])(float(val))
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus %d is not supported "
-              "(the multi-GPU decomposition is a design note in DESIGN.md)" % args.gpus, file=sys.stderr)
+              "(sharding over several GPUs is described, not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -386,7 +386,8 @@ fse_status_t fse_plan_set_tuning(fse_plan_t *plan, const fse_tuning_t *tuning);
  * weights, time `repeats` runs of fse_set_points + fse_eval (with w:
  * fse_eval_with_adjoint; periodic plans fse_eval + fse_eval_adjoint) with HIP
  * events for each candidate of each knob in turn (bin side, real-space waves,
- * the two queue depths, the FFT line cap), keep the fastest, and leave the plan
+ * the two queue depths, the FFT line cap; a queue depth whose pass the timed
+ * calls never run keeps its value), keep the fastest, and leave the plan
  * with it and the points set.  *best (may be NULL) receives the tuning.  Allocates
  * temporary outputs and synchronises the stream.
  */

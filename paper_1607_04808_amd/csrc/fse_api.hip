@@ -1285,8 +1285,13 @@ fse_status_t autotune_t(fse_plan* p, int64_t n, const T* x, const T* a, const T*
     fse_status_t rc = apply_tuning(p, best);
     if (rc == FSE_OK) rc = time_workload<T>(p, n, x, a, b, w, u, ds, dx, repeats, &best_ms);
     const bool f32 = sizeof(T) == 4;
+    // a queue depth whose pass the timed workload never runs keeps its value (the
+    // fused call for one source set runs only the gradient pass; without w only
+    // value passes run)
+    const bool grad_only = w && !p->periodic && p->kernel != FSE_STRESSLET && p->batch == 1;
     // each knob in turn, the others held at the best so far
     for (int knob = 0; knob < 5 && rc == FSE_OK; ++knob) {
+        if ((knob == 2 && grad_only) || (knob == 3 && !w)) continue;
         std::vector<int> cand;
         if (knob == 0) cand = {5, 6, 7, 8};
         else if (knob == 1) cand = {1, 2, 3, 4};
