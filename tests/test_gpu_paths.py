@@ -1,9 +1,9 @@
 """Parity on every code path the ABI admits, element by element against the oracle:
 
 * Gaussian supports that select each quadrature kernel: P = 8 (the generic
-  row walk), P = 11 and 18 (the headline forms' widths, padded to 12 and 20),
-  P = 24 and 28 in FP64 (the column kernel's widest ring, then the block and
-  global-memory kernels), P = 32 in both precisions;
+  row walk), P = 11 and 18 (the headline forms' widths, whose x-sums run 11
+  and 18 terms), P = 24 and 28 in FP64 (the column kernel's widest ring, then
+  the block and global-memory kernels), P = 32 in both precisions;
 * FFT sizes whose stages run fused in FP32: n = 50 (5 5 | 2) and n = 60 (5 4 | 3);
 * the batched adjoint against single adjoints;
 * the FP32 adjoints (stokeslet and rotlet) against the oracle's discrete gradient.
@@ -48,8 +48,8 @@ def _geo(plan, p):
 # (P, xi, M, Mt, dtypes): eta < 0.7 in every case
 PCASES = [
     (8, 10.0, 20, 0, ("f64", "f32")),
-    (11, 8.5, 20, 0, ("f64", "f32")),   # odd P, the FP32 headline's (x-sums padded to 12)
-    (18, 6.5, 20, 0, ("f64",)),         # the FP64 headline's P (x-sums padded to 20)
+    (11, 8.5, 20, 0, ("f64", "f32")),   # odd P, the FP32 headline's (FP32: 11-term x-sums)
+    (18, 6.5, 20, 0, ("f64",)),         # the FP64 headline's P (18-term x-sums)
     (24, 5.5, 20, 0, ("f64", "f32")),
     (28, 5.0, 20, 0, ("f64",)),
     (32, 4.0, 20, 54, ("f64", "f32")),
@@ -183,7 +183,8 @@ def test_fp32_adjoint_matches_oracle(kernel):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_tuning_changes_shapes_not_results(dtype):
     """Every bin side, queue depth and wave count gives the same sums (FP64 to
-    rounding; FP32 within its rounding), and autotune leaves a working plan."""
+    rounding; FP32 within its rounding), and autotune leaves a working plan and
+    changes no queue depth whose pass the timed calls do not run."""
     n = 4000
     prm = F.make_params(9.0, 0.35, 22, 12, L=1.0)
     x, f, w = W.uniform_cube(n, 390), W.normal_strengths(n, 391), W.normal_strengths(n, 392)
@@ -204,8 +205,17 @@ def test_tuning_changes_shapes_not_results(dtype):
             assert plan.tuning() == t
             assert relmax(plan.eval(ft).double().cpu().numpy(), u0) < tol
             assert relmax(plan.adjoint(ft, wt)[1].double().cpu().numpy(), d0) < tol
+        # queue depths outside the candidate sets: a knob the timed calls never
+        # exercise must keep its value (the fused call runs no value-only pass,
+        # and without w no gradient pass runs)
+        plan.set_tuning(dict(plan.tuning(), real_queue=40, real_queue_grad=40))
         best = plan.autotune(xt, ft, None, wt, repeats=1)
         assert plan.tuning() == best
+        assert best["real_queue"] == 40
+        assert relmax(plan.eval(ft).double().cpu().numpy(), u0) < tol
+        plan.set_tuning(dict(best, real_queue_grad=40))
+        best = plan.autotune(xt, ft, repeats=1)
+        assert best["real_queue_grad"] == 40
         assert relmax(plan.eval(ft).double().cpu().numpy(), u0) < tol
         with pytest.raises(F.FseError):
             plan.set_tuning(dict(best, bin_side=3))
