@@ -61,6 +61,37 @@ def test_fused_matches_separate_calls(kernel, dtype, batch, P):
     assert relmax(df2, df0) < TOL[dtype] and relmax(dx2, dx0) < TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("P,xi,Mt", [(24, 5.5, 0), (32, 4.0, 54)])
+def test_fused_wide_windows(dtype, P, xi, Mt):
+    """Wide windows: every point's window meets all four 4 x 4 blocks of a spreading
+    wave's tile and spans several bins; the fused call's six-component spreading
+    and shared sweeps still agree with the separate calls and with the oracle's
+    discrete adjoint."""
+    from oracle import se
+    n = 900
+    prm = F.make_params(xi, 3.5 / xi, 20, P, L=1.0, Mt=Mt)
+    x, f, w = W.uniform_cube(n, 445), W.normal_strengths(n, 446), W.normal_strengths(n, 447)
+    plan = F.Plan("stokeslet", dtype, prm, nmax=n, tuned=False)
+    try:
+        xt, ft, wt = _t(x, dtype), _t(f, dtype), _t(w, dtype)
+        plan.set_points(xt)
+        u0 = plan.eval(ft).double().cpu().numpy()
+        df0, dx0 = (a.double().cpu().numpy() for a in plan.adjoint(ft, wt, recompute=False))
+        u1, df1, dx1 = (a.double().cpu().numpy() for a in plan.eval_with_adjoint(ft, wt))
+        g = se.geometry(prm.xi, prm.rc, prm.M, prm.P, tuple(prm.box_lo), prm.L, Mt=plan.geometry.Mt,
+                        deltaL_rule=prm.deltaL_rule)
+    finally:
+        plan.close()
+    e = (relmax(u1, u0), relmax(df1, df0), relmax(dx1, dx0))
+    print(dtype, "P", P, "fused vs separate: u %.1e  dL/df %.1e  dL/dx %.1e" % e)
+    assert max(e) < TOL[dtype]
+    as64 = (lambda a: np.asarray(a, np.float32).astype(np.float64)) if dtype == "f32" else np.asarray
+    ex = relmax(dx1.reshape(n, 3), se.grad_x("stokeslet", as64(x), as64(f), as64(w), g))
+    print(dtype, "P", P, "dL/dx vs oracle %.1e" % ex)
+    assert ex < (1e-10 if dtype == "f64" else 2e-6)
+
+
 def test_fused_against_direct_sums():
     n = 3000
     prm = F.make_params(10.0, 0.5, 40, 20, L=1.0)  # xi r_c = 5, M / xi L = 4: about 1e-10
